@@ -1,0 +1,261 @@
+/*
+ * hpop: heterogeneous POP efficiency metrics on an AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the engine that reduces timestamped traces of host states and
+ * device activity to the two metric trees of Rahimi et al., "Hardware-
+ * Agnostic and Insightful Efficiency Metrics for Accelerated Systems"
+ * (arXiv 2603.26576):
+ *
+ *   host tree (Section 4.1, eqs. 6-8)
+ *     Parallel Efficiency            = sum_i U_i / (n E)                 (eq. 6)
+ *     +- MPI Parallel Efficiency     = sum_i (U_i + W_i) / (n E)         (eq. 7)
+ *     |  +- Communication Efficiency = max_i (U_i + W_i) / E             (eq. 5, U+W useful)
+ *     |  +- Load Balance             = sum_i (U_i + W_i) / (n max(U+W))  (eq. 4, U+W useful)
+ *     +- Device Offload Efficiency   = sum_i U_i / sum_i (U_i + W_i)     (eq. 8)
+ *   device tree (Section 4.1, eqs. 9-12)
+ *     Parallel Efficiency            = sum_g K_g / (m E)                 (eq. 9)
+ *     +- Load Balance                = sum_g K_g / (m max K)             (eq. 10)
+ *     +- Communication Efficiency    = max K / max (K + M)               (eq. 11)
+ *     +- Orchestration Efficiency    = max (K + M) / E                   (eq. 12)
+ *
+ * U, W and MPI are the host states Useful, Device Offloading and MPI; K and M
+ * are device Kernel and Memory-operation time. Device records are flattened
+ * as in Section 4.2: overlapping kernels of any streams count once, memory
+ * operations under kernels are removed, uncovered time is idle. Host records
+ * overlap with the priority Useful > Offloading > MPI; host time covered by
+ * no record is "Other". E is the region length t1 - t0.
+ *
+ * Every interval is half-open [start, end) in int64 nanoseconds, with
+ * 0 <= start <= end < 2^62. A ratio whose denominator is 0 is defined as 1.0
+ * and its bit is set in hpop_metric_tree.undefined_mask (bit j = j-th ratio
+ * in the order of the struct fields).
+ *
+ * Errors: every call returns an hpop_status (0 = OK, negative = error); no
+ * exception crosses the ABI; a failed call leaves the session unchanged
+ * except where a function says otherwise. hpop_last_error() gives a message.
+ * Sessions are not thread-safe (one thread at a time per session); the
+ * server is thread-safe.
+ */
+#ifndef HPOP_H
+#define HPOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hpop_status;
+#define HPOP_OK 0
+#define HPOP_E_ARG (-1)          /* null pointer, negative count, bad flag */
+#define HPOP_E_KIND (-2)         /* unknown kind, or host kind on a device resource and vice versa */
+#define HPOP_E_RESOURCE (-3)     /* resource id outside 0 .. n_hosts+n_devices-1 */
+#define HPOP_E_BAD_INTERVAL (-4) /* start > end, start < 0 or end >= 2^62 */
+#define HPOP_E_REGION (-5)       /* t0 >= t1, or an unknown region id */
+#define HPOP_E_OVERFLOW (-6)     /* (t1 - t0) * max(n, m) >= 2^53: ratios would not be exact */
+#define HPOP_E_OOM (-7)          /* device or host allocation failed */
+#define HPOP_E_BUSY (-8)         /* server queue full (back-pressure); retry later */
+#define HPOP_E_HIP (-9)          /* a HIP runtime call failed; the message names it */
+#define HPOP_E_TIMEOUT (-10)     /* hpop_server_wait timed out; the ticket stays valid */
+#define HPOP_E_STATE (-11)       /* call not valid in the current state */
+
+/* record kinds (Section 4.1 host states and device states) */
+#define HPOP_HOST_USEFUL 0   /* host computing */
+#define HPOP_HOST_OFFLOAD 1  /* host blocked in a device runtime call: launch, copy, synchronisation */
+#define HPOP_HOST_MPI 2      /* host inside MPI */
+#define HPOP_DEV_KERNEL 3    /* device executing a kernel (any stream) */
+#define HPOP_DEV_MEMOP 4     /* device memory operation: memcpy H2D/D2H/D2D, memset */
+
+/* where the caller's arrays live */
+#define HPOP_MEM_HOST 0
+#define HPOP_MEM_DEVICE 1
+
+/* flags of hpop_metrics_compute_all and hpop_batch_compute */
+#define HPOP_FORCE_REBUILD 1u /* rebuild the merged interval lists even if no record was added */
+
+typedef struct hpop_session hpop_session;
+typedef struct hpop_server hpop_server;
+
+/* Optional device allocator. `stream` is the hipStream_t the memory is used on. */
+typedef void* (*hpop_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*hpop_free_fn)(void* ctx, void* ptr, void* stream);
+
+typedef struct {
+    int32_t n_hosts;       /* n: host processes, resource ids 0 .. n-1 */
+    int32_t n_devices;     /* m: devices, resource ids n .. n+m-1 */
+    void* stream;          /* hipStream_t for all work; NULL: the session creates one */
+    hpop_alloc_fn alloc;   /* NULL: hipMallocAsync on the session stream */
+    hpop_free_fn free;
+    void* alloc_ctx;
+} hpop_session_config;
+
+/* One region's metric trees with the exact integer aggregates they come from. */
+typedef struct {
+    int64_t E;                    /* region length t1 - t0 */
+    int32_t n, m;                 /* host processes and devices counted */
+    int64_t sumU, sumW, sumMPI, sumOther;
+    int64_t sumUW, maxUW;         /* sum and max over hosts of U + W */
+    int64_t sumK, sumM, maxK, maxKM;
+    double host_pe, host_mpi_pe, host_mpi_lb, host_mpi_ce, host_oe;  /* bits 0-4 */
+    double dev_pe, dev_lb, dev_ce, dev_oe;                            /* bits 5-8 */
+    uint32_t undefined_mask;
+    uint32_t reserved;
+} hpop_metric_tree;
+
+/* Tuning of the reduction kernels (see hpop_autotune). Zero fields keep defaults. */
+typedef struct {
+    int32_t bucket_target;  /* mean records per time bucket of a resource (64 .. 4096) */
+    int32_t bucket_cap;     /* records a bucket may hold for the on-chip sort: 2048 or 4096 */
+    int32_t tile_elems;     /* records per workgroup in the streaming passes (1024 .. 16384) */
+    int32_t reserved;
+} hpop_tuning;
+
+/* Counters of one session (sizes of the last build). */
+typedef struct {
+    int64_t n_events;       /* records added */
+    int64_t n_chunks;       /* add_events calls kept */
+    int64_t n_buckets;      /* time buckets of the last build */
+    int64_t n_oversized;    /* buckets of the last build too large for the on-chip sort */
+    int32_t n_regions;
+    int32_t graph_replays;  /* builds served by replaying a captured HIP graph */
+} hpop_session_info;
+
+/* One batch of records of one kind on one resource (hpop_add_events_multi,
+ * hpop_server_submit). */
+typedef struct {
+    int32_t resource;
+    int32_t kind;
+    const int64_t* start;
+    const int64_t* end;
+    int64_t count;
+} hpop_event_chunk;
+
+/* Status text; never NULL. */
+const char* hpop_status_string(hpop_status status);
+/* Last error message of a session (owned by the session, valid until its next call);
+ * with s == NULL the calling thread's last error of a session-less call. */
+const char* hpop_last_error(const hpop_session* s);
+
+/* Create a session for n hosts and m devices (both fixed; resources without
+ * records still count in n and m). The HIP device current on the calling
+ * thread is used. */
+hpop_status hpop_session_create(const hpop_session_config* cfg, hpop_session** out);
+hpop_status hpop_session_destroy(hpop_session* s);
+
+/* Append `count` records of one kind on one resource (Section 4.2: records
+ * arrive in batches, in any order). start/end are HPOP_MEM_HOST or
+ * HPOP_MEM_DEVICE pointers to int64 arrays; they are copied before the call
+ * returns (host) or in stream order on the session stream (device: the
+ * caller must not overwrite them until that stream passes this call).
+ * Host input is validated here (HPOP_E_BAD_INTERVAL names the index);
+ * device input is validated by the next build, which then fails with
+ * HPOP_E_BAD_INTERVAL naming the call and index, and drops that call's records. */
+hpop_status hpop_add_events(hpop_session* s, int32_t resource, int32_t kind,
+                            const int64_t* start, const int64_t* end, int64_t count,
+                            int32_t mem_space);
+/* Several hpop_add_events calls at once (one staging copy for host input).
+ * Either every chunk is added or, on error, none is. */
+hpop_status hpop_add_events_multi(hpop_session* s, const hpop_event_chunk* chunks, int32_t n_chunks,
+                                  int32_t mem_space);
+/* Wait until the session stream has passed every call made so far (after
+ * which device arrays given to hpop_add_events may be reused). */
+hpop_status hpop_session_synchronize(hpop_session* s);
+/* Drop every record (regions are kept). */
+hpop_status hpop_clear_events(hpop_session* s);
+
+/* A user region [t0, t1) (Section 3.2: regions of interest annotated by the
+ * user). Returns its id (0, 1, ...). */
+hpop_status hpop_region_define(hpop_session* s, int64_t t0, int64_t t1, int32_t* out_region);
+hpop_status hpop_num_regions(const hpop_session* s, int32_t* out);
+
+/* Metric trees of one region / of every region (out: hpop_num_regions entries).
+ * Builds the merged interval lists first if records were added since the
+ * last build (or with HPOP_FORCE_REBUILD), then clips every resource to the
+ * region(s) and reduces. Blocks until the trees are in host memory. */
+hpop_status hpop_metrics_compute(hpop_session* s, int32_t region, hpop_metric_tree* out);
+hpop_status hpop_metrics_compute_all(hpop_session* s, uint32_t flags, hpop_metric_tree* out);
+
+/* State times of one resource in one region after a compute:
+ * host -> {Useful, Offloading, MPI, Other}, device -> {Kernel, Memory, Idle, 0}. */
+hpop_status hpop_resource_times(hpop_session* s, int32_t region, int32_t resource, int64_t out[4]);
+
+/* Batched evaluation: the records and regions of k sessions reduced together
+ * in one launch sequence (captured once in a HIP graph and replayed while no
+ * session changes). out receives every region of every session, session by
+ * session, regions in id order. All sessions must use the same HIP device;
+ * the work runs on the first session's stream. */
+hpop_status hpop_batch_compute(hpop_session* const* sessions, int32_t k, uint32_t flags,
+                               hpop_metric_tree* out);
+
+hpop_status hpop_session_get_info(const hpop_session* s, hpop_session_info* out);
+hpop_status hpop_session_set_tuning(hpop_session* s, const hpop_tuning* t);
+hpop_status hpop_session_get_tuning(const hpop_session* s, hpop_tuning* out);
+
+/* Per-kernel device time of the last build and clip, measured with HIP
+ * events on the session stream when enabled (off by default).
+ * names/ms receive up to `cap` entries; *n_out the number written. */
+hpop_status hpop_session_enable_timing(hpop_session* s, int32_t on);
+hpop_status hpop_session_stage_times(const hpop_session* s, int32_t cap, const char** names,
+                                     float* ms, int32_t* n_out);
+
+/* Autotuner: times candidate tunings on the given sessions (batched when
+ * k > 1), keeps the fastest, applies it to every session and returns it.
+ * With cache_path != NULL the choice is read from / appended to that JSON
+ * file, keyed by the workload's size class, so later calls skip the search. */
+hpop_status hpop_autotune(hpop_session* const* sessions, int32_t k, const char* cache_path,
+                          hpop_tuning* out);
+
+/* ----------------------------------------------------------------------------
+ * Serving runtime (online analysis: Section 3.2 describes TALP's run-time
+ * queries; Section 4.2 its batched, asynchronously delivered device records).
+ *
+ * The server keeps each session's merged interval lists resident in device
+ * memory. A submitted query carries new records of one session and closes a
+ * region [t0, t1); the server merges the records into the session state
+ * incrementally and returns the metric trees of that region and of the
+ * session's whole span so far. Queries of different sessions are admitted
+ * while others run (continuous batching) and reduced together; queries of one
+ * session are applied in submission order. The result of a query depends only
+ * on the records submitted to its session up to and including it.
+ * -------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t max_sessions;       /* sessions the server may open */
+    int32_t max_inflight;       /* queries admitted per device step (1 .. 4096) */
+    int32_t queue_capacity;     /* queued queries before hpop_server_submit returns HPOP_E_BUSY */
+    int32_t reserved;
+    int64_t mem_budget_bytes;   /* device bytes for staged records of admitted queries */
+} hpop_server_config;
+
+typedef struct {
+    int64_t completed;          /* queries finished */
+    int64_t events;             /* records merged */
+    int64_t device_steps;       /* batched device steps run */
+    double mean_batch;          /* mean queries per device step */
+    double p50_us, p99_us, max_us;  /* submit -> result latency of finished queries */
+} hpop_server_stats;
+
+hpop_status hpop_server_create(const hpop_server_config* cfg, hpop_server** out);
+hpop_status hpop_server_destroy(hpop_server* srv);
+/* Open a session of n hosts and m devices; t_origin is the start of its
+ * global region. */
+hpop_status hpop_server_open_session(hpop_server* srv, int32_t n_hosts, int32_t n_devices,
+                                     int64_t t_origin, int32_t* out_sid);
+/* Non-blocking. Records in `chunks` are HPOP_MEM_HOST (copied before return)
+ * or HPOP_MEM_DEVICE (read by the server's stream; keep them unchanged until
+ * the ticket completes). Returns HPOP_E_BUSY when the queue is full. */
+hpop_status hpop_server_submit(hpop_server* srv, int32_t sid, const hpop_event_chunk* chunks,
+                               int32_t n_chunks, int32_t mem_space, int64_t t0, int64_t t1,
+                               uint64_t* out_ticket);
+/* Wait for a ticket (timeout_ns < 0: forever). Writes the trees of the
+ * query's region and of [t_origin, max end so far) of its session. */
+hpop_status hpop_server_wait(hpop_server* srv, uint64_t ticket, int64_t timeout_ns,
+                             hpop_metric_tree* out_region, hpop_metric_tree* out_global);
+hpop_status hpop_server_get_stats(hpop_server* srv, hpop_server_stats* out);
+const char* hpop_server_last_error(const hpop_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPOP_H */

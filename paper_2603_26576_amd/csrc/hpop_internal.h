@@ -1,0 +1,120 @@
+// Internal layout shared by the runtime and the kernels of the engine.
+//
+// The build turns the records of every resource (a "segment") into, per
+// nested state level, a list of disjoint merged intervals with prefix
+// measures, stored per time bucket:
+//
+//   level 0: device {Kernel}            host {Useful}
+//   level 1: device {Kernel, Memory}    host {Useful, Offloading}
+//   level 2: -                          host {Useful, Offloading, MPI}
+//
+// Kernel time of a device in a region is the measure of level 0 inside it,
+// memory time the measure of level 1 minus that, idle the rest; host states
+// follow the same nesting (Section 4.2 post-processing and the host-state
+// priority Useful > Offloading > MPI).
+//
+// Pipeline (one pass over the records per arrow):
+//   records --stats--> per-segment min start / max start / max end, validation
+//           --hist---> per-bucket record counts (bucket = start >> shift)
+//           --scan---> bucket offsets
+//           --scatter-> records regrouped by bucket (16 B each) + per-bucket max end
+//   carry  : per-bucket running max end of all earlier buckets (per level)
+//   merge  : per bucket, sort by start in LDS, then a block-wide max-scan of
+//            ends with the carry finds merge breaks; each break starts a
+//            component written as (start, prefix measure within bucket)
+//   base   : per-bucket prefix of the buckets' measures
+//   region : M(t) = measure of the level before t, by binary search; a
+//            region's state time is M(t1) - M(t0); per-region reductions and
+//            the FP64 ratios.
+#pragma once
+#include <stdint.h>
+
+namespace hpop {
+
+constexpr int kLevels = 3;
+constexpr int64_t kTimeLimit = int64_t(1) << 62;
+constexpr int kSlotShift = 62;  // element end word: end | slot << 62
+
+struct ChunkDesc {
+  const int64_t* s;
+  const int64_t* e;
+  int64_t count;
+  int64_t tile_begin;  // first tile of this chunk in the streaming passes
+  int32_t seg;         // global segment (resource) index
+  int32_t slot;        // level rank of the kind: 0, 1 or 2
+  int32_t chunk_id;    // index in the chunk table (error reports)
+  int32_t pad;
+};
+
+struct SegDesc {
+  int64_t bucket_begin;  // first global bucket of the segment
+  int32_t log_nb;        // the segment has 1 << log_nb buckets
+  int32_t n_levels;      // 2 for devices, 3 for hosts
+};
+
+struct SegStats {
+  unsigned long long min_s;  // over valid non-empty records; ULLONG_MAX if none
+  unsigned long long max_s;
+  unsigned long long max_e;
+  unsigned long long pad;
+};
+
+struct RegionDesc {
+  int64_t t0, t1;
+  int32_t seg_begin;   // first segment of the region's session (hosts first, then devices)
+  int32_t n_hosts;
+  int32_t n_devices;
+  int32_t pad;
+  int64_t times_off;   // offset (in resources) of the region's rows in the times array
+};
+
+struct Tree {  // identical layout to hpop_metric_tree
+  int64_t E;
+  int32_t n, m;
+  int64_t sum[10];
+  double ratio[9];
+  uint32_t undefined_mask;
+  uint32_t reserved;
+};
+
+struct Comp {  // one merged component inside a bucket
+  int64_t cs;  // start
+  int64_t pl;  // measure of the level before cs, counted from the bucket's start (with carry)
+};
+
+struct Elem {  // one record regrouped by bucket
+  int64_t s;
+  int64_t e_slot;  // end | slot << 62
+};
+
+// Device pointers of one build plan.
+struct Plan {
+  const ChunkDesc* chunks;
+  int32_t n_chunks;
+  int32_t n_segs;
+  int64_t n_tiles;
+  int32_t tile_elems;
+  int32_t cap;                       // records a bucket may hold for the LDS sort
+  const SegDesc* segs;
+  SegStats* stats;
+  int64_t n_buckets;
+  unsigned int* counts;              // [n_buckets]
+  unsigned long long* offsets;       // [n_buckets + 1]
+  unsigned long long* cursor;        // [n_buckets]
+  unsigned long long* maxend;        // [n_buckets][3] per slot, 0 = none
+  long long* carry;                  // [n_buckets][3] per level
+  long long* bsum;                    // [n_buckets][3] measure contributed by the bucket
+  unsigned int* ncomp;               // [n_buckets][3]
+  long long* base;                    // [n_buckets][3] measure of all earlier buckets
+  long long* seg_total;              // [n_segs][3]
+  Elem* elems;                       // [n_elems]
+  Elem* elems2;                      // [n_elems] scratch for oversized buckets
+  Comp* comp[kLevels];               // [n_elems] each
+  int64_t n_elems;
+  unsigned long long* err;           // [0] first bad record: chunk << 40 | index
+  unsigned long long* scan_state;    // decoupled look-back words of the bucket scan
+  unsigned int* ticket;              // [4] tickets / counters
+  unsigned long long* oversized;     // [0] buckets above the on-chip capacity
+};
+
+}  // namespace hpop

@@ -1,0 +1,23 @@
+// Launchers of the reduction kernels (all asynchronous on `st`).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "hpop_internal.h"
+
+namespace hpop {
+
+constexpr int kScanTile = 4096;  // bucket counts per workgroup of the offset scan
+constexpr int kHistWin = 2048;   // LDS bucket window of one streaming tile
+
+hipError_t launch_reset(const Plan& p, hipStream_t st);
+hipError_t launch_stats(const Plan& p, hipStream_t st);
+hipError_t launch_hist(const Plan& p, hipStream_t st);
+hipError_t launch_scan(const Plan& p, hipStream_t st);
+hipError_t launch_scatter(const Plan& p, hipStream_t st);
+hipError_t launch_carry(const Plan& p, hipStream_t st);
+hipError_t launch_merge(const Plan& p, int cap, hipStream_t st);
+hipError_t launch_base(const Plan& p, hipStream_t st);
+hipError_t launch_region(const Plan& p, const RegionDesc* regions, int n_regions, Tree* trees, long long* times,
+                         hipStream_t st);
+
+}  // namespace hpop

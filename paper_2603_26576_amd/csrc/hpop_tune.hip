@@ -1,0 +1,147 @@
+// Autotuner: picks the bucket size, on-chip bucket capacity and streaming tile
+// of the reduction kernels by timing full builds on the caller's workload, and
+// remembers the choice per workload size class in a small JSON file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "hpop.h"
+#include "hpop_runtime.h"
+
+using namespace hpop;
+
+namespace {
+
+// size class: log2 of records and of resources, rounded
+std::string size_key(hpop_session* const* ss, int k) {
+  long long ev = 0, res = 0;
+  for (int i = 0; i < k; ++i) {
+    ev += ss[i]->n_events;
+    res += ss[i]->n_hosts + ss[i]->n_devices;
+  }
+  char buf[96];
+  snprintf(buf, sizeof buf, "ev2^%d_res2^%d_k2^%d", (int)std::lround(std::log2((double)std::max(1ll, ev))),
+           (int)std::lround(std::log2((double)std::max(1ll, res))), (int)std::lround(std::log2((double)k)));
+  return buf;
+}
+
+// cache file: {"key": [bucket_target, bucket_cap, tile_elems], ...}
+std::map<std::string, std::vector<int>> read_cache(const char* path) {
+  std::map<std::string, std::vector<int>> m;
+  std::ifstream f(path);
+  if (!f) return m;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t i = 0;
+  while (true) {
+    size_t q0 = s.find('"', i);
+    if (q0 == std::string::npos) break;
+    size_t q1 = s.find('"', q0 + 1);
+    if (q1 == std::string::npos) break;
+    size_t b0 = s.find('[', q1), b1 = s.find(']', q1);
+    if (b0 == std::string::npos || b1 == std::string::npos || b1 < b0) break;
+    int a = 0, b = 0, c = 0;
+    if (sscanf(s.c_str() + b0 + 1, "%d , %d , %d", &a, &b, &c) == 3) m[s.substr(q0 + 1, q1 - q0 - 1)] = {a, b, c};
+    i = b1 + 1;
+  }
+  return m;
+}
+
+bool write_cache(const char* path, const std::map<std::string, std::vector<int>>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    if (!f) return false;
+    f << "{\n";
+    size_t n = 0;
+    for (auto& kv : m) {
+      f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", " << kv.second[2] << "]"
+        << (++n < m.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+  }
+  return std::rename(tmp.c_str(), path) == 0;
+}
+
+hpop_status run_once(hpop_session* const* ss, int k, std::vector<hpop_metric_tree>& out) {
+  if (k == 1) return hpop_metrics_compute_all(ss[0], HPOP_FORCE_REBUILD, out.data());
+  return hpop_batch_compute(ss, k, HPOP_FORCE_REBUILD, out.data());
+}
+
+}  // namespace
+
+extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const char* cache_path, hpop_tuning* out) {
+  try {
+    if (!ss || k <= 0 || !out) {
+      g_thread_error = "bad arguments";
+      return HPOP_E_ARG;
+    }
+    for (int i = 0; i < k; ++i)
+      if (!ss[i]) {
+        g_thread_error = "null session";
+        return HPOP_E_ARG;
+      }
+    const std::string key = size_key(ss, k);
+    std::map<std::string, std::vector<int>> cache;
+    if (cache_path) cache = read_cache(cache_path);
+    hpop_tuning best{};
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      best.bucket_target = it->second[0];
+      best.bucket_cap = it->second[1];
+      best.tile_elems = it->second[2];
+    } else {
+      size_t nreg = 0;
+      for (int i = 0; i < k; ++i) nreg += ss[i]->regions.size();
+      std::vector<hpop_metric_tree> trees(std::max<size_t>(1, nreg));
+      double best_t = 1e30;
+      const int targets[] = {256, 512, 1024};
+      const int caps[] = {2048, 4096};
+      const int tiles[] = {2048, 4096, 8192};
+      for (int tg : targets)
+        for (int cp : caps)
+          for (int tl : tiles) {
+            if (cp == 4096 && tg < 512) continue;  // small buckets never need the large capacity
+            hpop_tuning t{tg, cp, tl, 0};
+            for (int i = 0; i < k; ++i) ss[i]->tuning = t;
+            hpop_status st = run_once(ss, k, trees);  // warm-up: plan, allocations, graph
+            if (st != HPOP_OK) return st;
+            std::vector<double> v;
+            for (int r = 0; r < 3; ++r) {
+              auto t0 = std::chrono::steady_clock::now();
+              st = run_once(ss, k, trees);
+              auto t1 = std::chrono::steady_clock::now();
+              if (st != HPOP_OK) return st;
+              v.push_back(std::chrono::duration<double>(t1 - t0).count());
+            }
+            std::sort(v.begin(), v.end());
+            if (v[1] < best_t) {
+              best_t = v[1];
+              best = t;
+            }
+          }
+      if (cache_path) {
+        cache[key] = {best.bucket_target, best.bucket_cap, best.tile_elems};
+        if (!write_cache(cache_path, cache)) {
+          g_thread_error = std::string("cannot write tuning cache ") + cache_path;
+          return HPOP_E_ARG;
+        }
+      }
+    }
+    for (int i = 0; i < k; ++i) ss[i]->tuning = best;
+    *out = best;
+    return HPOP_OK;
+  } catch (...) {
+    g_thread_error = "internal error in autotune";
+    return HPOP_E_STATE;
+  }
+}

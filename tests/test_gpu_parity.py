@@ -1,0 +1,204 @@
+"""GPU parity: the HIP engine, called through its C ABI, against the CPU oracle.
+
+Integers (state times, sums, maxima) must be bit-exact; the FP64 ratios come
+from the same exact integers through one IEEE division each, so they must be
+bit-identical (the stated bound is 1e-15 relative; the test demands 0).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2603_26576_amd as hp
+import tracegen as tg
+import pils
+from engine_util import assert_same, engine_results, gpu_available, new_session, run_engine
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    hp.lib()
+
+
+def check(trace, **kw):
+    print("case: n=%d m=%d events=%d regions=%d %s" % (trace.n_hosts, trace.n_devices, trace.n_events,
+                                                        len(trace.regions), kw), flush=True)
+    want = oracle.compute(trace)
+    got = run_engine(trace, **kw)
+    assert_same(got, want, str(kw))
+    return got
+
+
+@pytest.mark.parametrize("case", pils.load(), ids=lambda c: c[0])
+def test_pils_tables(case):
+    name, printed, t = case
+    for variant in ({}, {"kernel_streams": 4, "hidden_memops": 3}, {"t0": tg.T0}):
+        got = check(pils.build_trace(t, **variant))
+        assert np.all(np.abs(got["ratios"][0] - np.array(printed)) <= 0.005 + 1e-12)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_tiny(seed):
+    rng = np.random.default_rng(1000 + seed)
+    tr = tg.random_tiny(rng, max_span=int(rng.integers(2, 5000)), max_events=int(rng.integers(1, 300)),
+                        t0=int(rng.integers(0, 1 << 61)), n_regions=4)
+    check(tr)
+
+
+def test_small_config_full_size():
+    check(tg.small())
+
+
+def test_mid_config_scaled():
+    check(tg.mid(scale=0.02))
+
+
+def test_large_config_scaled():
+    check(tg.large(scale=0.004, ranks=32))
+
+
+def test_device_pointer_input_matches_host_input():
+    tr = tg.make_trace(21, 5, 5, 4, 3000, 1000, regions="tiles", n_regions=7)
+    a = run_engine(tr)
+    b = run_engine(tr, device=True)
+    assert_same(b, a, "device input")
+
+
+@pytest.mark.parametrize("tuning", [
+    {"bucket_target": 16, "bucket_cap": 2048, "tile_elems": 2048},
+    {"bucket_target": 256, "bucket_cap": 4096, "tile_elems": 8192},
+    {"bucket_target": 4096, "bucket_cap": 2048, "tile_elems": 4096},
+    {"bucket_target": 4096, "bucket_cap": 4096, "tile_elems": 2048},
+])
+def test_tunings_agree(tuning):
+    tr = tg.make_trace(22, 4, 4, 8, 20000, 5000, w_range=(0.5, 1.5), regions="nested", n_regions=6)
+    check(tr, tuning=tuning)
+
+
+def test_oversized_bucket_slow_path():
+    """Most starts packed in a few ns with one far outlier: one bucket gets
+    every record and must take the global-memory sort path."""
+    rng = np.random.default_rng(5)
+    n = 30000
+    s = rng.integers(0, 3000, size=n).astype(np.int64)
+    e = s + rng.integers(1, 50, size=n)
+    s[-1], e[-1] = 10 ** 9, 10 ** 9 + 5
+    k = rng.random(n) < 0.3
+    chunks = [tg.Chunk(0, tg.DEV_KERNEL, s[~k], e[~k]), tg.Chunk(0, tg.DEV_MEMOP, s[k], e[k])]
+    hs = np.sort(rng.integers(0, 5000, size=9000)).astype(np.int64)
+    chunks.append(tg.Chunk(1, tg.DEV_KERNEL, hs, hs + 3))
+    tr = tg.Trace(0, 2, chunks, [(0, 10 ** 9 + 10), (100, 2000), (1500, 10 ** 9 + 1)])
+    got = check(tr)
+    s_ = hp.hpop_session_create(0, 2)
+    try:
+        hp.add_chunks(s_, [(c.resource, c.kind, c.start, c.end) for c in tr.chunks])
+        for a, b in tr.regions:
+            hp.hpop_region_define(s_, a, b)
+        hp.hpop_metrics_compute_all(s_)
+        assert hp.hpop_session_get_info(s_).n_oversized >= 1
+    finally:
+        hp.hpop_session_destroy(s_)
+
+
+def test_identical_starts_and_degenerate_intervals():
+    n = 5000
+    s = np.full(n, 7_000_000, np.int64)
+    e = s + np.arange(n) % 17  # many empty intervals
+    chunks = [tg.Chunk(0, tg.HOST_USEFUL, s, e), tg.Chunk(0, tg.HOST_MPI, s - 3, s + 40),
+              tg.Chunk(1, tg.DEV_KERNEL, np.array([5, 5, 5, 9], np.int64), np.array([5, 9, 9, 9], np.int64)),
+              tg.Chunk(1, tg.DEV_MEMOP, np.array([0, 9], np.int64), np.array([20, 9], np.int64))]
+    tr = tg.Trace(1, 1, chunks, [(0, 8_000_000), (7_000_001, 7_000_016), (6, 7)])
+    check(tr)
+
+
+def test_resources_without_records_and_empty_session():
+    tr = tg.Trace(3, 2, [tg.Chunk(1, tg.HOST_USEFUL, np.array([10], np.int64), np.array([20], np.int64))],
+                  [(0, 100)])
+    check(tr)
+    check(tg.Trace(2, 2, [], [(0, 100), (5, 6)]))
+
+
+def test_extreme_timestamps():
+    top = (1 << 62) - 1
+    chunks = [tg.Chunk(0, tg.DEV_KERNEL, np.array([0, top - 10, top - 5], np.int64),
+                       np.array([3, top - 1, top], np.int64)),
+              tg.Chunk(0, tg.DEV_MEMOP, np.array([1, top - 20], np.int64), np.array([top - 30, top - 2], np.int64))]
+    tr = tg.Trace(0, 1, chunks, [(top - (1 << 52), top), (0, 1 << 40)])
+    check(tr)
+
+
+def test_repeated_builds_identical_and_graph_replay():
+    tr = tg.make_trace(31, 6, 6, 4, 20000, 4000, regions="tiles", n_regions=5)
+    want = oracle.compute(tr)
+    s, keep = new_session(tr)
+    try:
+        for _ in range(5):
+            got = engine_results(s, tr, flags=hp.HPOP_FORCE_REBUILD)
+            assert_same(got, want, "replay")
+        assert hp.hpop_session_get_info(s).graph_replays >= 4
+    finally:
+        hp.hpop_session_destroy(s)
+
+
+def test_incremental_add_and_new_region():
+    tr = tg.make_trace(32, 4, 4, 4, 5000, 2000, regions="nested", n_regions=3)
+    half = len(tr.chunks) // 2
+    first = tg.Trace(tr.n_hosts, tr.n_devices, tr.chunks[:half], tr.regions)
+    s, keep = new_session(first)
+    try:
+        assert_same(engine_results(s, first), oracle.compute(first), "first half")
+        keep2 = hp.add_chunks(s, [(c.resource, c.kind, c.start, c.end) for c in tr.chunks[half:]])
+        assert_same(engine_results(s, tr), oracle.compute(tr), "all")
+        lo, hi = tr.span()
+        hp.hpop_region_define(s, lo + 1000, hi - 999)
+        tr2 = tg.Trace(tr.n_hosts, tr.n_devices, tr.chunks, tr.regions + [(lo + 1000, hi - 999)])
+        assert_same(engine_results(s, tr2), oracle.compute(tr2), "new region")
+    finally:
+        hp.hpop_session_destroy(s)
+
+
+def test_invalid_device_record_reported_and_dropped():
+    import torch
+    good = tg.make_trace(33, 2, 2, 2, 500, 200)
+    s, keep = new_session(good)
+    try:
+        bad_s = torch.tensor([10, 20, 30], dtype=torch.int64, device="cuda")
+        bad_e = torch.tensor([11, 19, 31], dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        hp.hpop_add_events(s, 2, hp.HPOP_DEV_KERNEL, bad_s, bad_e)
+        with pytest.raises(hp.HpopError) as ei:
+            hp.hpop_metrics_compute_all(s)
+        assert ei.value.status == hp.HPOP_E_BAD_INTERVAL
+        assert "index 1" in ei.value.message
+        # the offending call was dropped: the session equals the good trace again
+        assert_same(engine_results(s, good), oracle.compute(good), "after drop")
+    finally:
+        hp.hpop_session_destroy(s)
+
+
+def test_batched_equals_single():
+    traces = tg.batched(seed=77, n_traces=12, max_events=3e4)
+    sessions = []
+    try:
+        for tr in traces:
+            s, _ = new_session(tr)
+            sessions.append(s)
+        trees = hp.hpop_batch_compute(sessions)
+        k = 0
+        for tr in traces:
+            want = oracle.compute(tr)
+            for g in range(len(tr.regions)):
+                np.testing.assert_array_equal(hp.tree_sums(trees[k]), want["sums"][g])
+                np.testing.assert_array_equal(hp.tree_ratios(trees[k]).view(np.int64),
+                                              want["ratios"][g].view(np.int64))
+                k += 1
+        # replayed graph gives the same trees
+        again = hp.hpop_batch_compute(sessions, hp.HPOP_FORCE_REBUILD)
+        for a, b in zip(trees, again):
+            np.testing.assert_array_equal(hp.tree_sums(a), hp.tree_sums(b))
+    finally:
+        for s in sessions:
+            hp.hpop_session_destroy(s)
