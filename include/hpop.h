@@ -117,6 +117,7 @@ typedef struct {
     int64_t n_chunks;       /* add_events calls kept */
     int64_t n_buckets;      /* time buckets of the last build */
     int64_t n_oversized;    /* buckets of the last build too large for the on-chip sort */
+    int64_t n_components;   /* merged intervals written by the last build, all levels */
     int32_t n_regions;
     int32_t graph_replays;  /* builds served by replaying a captured HIP graph */
 } hpop_session_info;

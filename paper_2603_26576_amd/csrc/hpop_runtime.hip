@@ -825,6 +825,18 @@ hpop_status hpop_session_get_info(const hpop_session* s, hpop_session_info* out)
   out->n_chunks = (int64_t)s->chunks.size();
   out->n_buckets = s->engine.ws.plan.n_buckets;
   out->n_oversized = s->engine.last_oversized;
+  out->n_components = 0;
+  if (s->engine.built && s->engine.ws.plan.n_buckets > 0) {
+    // read back the per-bucket component counts (diagnostics, not on the hot path)
+    const long long nb = s->engine.ws.plan.n_buckets;
+    std::vector<unsigned int> nc((size_t)(3 * nb));
+    if (hipStreamSynchronize(s->stream) == hipSuccess &&
+        hipMemcpy(nc.data(), s->engine.ws.plan.ncomp, nc.size() * 4, hipMemcpyDeviceToHost) == hipSuccess) {
+      long long t = 0;
+      for (unsigned int v : nc) t += v;
+      out->n_components = t;
+    }
+  }
   out->n_regions = (int32_t)s->regions.size();
   out->graph_replays = s->engine.graph_replays + s->batch_engine.graph_replays;
   return HPOP_OK;
