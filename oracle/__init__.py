@@ -23,6 +23,18 @@ SUM_NAMES = ["sumU", "sumW", "sumMPI", "sumOther", "sumUW", "maxUW", "sumK", "su
 _lib = None
 
 
+def load_library(path):
+    """ctypes handle with the oracle's signatures (also used to load rebuilt variants)."""
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.oracle_union_measure.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P, P, P]
+    lib.oracle_union_measure.restype = ctypes.c_int
+    lib.oracle_compute.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P, P, P, P,
+                                   ctypes.c_int32, P, P, ctypes.c_int32, P, P, P, P]
+    lib.oracle_compute.restype = ctypes.c_int
+    return lib
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc -O2 into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
@@ -38,14 +50,7 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        lib.oracle_union_measure.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, P, P, P]
-        lib.oracle_union_measure.restype = ctypes.c_int
-        lib.oracle_compute.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, P, P, P, P,
-                                       ctypes.c_int32, P, P, ctypes.c_int32, P, P, P, P]
-        lib.oracle_compute.restype = ctypes.c_int
-        _lib = lib
+        _lib = load_library(_LIB)
     return _lib
 
 
@@ -72,8 +77,8 @@ class OracleError(ValueError):
         self.code = code
 
 
-def compute_arrays(n_hosts, n_devices, resource, kind, start, end, regions, threads=1):
-    lib = _load()
+def compute_arrays(n_hosts, n_devices, resource, kind, start, end, regions, threads=1, lib=None):
+    lib = lib or _load()
     resource = np.ascontiguousarray(resource, np.int32)
     kind = np.ascontiguousarray(kind, np.int32)
     start = np.ascontiguousarray(start, np.int64)
@@ -94,8 +99,8 @@ def compute_arrays(n_hosts, n_devices, resource, kind, start, end, regions, thre
     return {"times": times, "sums": sums, "ratios": ratios, "mask": mask}
 
 
-def compute(trace, threads=1, regions=None):
+def compute(trace, threads=1, regions=None, lib=None):
     """Evaluate a tracegen.Trace: dict with times, sums, ratios, mask arrays."""
     res, kind, s, e = trace.flat()
     return compute_arrays(trace.n_hosts, trace.n_devices, res, kind, s, e,
-                          trace.regions if regions is None else regions, threads)
+                          trace.regions if regions is None else regions, threads, lib)

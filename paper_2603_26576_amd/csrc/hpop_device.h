@@ -1,0 +1,485 @@
+// Device building blocks shared by the trace-reduction and serving kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "hpop_internal.h"
+
+namespace hpop {
+
+// ----------------------------------------------------------------------------
+// small device helpers
+// ----------------------------------------------------------------------------
+
+__device__ __forceinline__ int bitlen64(unsigned long long x) { return x ? 64 - __clzll((long long)x) : 0; }
+
+__device__ __forceinline__ bool rec_valid(long long s, long long e) {
+  return s >= 0 && s <= e && e < kTimeLimit;
+}
+
+struct Geom {
+  long long min_s;
+  long long max_e;
+  int shift;
+  int log_nb;
+  bool empty;
+};
+
+__device__ __forceinline__ Geom seg_geom(const SegStats& st, const SegDesc& sd) {
+  Geom g;
+  g.empty = st.min_s > st.max_s;
+  g.min_s = (long long)st.min_s;
+  g.max_e = (long long)st.max_e;
+  g.log_nb = sd.log_nb;
+  const int bl = g.empty ? 0 : bitlen64(st.max_s - st.min_s);
+  g.shift = bl > sd.log_nb ? bl - sd.log_nb : 0;
+  return g;
+}
+
+// bucket of a record start inside its segment (clamped; start >= min_s for valid records)
+__device__ __forceinline__ int bucket_of(long long s, const Geom& g) {
+  unsigned long long rel = (unsigned long long)(s - g.min_s);
+  unsigned long long b = rel >> g.shift;
+  const unsigned long long nb = 1ull << g.log_nb;
+  return (int)(b < nb ? b : nb - 1);
+}
+
+// index of the last entry with key <= x in a sorted array of n int64 (n >= 1, a[0] <= x)
+__device__ __forceinline__ int upper_index_chunk(const ChunkDesc* c, int n, long long x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (c[mid].tile_begin <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int upper_index_seg(const SegDesc* s, int n, long long x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (s[mid].bucket_begin <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ long long wave_red_min(long long v) {
+  for (int d = 32; d >= 1; d >>= 1) { long long o = __shfl_xor(v, d, 64); v = o < v ? o : v; }
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_red_minu(unsigned long long v) {
+  for (int d = 32; d >= 1; d >>= 1) { unsigned long long o = __shfl_xor(v, d, 64); v = o < v ? o : v; }
+  return v;
+}
+__device__ __forceinline__ unsigned long long wave_red_maxu(unsigned long long v) {
+  for (int d = 32; d >= 1; d >>= 1) { unsigned long long o = __shfl_xor(v, d, 64); v = o > v ? o : v; }
+  return v;
+}
+__device__ __forceinline__ long long wave_red_sum(long long v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+__device__ __forceinline__ long long wave_red_max(long long v) {
+  for (int d = 32; d >= 1; d >>= 1) { long long o = __shfl_xor(v, d, 64); v = o > v ? o : v; }
+  return v;
+}
+
+struct OpMax {
+  __device__ static long long apply(long long a, long long b) { return a > b ? a : b; }
+};
+struct OpSum {
+  __device__ static long long apply(long long a, long long b) { return a + b; }
+};
+
+// Block-wide exclusive scan of K int64 lanes per thread (thread order), with totals.
+// `lds` holds NW*K int64. Contains barriers: call from uniform control flow.
+template <int THREADS, int K, class Op>
+__device__ __forceinline__ void block_excl_scan(const long long (&v)[K], long long (&excl)[K],
+                                                long long (&total)[K], long long ident, long long* lds) {
+  constexpr int NW = THREADS / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  long long inc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    long long x = v[k];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      long long y = __shfl_up(x, d, 64);
+      if (lane >= d) x = Op::apply(x, y);
+    }
+    inc[k] = x;
+  }
+  if (lane == 63) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) lds[wave * K + k] = inc[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    long long pre = ident, tot = ident;
+    for (int w = 0; w < NW; ++w) {
+      const long long t = lds[w * K + k];
+      if (w < wave) pre = Op::apply(pre, t);
+      tot = Op::apply(tot, t);
+    }
+    long long ex = __shfl_up(inc[k], 1, 64);
+    if (lane == 0) ex = ident;
+    excl[k] = Op::apply(pre, ex);
+    total[k] = tot;
+  }
+  __syncthreads();
+}
+
+// One stable LSD pass on 8 bits of (start - lo) >> sh over the positions
+// in[0..n): out[] receives the element indices in the new order, dstart[d] the
+// first output position of digit d. Waves own contiguous position ranges;
+// lanes with equal digits are matched with ballots, so the pass is stable.
+template <int THREADS, int MAXR>
+__device__ __forceinline__ void radix_pass(const Elem* E, const unsigned short* in, unsigned short* out, int n,
+                                           long long lo, int sh, unsigned int* whist, unsigned int* dstart,
+                                           long long* lds_scan) {
+  constexpr int NW = THREADS / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int span = (((n + NW - 1) / NW) + 63) & ~63;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int i = threadIdx.x; i < NW * 256; i += THREADS) whist[i] = 0;
+  __syncthreads();
+  unsigned int loc[MAXR];
+  unsigned char dig[MAXR];
+  unsigned short idx[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) {
+    loc[r] = 0;
+    dig[r] = 0;
+    idx[r] = 0;
+    if (r * 64 < span) {  // wave-uniform
+      const int pos = wave * span + r * 64 + lane;
+      const bool act = pos < n;
+      const unsigned short i = act ? (in ? in[pos] : (unsigned short)pos) : (unsigned short)0;
+      const unsigned int d = act ? (unsigned int)(((unsigned long long)(E[i].s - lo) >> sh) & 255ull) : 0u;
+      unsigned long long peers = __ballot(act);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const bool b = (d >> bit) & 1u;
+        const unsigned long long m = __ballot(b);
+        peers &= b ? m : ~m;
+      }
+      if (act) {
+        unsigned int* h = &whist[wave * 256 + d];
+        const unsigned int before = *h;
+        loc[r] = before + (unsigned int)__popcll(peers & lt);
+        dig[r] = (unsigned char)d;
+        idx[r] = i;
+        if ((peers & lt) == 0) *h = before + (unsigned int)__popcll(peers);
+      }
+    }
+  }
+  __syncthreads();
+  // digit-major exclusive prefix over (digit, wave)
+  {
+    long long tot = 0;
+    unsigned int h[NW];
+    if (threadIdx.x < 256) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) { h[w] = whist[w * 256 + threadIdx.x]; tot += h[w]; }
+    }
+    long long v[1] = {threadIdx.x < 256 ? tot : 0}, ex[1], all[1];
+    block_excl_scan<THREADS, 1, OpSum>(v, ex, all, 0, lds_scan);
+    if (threadIdx.x < 256) {
+      unsigned int run = (unsigned int)ex[0];
+      dstart[threadIdx.x] = run;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) { whist[w * 256 + threadIdx.x] = run; run += h[w]; }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) {
+    if (r * 64 < span) {
+      const int pos = wave * span + r * 64 + lane;
+      if (pos < n) out[whist[wave * 256 + dig[r]] + loc[r]] = idx[r];
+    }
+  }
+  __syncthreads();
+}
+
+struct FlatState {
+  long long M[3];  // running max end (with the carry)
+  long long P[3];  // measure accumulated in this bucket
+  long long R[3];  // components written in this bucket
+};
+
+// Flatten one sorted tile: positions 0..n-1 in order ord (or identity).
+// Writes components of each level at comp[l][off + R], advances `st`.
+template <int THREADS>
+__device__ __forceinline__ void flatten_tile(const Elem* E, const unsigned short* ord, int n, int nlev,
+                                             long long off, Comp* const* comp, FlatState& st, long long* lds_scan,
+                                             long long* lds_bc) {
+  const int ipt = (n + THREADS - 1) / THREADS;
+  const int p0 = threadIdx.x * ipt;
+  const int p1 = min(n, p0 + ipt);
+  const long long EMASK = (1ll << kSlotShift) - 1;
+  // phase A: exclusive max-scan of ends per level
+  long long tmax[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
+  for (int q = p0; q < p1; ++q) {
+    const Elem el = E[ord ? ord[q] : q];
+    const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
+    const long long e = el.e_slot & EMASK;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      if (slot <= l && e > tmax[l]) tmax[l] = e;
+  }
+  long long exm[3], totm[3];
+  block_excl_scan<THREADS, 3, OpMax>(tmax, exm, totm, LLONG_MIN, lds_scan);
+  long long M[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) M[l] = exm[l] > st.M[l] ? exm[l] : st.M[l];
+  // phase B: per-thread measure and break counts
+  long long acc[6] = {0, 0, 0, 0, 0, 0};
+  {
+    long long Mb[3] = {M[0], M[1], M[2]};
+    for (int q = p0; q < p1; ++q) {
+      const Elem el = E[ord ? ord[q] : q];
+      const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
+      const long long e = el.e_slot & EMASK;
+      const long long s = el.s;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        if (l < nlev && slot <= l) {
+          const long long lo = s > Mb[l] ? s : Mb[l];
+          if (e > lo) acc[l] += e - lo;
+          if (s > Mb[l]) acc[3 + l] += 1;
+          if (e > Mb[l]) Mb[l] = e;
+        }
+      }
+    }
+  }
+  long long exa[6], tota[6];
+  block_excl_scan<THREADS, 6, OpSum>(acc, exa, tota, 0, lds_scan);
+  // phase C: write components
+  {
+    long long P[3], R[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      P[l] = st.P[l] + exa[l];
+      R[l] = st.R[l] + exa[3 + l];
+    }
+    for (int q = p0; q < p1; ++q) {
+      const Elem el = E[ord ? ord[q] : q];
+      const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
+      const long long e = el.e_slot & EMASK;
+      const long long s = el.s;
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        if (l < nlev && slot <= l) {
+          if (s > M[l]) {
+            Comp c;
+            c.cs = s;
+            c.pl = P[l];
+            comp[l][off + R[l]] = c;
+            R[l] += 1;
+          }
+          const long long lo = s > M[l] ? s : M[l];
+          if (e > lo) P[l] += e - lo;
+          if (e > M[l]) M[l] = e;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    st.M[l] = totm[l] > st.M[l] ? totm[l] : st.M[l];
+    st.P[l] += tota[l];
+    st.R[l] += tota[3 + l];
+  }
+  (void)lds_bc;
+}
+
+__device__ __forceinline__ double ratio(long long num, long long den, int bit, unsigned int& mask) {
+  if (den == 0) {
+    mask |= 1u << bit;
+    return 1.0;
+  }
+  return (double)num / (double)den;
+}
+
+
+// LDS of the sorting workgroups (one bucket or one list tile at a time).
+template <int THREADS, int CAP>
+struct SortSmem {
+  static constexpr int NW = THREADS / 64;
+  Elem E[CAP];
+  unsigned short ordA[CAP];
+  unsigned short ordB[CAP];
+  unsigned int whist[NW * 256];
+  unsigned int dstart[256];
+  unsigned int dcount[256];
+  long long lds_scan[NW * 6];
+  unsigned long long red[2][NW];
+};
+
+// Block-wide OR and AND of per-thread key accumulators: the bits in which keys differ.
+template <int THREADS>
+__device__ __forceinline__ unsigned long long block_vary(unsigned long long kor, unsigned long long kand,
+                                                         unsigned long long (*red)[THREADS / 64]) {
+  constexpr int NW = THREADS / 64;
+  for (int d = 32; d >= 1; d >>= 1) {
+    kor |= __shfl_xor(kor, d, 64);
+    kand &= __shfl_xor(kand, d, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[0][wave] = kor;
+    red[1][wave] = kand;
+  }
+  __syncthreads();
+  kor = 0;
+  kand = ~0ull;
+  for (int w = 0; w < NW; ++w) {
+    kor |= red[0][w];
+    kand &= red[1][w];
+  }
+  __syncthreads();
+  return kor ^ kand;
+}
+
+// Sort sm.E[0..n) (n <= CAP, already in LDS and visible to the block) by
+// start - lo. Returns the sorted order, or nullptr when E is already in an
+// acceptable order (all starts equal). Only the bits that vary are sorted.
+template <int THREADS, int CAP>
+__device__ const unsigned short* sort_lds(SortSmem<THREADS, CAP>& sm, int n, long long lo) {
+  constexpr int MAXR = CAP / THREADS;
+  unsigned long long kor = 0, kand = ~0ull;
+  for (int i = threadIdx.x; i < n; i += THREADS) {
+    const unsigned long long k = (unsigned long long)(sm.E[i].s - lo);
+    kor |= k;
+    kand &= k;
+  }
+  const unsigned long long vary = block_vary<THREADS>(kor, kand, sm.red);
+  if (!vary) return nullptr;
+  const int lb = __ffsll((long long)vary) - 1;
+  const int hb = bitlen64(vary);
+  const int passes = (hb - lb + 7) >> 3;
+  const unsigned short* in = nullptr;  // identity for the first pass
+  for (int ps = 0; ps < passes; ++ps) {
+    unsigned short* out = (ps & 1) ? sm.ordB : sm.ordA;
+    radix_pass<THREADS, MAXR>(sm.E, in, out, n, lo, lb + 8 * ps, sm.whist, sm.dstart, sm.lds_scan);
+    in = out;
+  }
+  return in;
+}
+
+// Stable LSD sort of n records in global memory by start - lo, CAP records of
+// LDS at a time; dst is scratch of the same size. Returns the buffer that
+// holds the sorted records (src or dst).
+template <int THREADS, int CAP>
+__device__ Elem* sort_global(SortSmem<THREADS, CAP>& sm, Elem* src, Elem* dst, long long n, long long lo) {
+  constexpr int MAXR = CAP / THREADS;
+  unsigned long long kor = 0, kand = ~0ull;
+  for (long long i = threadIdx.x; i < n; i += THREADS) {
+    const unsigned long long k = (unsigned long long)(src[i].s - lo);
+    kor |= k;
+    kand &= k;
+  }
+  const unsigned long long vary = block_vary<THREADS>(kor, kand, sm.red);
+  if (!vary) return src;
+  const int lb = __ffsll((long long)vary) - 1;
+  const int hb = bitlen64(vary);
+  const int passes = (hb - lb + 7) >> 3;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int sh = lb + 8 * ps;
+    // digit histogram of all records -> running output base per digit
+    for (int i = threadIdx.x; i < 256; i += THREADS) sm.dcount[i] = 0;
+    __syncthreads();
+    for (long long i = threadIdx.x; i < n; i += THREADS)
+      atomicAdd(&sm.dcount[((unsigned long long)(src[i].s - lo) >> sh) & 255ull], 1u);
+    __syncthreads();
+    {
+      long long v[1] = {threadIdx.x < 256 ? (long long)sm.dcount[threadIdx.x] : 0}, ex[1], all[1];
+      block_excl_scan<THREADS, 1, OpSum>(v, ex, all, 0, sm.lds_scan);
+      if (threadIdx.x < 256) sm.dcount[threadIdx.x] = (unsigned int)ex[0];
+    }
+    __syncthreads();
+    for (long long t0 = 0; t0 < n; t0 += CAP) {
+      const int cnt = (int)min((long long)CAP, n - t0);
+      for (int i = threadIdx.x; i < cnt; i += THREADS) sm.E[i] = src[t0 + i];
+      __syncthreads();
+      radix_pass<THREADS, MAXR>(sm.E, nullptr, sm.ordA, cnt, lo, sh, sm.whist, sm.dstart, sm.lds_scan);
+      for (int q = threadIdx.x; q < cnt; q += THREADS) {
+        const unsigned short i = sm.ordA[q];
+        const unsigned int d = (unsigned int)(((unsigned long long)(sm.E[i].s - lo) >> sh) & 255ull);
+        dst[sm.dcount[d] + (q - sm.dstart[d])] = sm.E[i];
+      }
+      __syncthreads();
+      if (threadIdx.x < 256) {
+        const unsigned int d = threadIdx.x;
+        const unsigned int next = d < 255 ? sm.dstart[d + 1] : (unsigned int)cnt;
+        sm.dcount[d] += next - sm.dstart[d];
+      }
+      __syncthreads();
+    }
+    Elem* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
+// Ratios of one region's metric trees from exact integer aggregates.
+// v: sumU, sumW, sumMPI, sumOther, sumK, sumM, maxUW, maxK, maxKM
+__device__ __forceinline__ Tree make_tree(long long E, int n_hosts, int n_devices, const long long (&v)[9]) {
+  Tree t;
+  t.E = E;
+  t.n = n_hosts;
+  t.m = n_devices;
+  const long long U = v[0], W = v[1], UW = v[0] + v[1];
+  t.sum[0] = U;
+  t.sum[1] = W;
+  t.sum[2] = v[2];
+  t.sum[3] = v[3];
+  t.sum[4] = UW;
+  t.sum[5] = v[6];
+  t.sum[6] = v[4];
+  t.sum[7] = v[5];
+  t.sum[8] = v[7];
+  t.sum[9] = v[8];
+  unsigned int mask = 0;
+  const long long n = n_hosts, m = n_devices;
+  t.ratio[0] = ratio(U, n * E, 0, mask);        // eq. 6
+  t.ratio[1] = ratio(UW, n * E, 1, mask);       // eq. 7
+  t.ratio[2] = ratio(UW, n * v[6], 2, mask);    // eq. 4, U+W useful
+  t.ratio[3] = ratio(v[6], E, 3, mask);         // eq. 5, U+W useful
+  t.ratio[4] = ratio(U, UW, 4, mask);           // eq. 8
+  t.ratio[5] = ratio(v[4], m * E, 5, mask);     // eq. 9
+  t.ratio[6] = ratio(v[4], m * v[7], 6, mask);  // eq. 10
+  t.ratio[7] = ratio(v[7], v[8], 7, mask);      // eq. 11
+  t.ratio[8] = ratio(v[8], E, 8, mask);         // eq. 12
+  t.undefined_mask = mask;
+  t.reserved = 0;
+  return t;
+}
+
+// Block reduction of per-thread resource state times into a tree (thread 0
+// returns it). Per thread: host rows add U, W, MPI, Other; device rows K, M.
+template <int THREADS>
+__device__ __forceinline__ void block_tree(long long (&v)[9], long long* lds) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v[i] = wave_red_sum(v[i]);
+#pragma unroll
+  for (int i = 6; i < 9; ++i) v[i] = wave_red_max(v[i]);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+    for (int i = 0; i < 9; ++i) lds[wave * 10 + i] = v[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < THREADS / 64; ++w) {
+      for (int i = 0; i < 6; ++i) v[i] += lds[w * 10 + i];
+      for (int i = 6; i < 9; ++i) v[i] = lds[w * 10 + i] > v[i] ? lds[w * 10 + i] : v[i];
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace hpop

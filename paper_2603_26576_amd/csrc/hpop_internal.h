@@ -113,7 +113,8 @@ struct Plan {
   int64_t n_elems;
   unsigned long long* err;           // [0] first bad record: chunk << 40 | index
   unsigned long long* scan_state;    // decoupled look-back words of the bucket scan
-  unsigned int* ticket;              // [4] tickets / counters
+  unsigned int* ticket;              // [4]: scan ticket, block-path take counter, block-path queue length
+  unsigned int* queue;               // [n_buckets] buckets handed to the block path
   unsigned long long* oversized;     // [0] buckets above the on-chip capacity
 };
 

@@ -7,135 +7,14 @@
 // over bucket counts.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
+#include "hpop_device.h"
 #include "hpop_internal.h"
 #include "hpop_kernels.h"
 
 namespace hpop {
-
-// ----------------------------------------------------------------------------
-// small device helpers
-// ----------------------------------------------------------------------------
-
-__device__ __forceinline__ int bitlen64(unsigned long long x) { return x ? 64 - __clzll((long long)x) : 0; }
-
-__device__ __forceinline__ bool rec_valid(long long s, long long e) {
-  return s >= 0 && s <= e && e < kTimeLimit;
-}
-
-struct Geom {
-  long long min_s;
-  long long max_e;
-  int shift;
-  int log_nb;
-  bool empty;
-};
-
-__device__ __forceinline__ Geom seg_geom(const SegStats& st, const SegDesc& sd) {
-  Geom g;
-  g.empty = st.min_s > st.max_s;
-  g.min_s = (long long)st.min_s;
-  g.max_e = (long long)st.max_e;
-  g.log_nb = sd.log_nb;
-  const int bl = g.empty ? 0 : bitlen64(st.max_s - st.min_s);
-  g.shift = bl > sd.log_nb ? bl - sd.log_nb : 0;
-  return g;
-}
-
-// bucket of a record start inside its segment (clamped; start >= min_s for valid records)
-__device__ __forceinline__ int bucket_of(long long s, const Geom& g) {
-  unsigned long long rel = (unsigned long long)(s - g.min_s);
-  unsigned long long b = rel >> g.shift;
-  const unsigned long long nb = 1ull << g.log_nb;
-  return (int)(b < nb ? b : nb - 1);
-}
-
-// index of the last entry with key <= x in a sorted array of n int64 (n >= 1, a[0] <= x)
-__device__ __forceinline__ int upper_index_chunk(const ChunkDesc* c, int n, long long x) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (c[mid].tile_begin <= x) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ int upper_index_seg(const SegDesc* s, int n, long long x) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (s[mid].bucket_begin <= x) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ long long wave_red_min(long long v) {
-  for (int d = 32; d >= 1; d >>= 1) { long long o = __shfl_xor(v, d, 64); v = o < v ? o : v; }
-  return v;
-}
-__device__ __forceinline__ unsigned long long wave_red_minu(unsigned long long v) {
-  for (int d = 32; d >= 1; d >>= 1) { unsigned long long o = __shfl_xor(v, d, 64); v = o < v ? o : v; }
-  return v;
-}
-__device__ __forceinline__ unsigned long long wave_red_maxu(unsigned long long v) {
-  for (int d = 32; d >= 1; d >>= 1) { unsigned long long o = __shfl_xor(v, d, 64); v = o > v ? o : v; }
-  return v;
-}
-__device__ __forceinline__ long long wave_red_sum(long long v) {
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
-}
-__device__ __forceinline__ long long wave_red_max(long long v) {
-  for (int d = 32; d >= 1; d >>= 1) { long long o = __shfl_xor(v, d, 64); v = o > v ? o : v; }
-  return v;
-}
-
-struct OpMax {
-  __device__ static long long apply(long long a, long long b) { return a > b ? a : b; }
-};
-struct OpSum {
-  __device__ static long long apply(long long a, long long b) { return a + b; }
-};
-
-// Block-wide exclusive scan of K int64 lanes per thread (thread order), with totals.
-// `lds` holds NW*K int64. Contains barriers: call from uniform control flow.
-template <int THREADS, int K, class Op>
-__device__ __forceinline__ void block_excl_scan(const long long (&v)[K], long long (&excl)[K],
-                                                long long (&total)[K], long long ident, long long* lds) {
-  constexpr int NW = THREADS / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  long long inc[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    long long x = v[k];
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      long long y = __shfl_up(x, d, 64);
-      if (lane >= d) x = Op::apply(x, y);
-    }
-    inc[k] = x;
-  }
-  if (lane == 63) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) lds[wave * K + k] = inc[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    long long pre = ident, tot = ident;
-    for (int w = 0; w < NW; ++w) {
-      const long long t = lds[w * K + k];
-      if (w < wave) pre = Op::apply(pre, t);
-      tot = Op::apply(tot, t);
-    }
-    long long ex = __shfl_up(inc[k], 1, 64);
-    if (lane == 0) ex = ident;
-    excl[k] = Op::apply(pre, ex);
-    total[k] = tot;
-  }
-  __syncthreads();
-}
 
 // ----------------------------------------------------------------------------
 // reset: per-build counters to their identities
@@ -508,189 +387,13 @@ __global__ __launch_bounds__(THREADS) void k_base(Plan p) {
 // merge: per bucket, sort by start in LDS and flatten each level
 // ----------------------------------------------------------------------------
 
-// One stable LSD pass on 8 bits of (start - lo) >> sh over the positions
-// in[0..n): out[] receives the element indices in the new order, dstart[d] the
-// first output position of digit d. Waves own contiguous position ranges;
-// lanes with equal digits are matched with ballots, so the pass is stable.
-template <int THREADS, int MAXR>
-__device__ __forceinline__ void radix_pass(const Elem* E, const unsigned short* in, unsigned short* out, int n,
-                                           long long lo, int sh, unsigned int* whist, unsigned int* dstart,
-                                           long long* lds_scan) {
-  constexpr int NW = THREADS / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int span = (((n + NW - 1) / NW) + 63) & ~63;
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int i = threadIdx.x; i < NW * 256; i += THREADS) whist[i] = 0;
-  __syncthreads();
-  unsigned int loc[MAXR];
-  unsigned char dig[MAXR];
-  unsigned short idx[MAXR];
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) {
-    loc[r] = 0;
-    dig[r] = 0;
-    idx[r] = 0;
-    if (r * 64 < span) {  // wave-uniform
-      const int pos = wave * span + r * 64 + lane;
-      const bool act = pos < n;
-      const unsigned short i = act ? (in ? in[pos] : (unsigned short)pos) : (unsigned short)0;
-      const unsigned int d = act ? (unsigned int)(((unsigned long long)(E[i].s - lo) >> sh) & 255ull) : 0u;
-      unsigned long long peers = __ballot(act);
-#pragma unroll
-      for (int bit = 0; bit < 8; ++bit) {
-        const bool b = (d >> bit) & 1u;
-        const unsigned long long m = __ballot(b);
-        peers &= b ? m : ~m;
-      }
-      if (act) {
-        unsigned int* h = &whist[wave * 256 + d];
-        const unsigned int before = *h;
-        loc[r] = before + (unsigned int)__popcll(peers & lt);
-        dig[r] = (unsigned char)d;
-        idx[r] = i;
-        if ((peers & lt) == 0) *h = before + (unsigned int)__popcll(peers);
-      }
-    }
-  }
-  __syncthreads();
-  // digit-major exclusive prefix over (digit, wave)
-  {
-    long long tot = 0;
-    unsigned int h[NW];
-    if (threadIdx.x < 256) {
-#pragma unroll
-      for (int w = 0; w < NW; ++w) { h[w] = whist[w * 256 + threadIdx.x]; tot += h[w]; }
-    }
-    long long v[1] = {threadIdx.x < 256 ? tot : 0}, ex[1], all[1];
-    block_excl_scan<THREADS, 1, OpSum>(v, ex, all, 0, lds_scan);
-    if (threadIdx.x < 256) {
-      unsigned int run = (unsigned int)ex[0];
-      dstart[threadIdx.x] = run;
-#pragma unroll
-      for (int w = 0; w < NW; ++w) { whist[w * 256 + threadIdx.x] = run; run += h[w]; }
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) {
-    if (r * 64 < span) {
-      const int pos = wave * span + r * 64 + lane;
-      if (pos < n) out[whist[wave * 256 + dig[r]] + loc[r]] = idx[r];
-    }
-  }
-  __syncthreads();
-}
-
-struct FlatState {
-  long long M[3];  // running max end (with the carry)
-  long long P[3];  // measure accumulated in this bucket
-  long long R[3];  // components written in this bucket
-};
-
-// Flatten one sorted tile: positions 0..n-1 in order ord (or identity).
-// Writes components of each level at comp[l][off + R], advances `st`.
-template <int THREADS>
-__device__ __forceinline__ void flatten_tile(const Elem* E, const unsigned short* ord, int n, int nlev,
-                                             long long off, Comp* const* comp, FlatState& st, long long* lds_scan,
-                                             long long* lds_bc) {
-  const int ipt = (n + THREADS - 1) / THREADS;
-  const int p0 = threadIdx.x * ipt;
-  const int p1 = min(n, p0 + ipt);
-  const long long EMASK = (1ll << kSlotShift) - 1;
-  // phase A: exclusive max-scan of ends per level
-  long long tmax[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
-  for (int q = p0; q < p1; ++q) {
-    const Elem el = E[ord ? ord[q] : q];
-    const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
-    const long long e = el.e_slot & EMASK;
-#pragma unroll
-    for (int l = 0; l < 3; ++l)
-      if (slot <= l && e > tmax[l]) tmax[l] = e;
-  }
-  long long exm[3], totm[3];
-  block_excl_scan<THREADS, 3, OpMax>(tmax, exm, totm, LLONG_MIN, lds_scan);
-  long long M[3];
-#pragma unroll
-  for (int l = 0; l < 3; ++l) M[l] = exm[l] > st.M[l] ? exm[l] : st.M[l];
-  // phase B: per-thread measure and break counts
-  long long acc[6] = {0, 0, 0, 0, 0, 0};
-  {
-    long long Mb[3] = {M[0], M[1], M[2]};
-    for (int q = p0; q < p1; ++q) {
-      const Elem el = E[ord ? ord[q] : q];
-      const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
-      const long long e = el.e_slot & EMASK;
-      const long long s = el.s;
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        if (l < nlev && slot <= l) {
-          const long long lo = s > Mb[l] ? s : Mb[l];
-          if (e > lo) acc[l] += e - lo;
-          if (s > Mb[l]) acc[3 + l] += 1;
-          if (e > Mb[l]) Mb[l] = e;
-        }
-      }
-    }
-  }
-  long long exa[6], tota[6];
-  block_excl_scan<THREADS, 6, OpSum>(acc, exa, tota, 0, lds_scan);
-  // phase C: write components
-  {
-    long long P[3], R[3];
-#pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      P[l] = st.P[l] + exa[l];
-      R[l] = st.R[l] + exa[3 + l];
-    }
-    for (int q = p0; q < p1; ++q) {
-      const Elem el = E[ord ? ord[q] : q];
-      const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
-      const long long e = el.e_slot & EMASK;
-      const long long s = el.s;
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        if (l < nlev && slot <= l) {
-          if (s > M[l]) {
-            Comp c;
-            c.cs = s;
-            c.pl = P[l];
-            comp[l][off + R[l]] = c;
-            R[l] += 1;
-          }
-          const long long lo = s > M[l] ? s : M[l];
-          if (e > lo) P[l] += e - lo;
-          if (e > M[l]) M[l] = e;
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    st.M[l] = totm[l] > st.M[l] ? totm[l] : st.M[l];
-    st.P[l] += tota[l];
-    st.R[l] += tota[3 + l];
-  }
-  (void)lds_bc;
-}
-
+// Block path: one workgroup flattens bucket gb (LDS radix sort up to CAP
+// records, global-memory radix sort beyond).
 template <int THREADS, int CAP>
-__global__ __launch_bounds__(THREADS) void k_merge(Plan p) {
-  constexpr int NW = THREADS / 64;
-  constexpr int MAXR = CAP / THREADS;  // rounds per wave in a radix pass
-  __shared__ Elem E[CAP];
-  __shared__ unsigned short ordA[CAP];
-  __shared__ unsigned short ordB[CAP];
-  __shared__ unsigned int whist[NW * 256];
-  __shared__ unsigned int dstart[256];
-  __shared__ unsigned int dcount[256];
-  __shared__ long long lds_scan[NW * 6];
-  __shared__ unsigned long long red[2][NW];
-  __shared__ int s_seg;
-
-  const long long gb = blockIdx.x;
-  if (threadIdx.x == 0) s_seg = upper_index_seg(p.segs, p.n_segs, gb);
+__device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS, CAP>& sm, int* s_seg) {
+  if (threadIdx.x == 0) *s_seg = upper_index_seg(p.segs, p.n_segs, gb);
   __syncthreads();
-  const int seg = s_seg;
+  const int seg = *s_seg;
   const SegDesc sd = p.segs[seg];
   const Geom g = seg_geom(p.stats[seg], sd);
   const long long bl = gb - sd.bucket_begin;
@@ -704,113 +407,24 @@ __global__ __launch_bounds__(THREADS) void k_merge(Plan p) {
     st.P[l] = 0;
     st.R[l] = 0;
   }
-  Comp* comp[3] = {p.comp[0], p.comp[1], p.comp[2]};
+  Comp* comp[3] = {p.comp[0] + off, p.comp[1] + off, p.comp[2] + off};
   if (n > 0) {
     const long long lo = g.min_s + (bl << g.shift);
     if (n <= CAP) {
       const int ni = (int)n;
-      // load the bucket (coalesced 16 B per lane) and find the bits that vary
-      unsigned long long kor = 0, kand = ~0ull;
-      for (int i = threadIdx.x; i < ni; i += THREADS) {
-        const Elem el = p.elems[off + i];
-        E[i] = el;
-        const unsigned long long k = (unsigned long long)(el.s - lo);
-        kor |= k;
-        kand &= k;
-      }
-      for (int d = 32; d >= 1; d >>= 1) {
-        kor |= __shfl_xor(kor, d, 64);
-        kand &= __shfl_xor(kand, d, 64);
-      }
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      if (lane == 0) { red[0][wave] = kor; red[1][wave] = kand; }
+      for (int i = threadIdx.x; i < ni; i += THREADS) sm.E[i] = p.elems[off + i];  // coalesced 16 B per lane
       __syncthreads();
-      kor = 0; kand = ~0ull;
-      for (int w = 0; w < NW; ++w) { kor |= red[0][w]; kand &= red[1][w]; }
-      const unsigned long long vary = kor ^ kand;
-      const unsigned short* ord = nullptr;
-      if (vary) {
-        const int lb = __ffsll((long long)vary) - 1;
-        const int hb = bitlen64(vary);
-        const int passes = (hb - lb + 7) >> 3;
-        unsigned short* in = nullptr;  // identity for the first pass
-        for (int ps = 0; ps < passes; ++ps) {
-          unsigned short* out = (ps & 1) ? ordB : ordA;
-          radix_pass<THREADS, MAXR>(E, in, out, ni, lo, lb + 8 * ps, whist, dstart, lds_scan);
-          in = out;
-        }
-        ord = in;
-      }
-      flatten_tile<THREADS>(E, ord, ni, nlev, off, comp, st, lds_scan, nullptr);
+      const unsigned short* ord = sort_lds<THREADS, CAP>(sm, ni, lo);
+      flatten_tile<THREADS>(sm.E, ord, ni, nlev, 0, comp, st, sm.lds_scan, nullptr);
     } else {
       // oversized bucket: stable LSD sort through global scratch, then flatten
       // CAP records at a time, carrying the running state across tiles
-      Elem* src = p.elems + off;
-      Elem* dst = p.elems2 + off;
-      unsigned long long kor = 0, kand = ~0ull;
-      for (long long i = threadIdx.x; i < n; i += THREADS) {
-        const unsigned long long k = (unsigned long long)(src[i].s - lo);
-        kor |= k;
-        kand &= k;
-      }
-      for (int d = 32; d >= 1; d >>= 1) {
-        kor |= __shfl_xor(kor, d, 64);
-        kand &= __shfl_xor(kand, d, 64);
-      }
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      if (lane == 0) { red[0][wave] = kor; red[1][wave] = kand; }
-      __syncthreads();
-      kor = 0; kand = ~0ull;
-      for (int w = 0; w < NW; ++w) { kor |= red[0][w]; kand &= red[1][w]; }
-      __syncthreads();
-      const unsigned long long vary = kor ^ kand;
-      if (vary) {
-        const int lb = __ffsll((long long)vary) - 1;
-        const int hb = bitlen64(vary);
-        const int passes = (hb - lb + 7) >> 3;
-        for (int ps = 0; ps < passes; ++ps) {
-          const int sh = lb + 8 * ps;
-          // global digit histogram -> running bin bases (dcount)
-          for (int i = threadIdx.x; i < 256; i += THREADS) dcount[i] = 0;
-          __syncthreads();
-          for (long long i = threadIdx.x; i < n; i += THREADS)
-            atomicAdd(&dcount[((unsigned long long)(src[i].s - lo) >> sh) & 255ull], 1u);
-          __syncthreads();
-          {
-            long long v[1] = {threadIdx.x < 256 ? (long long)dcount[threadIdx.x] : 0}, ex[1], all[1];
-            block_excl_scan<THREADS, 1, OpSum>(v, ex, all, 0, lds_scan);
-            if (threadIdx.x < 256) dcount[threadIdx.x] = (unsigned int)ex[0];
-          }
-          __syncthreads();
-          for (long long t0 = 0; t0 < n; t0 += CAP) {
-            const int cnt = (int)min((long long)CAP, n - t0);
-            for (int i = threadIdx.x; i < cnt; i += THREADS) E[i] = src[t0 + i];
-            __syncthreads();
-            radix_pass<THREADS, MAXR>(E, nullptr, ordA, cnt, lo, sh, whist, dstart, lds_scan);
-            for (int q = threadIdx.x; q < cnt; q += THREADS) {
-              const unsigned short i = ordA[q];
-              const unsigned int d = (unsigned int)(((unsigned long long)(E[i].s - lo) >> sh) & 255ull);
-              dst[dcount[d] + (q - dstart[d])] = E[i];
-            }
-            __syncthreads();
-            // advance the bin bases by this tile's digit counts
-            if (threadIdx.x < 256) {
-              const unsigned int d = threadIdx.x;
-              const unsigned int next = d < 255 ? dstart[d + 1] : (unsigned int)cnt;
-              dcount[d] += next - dstart[d];
-            }
-            __syncthreads();
-          }
-          Elem* t = src;
-          src = dst;
-          dst = t;
-        }
-      }
+      const Elem* src = sort_global<THREADS, CAP>(sm, p.elems + off, p.elems2 + off, n, lo);
       for (long long t0 = 0; t0 < n; t0 += CAP) {
         const int cnt = (int)min((long long)CAP, n - t0);
-        for (int i = threadIdx.x; i < cnt; i += THREADS) E[i] = src[t0 + i];
+        for (int i = threadIdx.x; i < cnt; i += THREADS) sm.E[i] = src[t0 + i];
         __syncthreads();
-        flatten_tile<THREADS>(E, nullptr, cnt, nlev, off, comp, st, lds_scan, nullptr);
+        flatten_tile<THREADS>(sm.E, nullptr, cnt, nlev, 0, comp, st, sm.lds_scan, nullptr);
         __syncthreads();
       }
     }
@@ -821,6 +435,259 @@ __global__ __launch_bounds__(THREADS) void k_merge(Plan p) {
       p.bsum[gb * 3 + l] = st.P[l];
       p.ncomp[gb * 3 + l] = (unsigned int)st.R[l];
     }
+  }
+  __syncthreads();
+}
+
+// Buckets the wave path handed over (ticket[2] of them in p.queue), taken by
+// persistent workgroups from a shared counter (ticket[1]). Every workgroup
+// exits once the counter passes the queue length.
+template <int THREADS, int CAP>
+__global__ __launch_bounds__(THREADS) void k_merge_block(Plan p) {
+  __shared__ SortSmem<THREADS, CAP> sm;
+  __shared__ int s_seg;
+  __shared__ unsigned int s_idx;
+  const unsigned int qlen = __hip_atomic_load(&p.ticket[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (true) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(&p.ticket[1], 1u);
+    __syncthreads();
+    const unsigned int idx = s_idx;
+    __syncthreads();
+    if (idx >= qlen) break;
+    merge_bucket_block<THREADS, CAP>(p, (long long)p.queue[idx], sm, &s_seg);
+  }
+}
+
+// Wave path: each wave flattens one bucket of at most kWaveCap records whose
+// time width fits 32 bits, with no workgroup barrier. The sort is a counting
+// sort on the top bits of the start offset into 1024 sub-bins followed by an
+// insertion sort inside each sub-bin (records with equal starts may end in
+// any order: the flattened result does not depend on it). Buckets that do not
+// fit, or whose sub-bins are too crowded, go to the block path's queue.
+struct WaveSmem {
+  unsigned int key[kWaveCap];
+  long long eslot[kWaveCap];
+  unsigned short ord[kWaveCap];
+  unsigned int bins[kWaveBins / 2];  // two 16-bit counters per word
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int K, class Op>
+__device__ __forceinline__ void wave_excl_scan(const long long (&v)[K], long long (&ex)[K], long long (&tot)[K],
+                                               long long ident) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    long long x = v[k];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const long long y = __shfl_up(x, d, 64);
+      if (lane >= d) x = Op::apply(x, y);
+    }
+    long long e = __shfl_up(x, 1, 64);
+    if (lane == 0) e = ident;
+    ex[k] = e;
+    tot[k] = __shfl(x, 63, 64);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
+  __shared__ WaveSmem wsm[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long gb = (long long)blockIdx.x * 4 + wave;
+  if (gb >= p.n_buckets) return;
+  WaveSmem& W = wsm[wave];
+  const int seg = upper_index_seg(p.segs, p.n_segs, gb);
+  const SegDesc sd = p.segs[seg];
+  const Geom g = seg_geom(p.stats[seg], sd);
+  const long long n = p.counts[gb];
+  const long long off = (long long)p.offsets[gb];
+  const int nlev = sd.n_levels;
+  if (n == 0) {
+    if (lane < 3) {
+      p.bsum[gb * 3 + lane] = 0;
+      p.ncomp[gb * 3 + lane] = 0;
+    }
+    return;
+  }
+  if (n > kWaveCap || g.shift > 32) {
+    if (lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
+    return;
+  }
+  const int ni = (int)n;
+  const long long lo = g.min_s + ((gb - sd.bucket_begin) << g.shift);
+  // load; find the highest varying key bit
+  unsigned int kor = 0;
+  for (int i = lane; i < ni; i += 64) {
+    const Elem el = p.elems[off + i];
+    const unsigned int k = (unsigned int)(el.s - lo);
+    W.key[i] = k;
+    W.eslot[i] = el.e_slot;
+    kor |= k;
+  }
+  for (int i = lane; i < kWaveBins / 2; i += 64) W.bins[i] = 0;
+  for (int d = 32; d >= 1; d >>= 1) kor |= __shfl_xor(kor, d, 64);
+  wave_sync();
+  const int hb = kor ? 32 - __clz((int)kor) : 0;
+  const int dsh = hb > 10 ? hb - 10 : 0;  // digit = key >> dsh, at most 1024 values
+  constexpr int RPL = kWaveCap / 64;
+  unsigned int rank[RPL], dig[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = r * 64 + lane;
+    rank[r] = 0;
+    dig[r] = 0;
+    if (i < ni) {
+      const unsigned int d = W.key[i] >> dsh;
+      const unsigned int sh = 16u * (d & 1u);
+      rank[r] = (atomicAdd(&W.bins[d >> 1], 1u << sh) >> sh) & 0xFFFFu;
+      dig[r] = d;
+    }
+  }
+  wave_sync();
+  // exclusive scan of the 1024 counters: lane owns bins 16*lane .. 16*lane+15
+  unsigned int cnt[16];
+  long long tot = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const unsigned int w = W.bins[lane * 8 + j];
+    cnt[2 * j] = w & 0xFFFFu;
+    cnt[2 * j + 1] = w >> 16;
+    tot += cnt[2 * j] + cnt[2 * j + 1];
+  }
+  long long v1[1] = {tot}, e1[1], t1[1];
+  wave_excl_scan<1, OpSum>(v1, e1, t1, 0);
+  unsigned int run = (unsigned int)e1[0];
+  unsigned int start[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    start[j] = run;
+    run += cnt[j];
+  }
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) W.bins[lane * 8 + j] = start[2 * j] | (start[2 * j + 1] << 16);
+  wave_sync();
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = r * 64 + lane;
+    if (i < ni) {
+      const unsigned int d = dig[r];
+      const unsigned int st0 = (W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu;
+      W.ord[st0 + rank[r]] = (unsigned short)i;
+    }
+  }
+  wave_sync();
+  // order inside each sub-bin by the full key
+  bool crowded = false;
+  if (dsh > 0) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int c = (int)cnt[j];
+      if (c < 2) continue;
+      if (c > 32) {
+        crowded = true;
+        continue;
+      }
+      unsigned short* o = W.ord + start[j];
+      for (int a = 1; a < c; ++a) {
+        const unsigned short x = o[a];
+        const unsigned int kx = W.key[x];
+        int b = a - 1;
+        while (b >= 0 && W.key[o[b]] > kx) {
+          o[b + 1] = o[b];
+          --b;
+        }
+        o[b + 1] = x;
+      }
+    }
+  }
+  if (__ballot(crowded)) {
+    if (lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
+    return;
+  }
+  wave_sync();
+  // flatten: lane owns sorted positions [q0, q1)
+  const int ipl = (ni + 63) >> 6;
+  const int q0 = min(ni, lane * ipl), q1 = min(ni, q0 + ipl);
+  const long long EMASK = (1ll << kSlotShift) - 1;
+  long long tmax[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
+  for (int q = q0; q < q1; ++q) {
+    const long long es = W.eslot[W.ord[q]];
+    const int slot = (int)((unsigned long long)es >> kSlotShift);
+    const long long e = es & EMASK;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+      if (slot <= l && e > tmax[l]) tmax[l] = e;
+  }
+  long long exm[3], totm[3];
+  wave_excl_scan<3, OpMax>(tmax, exm, totm, LLONG_MIN);
+  long long M[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    const long long c = p.carry[gb * 3 + l];
+    M[l] = exm[l] > c ? exm[l] : c;
+  }
+  long long acc[6] = {0, 0, 0, 0, 0, 0};
+  {
+    long long Mb[3] = {M[0], M[1], M[2]};
+    for (int q = q0; q < q1; ++q) {
+      const int i = W.ord[q];
+      const long long es = W.eslot[i];
+      const int slot = (int)((unsigned long long)es >> kSlotShift);
+      const long long e = es & EMASK;
+      const long long s = lo + (long long)W.key[i];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        if (l < nlev && slot <= l) {
+          const long long b = s > Mb[l] ? s : Mb[l];
+          if (e > b) acc[l] += e - b;
+          if (s > Mb[l]) acc[3 + l] += 1;
+          if (e > Mb[l]) Mb[l] = e;
+        }
+      }
+    }
+  }
+  long long exa[6], tota[6];
+  wave_excl_scan<6, OpSum>(acc, exa, tota, 0);
+  {
+    long long P[3], R[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      P[l] = exa[l];
+      R[l] = exa[3 + l];
+    }
+    for (int q = q0; q < q1; ++q) {
+      const int i = W.ord[q];
+      const long long es = W.eslot[i];
+      const int slot = (int)((unsigned long long)es >> kSlotShift);
+      const long long e = es & EMASK;
+      const long long s = lo + (long long)W.key[i];
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        if (l < nlev && slot <= l) {
+          if (s > M[l]) {
+            Comp c;
+            c.cs = s;
+            c.pl = P[l];
+            p.comp[l][off + R[l]] = c;
+            R[l] += 1;
+          }
+          const long long b = s > M[l] ? s : M[l];
+          if (e > b) P[l] += e - b;
+          if (e > M[l]) M[l] = e;
+        }
+      }
+    }
+  }
+  if (lane < 3) {
+    p.bsum[gb * 3 + lane] = tota[lane];
+    p.ncomp[gb * 3 + lane] = (unsigned int)tota[3 + lane];
   }
 }
 
@@ -862,14 +729,6 @@ __device__ long long measure_before(const Plan& p, int seg, int l, long long t) 
   return base + ck.pl + (ce < t ? ce : t) - ck.cs;
 }
 
-__device__ __forceinline__ double ratio(long long num, long long den, int bit, unsigned int& mask) {
-  if (den == 0) {
-    mask |= 1u << bit;
-    return 1.0;
-  }
-  return (double)num / (double)den;
-}
-
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_region(Plan p, const RegionDesc* regions, Tree* trees,
                                                     long long* times) {
@@ -901,42 +760,8 @@ __global__ __launch_bounds__(THREADS) void k_region(Plan p, const RegionDesc* re
     }
   }
   long long v[9] = {sU, sW, sMPI, sO, sK, sM, mUW, mK, mKM};
-#pragma unroll
-  for (int i = 0; i < 6; ++i) v[i] = wave_red_sum(v[i]);
-#pragma unroll
-  for (int i = 6; i < 9; ++i) v[i] = wave_red_max(v[i]);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-    for (int i = 0; i < 9; ++i) lds[wave * 10 + i] = v[i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < THREADS / 64; ++w) {
-      for (int i = 0; i < 6; ++i) v[i] += lds[w * 10 + i];
-      for (int i = 6; i < 9; ++i) v[i] = lds[w * 10 + i] > v[i] ? lds[w * 10 + i] : v[i];
-    }
-    Tree t;
-    t.E = E;
-    t.n = rd.n_hosts;
-    t.m = rd.n_devices;
-    const long long U = v[0], W = v[1], UW = v[0] + v[1];
-    t.sum[0] = U; t.sum[1] = W; t.sum[2] = v[2]; t.sum[3] = v[3];
-    t.sum[4] = UW; t.sum[5] = v[6];
-    t.sum[6] = v[4]; t.sum[7] = v[5]; t.sum[8] = v[7]; t.sum[9] = v[8];
-    unsigned int mask = 0;
-    const long long n = rd.n_hosts, m = rd.n_devices;
-    t.ratio[0] = ratio(U, n * E, 0, mask);          // eq. 6
-    t.ratio[1] = ratio(UW, n * E, 1, mask);         // eq. 7
-    t.ratio[2] = ratio(UW, n * v[6], 2, mask);      // eq. 4, U+W useful
-    t.ratio[3] = ratio(v[6], E, 3, mask);           // eq. 5, U+W useful
-    t.ratio[4] = ratio(U, UW, 4, mask);             // eq. 8
-    t.ratio[5] = ratio(v[4], m * E, 5, mask);       // eq. 9
-    t.ratio[6] = ratio(v[4], m * v[7], 6, mask);    // eq. 10
-    t.ratio[7] = ratio(v[7], v[8], 7, mask);        // eq. 11
-    t.ratio[8] = ratio(v[8], E, 8, mask);           // eq. 12
-    t.undefined_mask = mask;
-    t.reserved = 0;
-    trees[blockIdx.x] = t;
-  }
+  block_tree<THREADS>(v, lds);
+  if (threadIdx.x == 0) trees[blockIdx.x] = make_tree(E, rd.n_hosts, rd.n_devices, v);
 }
 
 // ----------------------------------------------------------------------------
@@ -991,10 +816,15 @@ hipError_t launch_carry(const Plan& p, hipStream_t st) {
 
 hipError_t launch_merge(const Plan& p, int cap, hipStream_t st) {
   if (p.n_buckets == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_merge_wave, dim3((unsigned)((p.n_buckets + 3) / 4)), dim3(256), 0, st, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // persistent workgroups for the buckets the wave path handed over
+  const unsigned grid = (unsigned)std::min<long long>(p.n_buckets, 1024);
   if (cap == 2048)
-    hipLaunchKernelGGL((k_merge<256, 2048>), dim3((unsigned)p.n_buckets), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_merge_block<256, 2048>), dim3(grid), dim3(256), 0, st, p);
   else
-    hipLaunchKernelGGL((k_merge<256, 4096>), dim3((unsigned)p.n_buckets), dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_merge_block<256, 4096>), dim3(grid), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 

@@ -156,6 +156,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   small += carve_bytes(3 * n_buckets, sizeof(unsigned int));
   small += carve_bytes(3 * n_segs, sizeof(long long));
   small += carve_bytes(1, 8) + carve_bytes(nscan, 8) + carve_bytes(4, 4) + carve_bytes(1, 8);
+  small += carve_bytes(n_buckets, sizeof(unsigned int));
   small += carve_bytes(n_regions, sizeof(RegionDesc)) + carve_bytes(n_regions, sizeof(Tree));
   small += carve_bytes(4 * n_times, sizeof(long long));
   if (!meta.reserve(a, small, false)) {
@@ -187,6 +188,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   p.scan_state = carve<unsigned long long>(cur, nscan);
   p.ticket = carve<unsigned int>(cur, 4);
   p.oversized = carve<unsigned long long>(cur, 1);
+  p.queue = carve<unsigned int>(cur, n_buckets);
   d_regions = carve<RegionDesc>(cur, n_regions);
   d_trees = carve<Tree>(cur, n_regions);
   d_times = carve<long long>(cur, 4 * n_times);
@@ -227,7 +229,7 @@ static hpop_status hip_fail(std::string& err, const char* what, hipError_t e) {
   } while (0)
 
 static void tuned(const hpop_tuning& t, int& target, int& cap, int& tile) {
-  target = t.bucket_target > 0 ? std::min(4096, std::max(16, t.bucket_target)) : 512;
+  target = t.bucket_target > 0 ? std::min(4096, std::max(16, t.bucket_target)) : 256;
   cap = t.bucket_cap == 4096 ? 4096 : 2048;
   tile = t.tile_elems == 2048 || t.tile_elems == 8192 ? t.tile_elems : 4096;
 }

@@ -103,6 +103,23 @@ def test_oversized_bucket_slow_path():
         hp.hpop_session_destroy(s_)
 
 
+def test_crowded_sub_bins_fall_back_to_block_path():
+    """A bucket small enough for one wave but with hundreds of starts packed in
+    one sub-bin of the wave path's counting sort."""
+    rng = np.random.default_rng(9)
+    spread = rng.integers(0, 1 << 22, size=150)
+    packed = 5000 + rng.integers(0, 60, size=250)
+    s = np.concatenate([spread, packed]).astype(np.int64)
+    e = s + rng.integers(1, 900, size=s.size)
+    k = rng.random(s.size) < 0.4
+    chunks = [tg.Chunk(0, tg.DEV_KERNEL, s[~k], e[~k]), tg.Chunk(0, tg.DEV_MEMOP, s[k], e[k]),
+              tg.Chunk(1, tg.HOST_USEFUL, s[:200], e[:200]), tg.Chunk(1, tg.HOST_MPI, s[200:], e[200:] + 7)]
+    tr = tg.Trace(0, 1, chunks[:2], [(0, 1 << 23), (5000, 5030), (4000, 6000)])
+    check(tr)
+    tr2 = tg.Trace(1, 0, [tg.Chunk(0, c.kind, c.start, c.end) for c in chunks[2:]], tr.regions)
+    check(tr2)
+
+
 def test_identical_starts_and_degenerate_intervals():
     n = 5000
     s = np.full(n, 7_000_000, np.int64)

@@ -1,0 +1,185 @@
+"""Serving runtime on the GPU: every query's trees equal the oracle on the
+records its session had received up to and including that query, whether the
+query ran alone or batched with queries of other sessions."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2603_26576_amd as hp
+import tracegen as tg
+from engine_util import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    hp.lib()
+
+
+def make_queries(seed, n_sessions, ranks, n_queries, mean_events=3000, p_early=0.3):
+    """Per session: a list of (chunks, t0, t1) continuing its own timeline."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_sessions):
+        origin = tg.T0 + s * 10 ** 12
+        frontier = origin
+        prev_close = origin
+        qs = []
+        for q in range(n_queries):
+            n_ev = int(rng.integers(mean_events // 4, mean_events * 2))
+            chunks = tg.continue_trace(rng, ranks, ranks, 3, n_ev, frontier, p_early=p_early, early_back=300_000)
+            hi = max(int(c.end.max()) for c in chunks)
+            frontier = max(frontier, hi)
+            qs.append((chunks, prev_close, frontier))
+            prev_close = frontier
+        out.append((origin, qs))
+    return out
+
+
+def expected(ranks, origin, qs, upto):
+    chunks = [c for q in qs[:upto + 1] for c in q[0]]
+    t0, t1 = qs[upto][1], qs[upto][2]
+    frontier = max(int(c.end.max()) for c in chunks)
+    tr = tg.Trace(ranks, ranks, chunks, [(t0, t1), (origin, frontier)])
+    return oracle.compute(tr)
+
+
+def as_payload(chunks, device):
+    out = []
+    for c in chunks:
+        if device:
+            import torch
+            out.append((c.resource, c.kind, torch.from_numpy(c.start).cuda(), torch.from_numpy(c.end).cuda()))
+        else:
+            out.append((c.resource, c.kind, c.start, c.end))
+    return out
+
+
+def check_tree(tree, want, g, what):
+    np.testing.assert_array_equal(hp.tree_sums(tree), want["sums"][g], err_msg=what)
+    np.testing.assert_array_equal(hp.tree_ratios(tree).view(np.int64), want["ratios"][g].view(np.int64), err_msg=what)
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_mixed_equals_alone_equals_oracle(device):
+    import torch
+    ranks, n_sessions, n_queries = 3, 4, 6
+    plan = make_queries(11 + device, n_sessions, ranks, n_queries)
+    # in the mix: all queries submitted up front, interleaved across sessions
+    srv = hp.hpop_server_create(max_sessions=8, max_inflight=8)
+    keep = []
+    try:
+        sids = [hp.hpop_server_open_session(srv, ranks, ranks, origin) for origin, _ in plan]
+        torch.cuda.synchronize()
+        tickets = {}
+        for q in range(n_queries):
+            for s in range(n_sessions):
+                chunks, t0, t1 = plan[s][1][q]
+                payload = as_payload(chunks, device)
+                keep.append(payload)
+                if device:
+                    torch.cuda.synchronize()
+                tickets[(s, q)] = hp.hpop_server_submit(srv, sids[s], payload,
+                                                        hp.HPOP_MEM_DEVICE if device else hp.HPOP_MEM_HOST, t0, t1)
+        mixed = {k: hp.hpop_server_wait(srv, t) for k, t in tickets.items()}
+        stats = hp.hpop_server_get_stats(srv)
+        assert stats.completed == n_sessions * n_queries
+        assert stats.mean_batch > 1.0  # queries of different sessions shared device steps
+    finally:
+        hp.hpop_server_destroy(srv)
+    for (s, q), (reg, glob) in mixed.items():
+        origin, qs = plan[s]
+        want = expected(ranks, origin, qs, q)
+        check_tree(reg, want, 0, "session %d query %d region" % (s, q))
+        check_tree(glob, want, 1, "session %d query %d global" % (s, q))
+    # alone: one session at a time, each query waited for before the next
+    srv = hp.hpop_server_create(max_sessions=8, max_inflight=1)
+    try:
+        for s in range(n_sessions):
+            sid = hp.hpop_server_open_session(srv, ranks, ranks, plan[s][0])
+            for q in range(n_queries):
+                chunks, t0, t1 = plan[s][1][q]
+                payload = as_payload(chunks, device)
+                if device:
+                    torch.cuda.synchronize()
+                t = hp.hpop_server_submit(srv, sid, payload, hp.HPOP_MEM_DEVICE if device else hp.HPOP_MEM_HOST,
+                                          t0, t1)
+                reg, glob = hp.hpop_server_wait(srv, t)
+                m_reg, m_glob = mixed[(s, q)]
+                np.testing.assert_array_equal(hp.tree_sums(reg), hp.tree_sums(m_reg))
+                np.testing.assert_array_equal(hp.tree_ratios(glob).view(np.int64),
+                                              hp.tree_ratios(m_glob).view(np.int64))
+    finally:
+        hp.hpop_server_destroy(srv)
+
+
+def test_large_batches_take_the_global_sort_path():
+    ranks = 2
+    plan = make_queries(23, 1, ranks, 3, mean_events=40000, p_early=1.0)
+    srv = hp.hpop_server_create(max_sessions=2, max_inflight=4)
+    try:
+        origin, qs = plan[0]
+        sid = hp.hpop_server_open_session(srv, ranks, ranks, origin)
+        for q, (chunks, t0, t1) in enumerate(qs):
+            t = hp.hpop_server_submit(srv, sid, as_payload(chunks, False), hp.HPOP_MEM_HOST, t0, t1)
+            reg, glob = hp.hpop_server_wait(srv, t)
+            want = expected(ranks, origin, qs, q)
+            check_tree(reg, want, 0, "query %d region" % q)
+            check_tree(glob, want, 1, "query %d global" % q)
+    finally:
+        hp.hpop_server_destroy(srv)
+
+
+def test_bad_device_record_rejected_and_state_unchanged():
+    import torch
+    ranks = 2
+    plan = make_queries(31, 1, ranks, 2)
+    srv = hp.hpop_server_create(max_sessions=2, max_inflight=4)
+    try:
+        origin, qs = plan[0]
+        sid = hp.hpop_server_open_session(srv, ranks, ranks, origin)
+        chunks, t0, t1 = qs[0]
+        t = hp.hpop_server_submit(srv, sid, as_payload(chunks, False), hp.HPOP_MEM_HOST, t0, t1)
+        hp.hpop_server_wait(srv, t)
+        bad_s = torch.tensor([origin + 5, origin + 9], dtype=torch.int64, device="cuda")
+        bad_e = torch.tensor([origin + 6, origin + 1], dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        t = hp.hpop_server_submit(srv, sid, [(ranks, hp.HPOP_DEV_KERNEL, bad_s, bad_e)], hp.HPOP_MEM_DEVICE,
+                                  t0, t1)
+        with pytest.raises(hp.HpopError) as ei:
+            hp.hpop_server_wait(srv, t)
+        assert ei.value.status == hp.HPOP_E_BAD_INTERVAL
+        chunks, t0, t1 = qs[1]
+        t = hp.hpop_server_submit(srv, sid, as_payload(chunks, False), hp.HPOP_MEM_HOST, t0, t1)
+        reg, glob = hp.hpop_server_wait(srv, t)
+        want = expected(ranks, origin, qs, 1)
+        check_tree(reg, want, 0, "after rejected query")
+        check_tree(glob, want, 1, "after rejected query")
+    finally:
+        hp.hpop_server_destroy(srv)
+
+
+def test_backpressure_busy():
+    srv = hp.hpop_server_create(max_sessions=1, max_inflight=1, queue_capacity=1, mem_budget_bytes=1 << 20)
+    try:
+        sid = hp.hpop_server_open_session(srv, 1, 1, 0)
+        s = np.arange(0, 200000, 10, dtype=np.int64)
+        e = s + 5
+        got_busy = False
+        tickets = []
+        for i in range(50):
+            try:
+                tickets.append(hp.hpop_server_submit(srv, sid, [(1, hp.HPOP_DEV_KERNEL, s + i * 10 ** 7,
+                                                                 e + i * 10 ** 7)], hp.HPOP_MEM_HOST,
+                                                     i * 10 ** 7, (i + 1) * 10 ** 7))
+            except hp.HpopError as err:
+                assert err.status == hp.HPOP_E_BUSY
+                got_busy = True
+        assert got_busy
+        for t in tickets:
+            hp.hpop_server_wait(srv, t)
+    finally:
+        hp.hpop_server_destroy(srv)
