@@ -83,6 +83,28 @@ def upload_session(hp, trace):
     return s
 
 
+def save_trace_cache(path, trace):
+    arrs = {"meta": np.array([trace.n_hosts, trace.n_devices, len(trace.chunks)], np.int64),
+            "regions": np.array(trace.regions, np.int64),
+            "info": np.array([trace.info["t0"], trace.info["t_end"]], np.int64),
+            "ovf": np.array([trace.info["overlap_fraction"]])}
+    for i, c in enumerate(trace.chunks):
+        arrs["c%d" % i] = np.array([c.resource, c.kind], np.int64)
+        arrs["s%d" % i] = c.start
+        arrs["e%d" % i] = c.end
+    np.savez(path, **arrs)
+
+
+def load_trace_cache(path, tg):
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    n, m, nc = (int(x) for x in z["meta"])
+    chunks = [tg.Chunk(int(z["c%d" % i][0]), int(z["c%d" % i][1]), z["s%d" % i], z["e%d" % i]) for i in range(nc)]
+    info = {"t0": int(z["info"][0]), "t_end": int(z["info"][1]), "overlap_fraction": float(z["ovf"][0]), "streams": 4}
+    return tg.Trace(n, m, chunks, [tuple(int(v) for v in r) for r in z["regions"]], info)
+
+
 def bench_single(hp, trace, steps, warmup, workload):
     import torch
     s = upload_session(hp, trace)
@@ -128,11 +150,14 @@ def bench_single(hp, trace, steps, warmup, workload):
             "oversized_buckets": int(info.n_oversized), "trees": trees}
 
 
-def bench_batched(hp, traces, steps, warmup):
+def bench_batched(hp, traces, steps, warmup, tune_cache=None):
     import torch
     sessions = [upload_session(hp, tr) for tr in traces]
     try:
         n_events = sum(tr.n_events for tr in traces)
+        t = time.time()
+        hp.hpop_autotune(sessions, tune_cache)  # picks bucket size, on-chip capacity, tile; cached per size class
+        log("autotune: %.1f s" % (time.time() - t))
         for _ in range(max(1, warmup)):
             hp.hpop_batch_compute(sessions, hp.HPOP_FORCE_REBUILD)
         torch.cuda.synchronize()
@@ -149,6 +174,139 @@ def bench_batched(hp, traces, steps, warmup):
     return {"traces": len(traces), "events": n_events, "segments": segs, "ms_per_step": round(dt * 1e3, 3),
             "events_per_s": n_events / dt,
             "tuning": {"bucket_target": tun.bucket_target, "bucket_cap": tun.bucket_cap, "tile_elems": tun.tile_elems}}
+
+
+def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, streams=4, warm=1_000_000):
+    """Poisson region-close queries against device-resident sessions.
+
+    Each session's record stream is generated once and uploaded to the GPU;
+    its first `warm` records are applied untimed, then every query takes the
+    next slice of its session's stream (log-uniform 10^4-10^6 records, spread
+    over all resources in proportion) and closes the region
+    [previous close, new frontier). Payloads are device-resident, so latency
+    and throughput measure the serving runtime and kernels, not PCIe.
+    """
+    import ctypes
+    import threading
+    import torch
+    import tracegen as tg
+    rng = np.random.default_rng(seed)
+    total_q = n_queries * len(lambdas)
+    sizes = np.rint(10 ** rng.uniform(4, 6, size=n_queries)).astype(np.int64)
+    owner = rng.integers(0, n_sessions, size=n_queries)
+    kids = np.random.SeedSequence(seed).spawn(n_sessions)
+    sess = []
+    for i in range(n_sessions):
+        need = warm + int(sizes[owner == i].sum())
+        per_res = max(4, need // (2 * ranks))
+        tr = tg.make_trace(0, ranks, ranks, streams, (8 * per_res) // 5, (2 * per_res) // 5 + 3,
+                           w_range=(0.8, 1.2), seed_seq=kids[i])
+        chunks = []
+        for c in tr.chunks:
+            chunks.append((c.resource, c.kind, torch.from_numpy(c.start).cuda(), torch.from_numpy(c.end).cuda(),
+                           np.maximum.accumulate(c.end)))
+        sess.append({"origin": tr.info["t0"], "chunks": chunks, "total": tr.n_events})
+    torch.cuda.synchronize()
+
+    def slices(sidx, n_rec, cursor):
+        """hpop_event_chunk array for the next n_rec records of a session, and the new frontier."""
+        S = sess[sidx]
+        arr = (hp.hpop_event_chunk * len(S["chunks"]))()
+        frontier = S["origin"]
+        k = 0
+        for j, (r, kind, st, en, pmax) in enumerate(S["chunks"]):
+            ln = st.numel()
+            a = cursor[j]
+            b = min(ln, a + max(1, int(round(n_rec * ln / S["total"]))))
+            if b > a:
+                arr[k] = hp.hpop_event_chunk(r, kind, st.data_ptr() + 8 * a, en.data_ptr() + 8 * a, b - a)
+                k += 1
+                frontier = max(frontier, int(pmax[b - 1]))
+            cursor[j] = b
+        return arr, k, frontier
+
+    lib = hp.lib()
+    results = []
+    for lam in lambdas:
+        srv = hp.hpop_server_create(max_sessions=n_sessions, max_inflight=n_sessions, queue_capacity=1 << 16,
+                                    mem_budget_bytes=64 << 30)
+        try:
+            sids = [hp.hpop_server_open_session(srv, ranks, ranks, S["origin"]) for S in sess]
+            cursors = [[0] * len(S["chunks"]) for S in sess]
+            closes = [S["origin"] for S in sess]
+            warm_t = []
+            for i in range(n_sessions):
+                arr, k, fr = slices(i, warm, cursors[i])
+                tk = ctypes.c_uint64()
+                rc = lib.hpop_server_submit(srv, sids[i], arr, k, hp.HPOP_MEM_DEVICE, closes[i], max(fr, closes[i] + 1),
+                                            ctypes.byref(tk))
+                assert rc == 0, rc
+                warm_t.append(tk.value)
+                closes[i] = max(fr, closes[i] + 1)
+            for t in warm_t:
+                hp.hpop_server_wait(srv, t)
+            base = hp.hpop_server_get_stats(srv)
+            plan = []
+            for q in range(n_queries):
+                i = int(owner[q])
+                arr, k, fr = slices(i, int(sizes[q]), cursors[i])
+                t1 = max(fr, closes[i] + 1)
+                plan.append((sids[i], arr, k, closes[i], t1, int(sizes[q])))
+                closes[i] = t1
+            arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_queries))
+            tickets = []
+            done = []
+
+            lat = []
+
+            def waiter():
+                for t, t_sub in iter(tickets_q.get, None):
+                    hp.hpop_server_wait(srv, t)
+                    now = time.perf_counter()
+                    done.append(now)
+                    lat.append(now - t_sub)
+
+            import queue as _q
+            tickets_q = _q.Queue()
+            th = threading.Thread(target=waiter)
+            th.start()
+            t_start = time.perf_counter()
+            busy = 0
+            for q, (sid, arr, k, a, b, n_rec) in enumerate(plan):
+                while time.perf_counter() - t_start < arrivals[q]:
+                    pass
+                tk = ctypes.c_uint64()
+                while True:
+                    rc = lib.hpop_server_submit(srv, sid, arr, k, hp.HPOP_MEM_DEVICE, a, b, ctypes.byref(tk))
+                    if rc != hp.HPOP_E_BUSY:
+                        break
+                    busy += 1
+                assert rc == 0, rc
+                tickets_q.put((tk.value, t_start + arrivals[q]))
+            tickets_q.put(None)
+            th.join()
+            t_end = max(done)
+            st = hp.hpop_server_get_stats(srv)
+        finally:
+            hp.hpop_server_destroy(srv)
+        ev = int(sizes.sum())
+        lat_us = np.sort(np.array(lat)) * 1e6
+        steps_run = max(1, st.device_steps - base.device_steps)
+        results.append({"lambda_req_s": lam, "queries": n_queries, "events": ev,
+                        "offered_events_per_s": ev / float(arrivals[-1]),
+                        "events_per_s": ev / (t_end - t_start),
+                        "achieved_req_s": n_queries / (t_end - t_start),
+                        "p50_us": round(float(np.percentile(lat_us, 50)), 1),
+                        "p99_us": round(float(np.percentile(lat_us, 99)), 1),
+                        "max_us": round(float(lat_us[-1]), 1),
+                        "mean_batch": round((st.mean_batch * st.device_steps - base.mean_batch * base.device_steps)
+                                            / steps_run, 2),
+                        "busy_retries": busy})
+        log("serving lambda=%d: %s" % (lam, results[-1]))
+    return {"sessions": n_sessions, "ranks": ranks, "devices": ranks, "streams": streams,
+            "warm_events_per_session": warm, "payload": "device-resident",
+            "latency": "scheduled arrival to trees on the host",
+            "runs": results}
 
 
 def cpu_baseline(trace, target_s=12.0):
@@ -184,6 +342,60 @@ def cpu_baseline(trace, target_s=12.0):
                       % (sub.n_hosts, sub.n_devices, sub.n_events, len(trace.regions), dt)}
 
 
+CALIB_BYTES = 1 << 30  # plain copy of 1 GiB: reads 1 GiB, writes 1 GiB
+
+
+def calibrate_copy(reps=5):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    a = torch.ones(CALIB_BYTES // 8, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": CALIB_BYTES, "reps": reps}))
+
+
+def _pmc_rows(path, counter):
+    """(kernel name, value) per dispatch from a rocprofv3 counter_collection.csv."""
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                rows.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    return rows
+
+
+def import_traffic(kernel, workload, fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out_dir):
+    """HBM bytes per launch of `kernel` from two counter runs, each scaled by the
+    same counter's reading for the calibration copy (FETCH_SIZE and WRITE_SIZE
+    are in KiB per dispatch)."""
+    def mean_for(rows, name):
+        v = [x for k, x in rows if name in k]
+        return sum(v) / len(v) if v else None
+    cal_f = max((x for k, x in _pmc_rows(cal_fetch_csv, "FETCH_SIZE") if "copy" in k.lower() or "elementwise" in k.lower()),
+                default=None)
+    cal_w = max((x for k, x in _pmc_rows(cal_write_csv, "WRITE_SIZE") if "copy" in k.lower() or "elementwise" in k.lower()),
+                default=None)
+    f = mean_for(_pmc_rows(fetch_csv, "FETCH_SIZE"), kernel)
+    w = mean_for(_pmc_rows(write_csv, "WRITE_SIZE"), kernel)
+    if None in (cal_f, cal_w, f, w):
+        raise SystemExit("missing counter rows (%s %s %s %s)" % (cal_f, cal_w, f, w))
+    sf = (CALIB_BYTES / 1024.0) / cal_f
+    sw = (CALIB_BYTES / 1024.0) / cal_w
+    rec = {"kernel": kernel, "workload": workload, "source_hash": kernel_source_hash(),
+           "fetch_kib_per_launch": f, "write_kib_per_launch": w,
+           "calibration_fetch_kib": cal_f, "calibration_write_kib": cal_w,
+           "fetch_scale": sf, "write_scale": sw,
+           "bytes_per_launch": int(f * 1024 * sf + w * 1024 * sw)}
+    path = os.path.join(out_dir, "traffic_%s_%s.json" % (kernel.replace("k_", ""), workload))
+    with open(path, "w") as fo:
+        json.dump(rec, fo, indent=1)
+    print(path, rec)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,8 +406,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-traces", type=int, default=1000)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-queries", type=int, default=400)
+    ap.add_argument("--serving-lambdas", default="2000,10000")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON)")
+    ap.add_argument("--trace-cache", default=None, help="npz file to reuse the generated workload")
+    ap.add_argument("--calibrate-copy", action="store_true", help="only run the plain copy used to scale counters")
+    ap.add_argument("--import-traffic", nargs=6, metavar=("KERNEL", "WORKLOAD", "FETCH_CSV", "WRITE_CSV",
+                                                          "CAL_FETCH_CSV", "CAL_WRITE_CSV"))
     args = ap.parse_args()
+    if args.import_traffic:
+        import_traffic(*args.import_traffic, out_dir=os.path.join(ROOT, "profiles"))
+        return
     if args.gpus != 1:
         print("this engine runs on one GPU; the per-resource sharding across GPUs is a design note only "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
@@ -203,13 +426,20 @@ def main():
     import torch
     import paper_2603_26576_amd as hp
     import tracegen as tg
-    hp.lib()
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    hp.lib()
 
     log("generating workload %s (scale %g)" % (args.workload, args.scale))
     t = time.time()
     if args.workload == "large":
-        trace = tg.large(scale=args.scale)
+        trace = load_trace_cache(args.trace_cache, tg) if args.trace_cache else None
+        if trace is None:
+            trace = tg.large(scale=args.scale)
+            if args.trace_cache:
+                save_trace_cache(args.trace_cache, trace)
         cfg = {"workload": "large imbalance sweep", "ranks": 256, "devices": 256, "streams": 4, "regions": 64,
                "device_events": 10 ** 8, "host_events": 25 * 10 ** 6}
     elif args.workload == "mid":
@@ -243,8 +473,12 @@ def main():
         t = time.time()
         traces = tg.batched(n_traces=args.batched_traces)
         log("generated %d records in %.1f s" % (sum(x.n_events for x in traces), time.time() - t))
-        out["batched"] = bench_batched(hp, traces, max(3, args.steps // 2), 1)
+        out["batched"] = bench_batched(hp, traces, max(3, args.steps // 2), 1, args.tune_cache)
         log("batched: %s" % out["batched"])
+    if not args.no_serving and args.serving_queries > 0:
+        lams = [int(x) for x in args.serving_lambdas.split(",") if x]
+        log("serving leg: lambdas %s, %d queries each" % (lams, args.serving_queries))
+        out["serving"] = serving_leg(hp, lams, args.serving_queries)
     line = json.dumps(out)
     print(line, flush=True)
     if args.json_out:

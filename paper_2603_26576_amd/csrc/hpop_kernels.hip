@@ -145,8 +145,17 @@ __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   const bool windowed = bmax - bmin < kHistWin;
   if (windowed) {
 #pragma unroll
-    for (int k = 0; k < IPT; ++k)
-      if (bk[k] >= 0) atomicAdd(&hist[bk[k] - bmin], 1u);
+    for (int k = 0; k < IPT; ++k) {
+      // one LDS atomic per distinct bucket of the wave, not one per record
+      unsigned long long todo = __ballot(bk[k] >= 0);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lb = __shfl(bk[k], leader, 64);
+        const unsigned long long m = __ballot(bk[k] == lb);
+        if (lane == leader) atomicAdd(&hist[lb - bmin], (unsigned int)__popcll(m));
+        todo &= ~m;
+      }
+    }
     __syncthreads();
     for (int i = threadIdx.x; i <= bmax - bmin; i += THREADS)
       if (hist[i]) atomicAdd(&p.counts[sd.bucket_begin + bmin + i], hist[i]);
@@ -265,12 +274,27 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   unsigned long long* gmax = p.maxend;
   if (bmax - bmin < kHistWin) {
     unsigned int rk[IPT];
+    const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
+      // lanes of one bucket share one LDS atomic: the leader reserves their
+      // ranks and folds their largest end in
       rk[k] = 0;
-      if (bk[k] >= 0) {
-        rk[k] = atomicAdd(&hist[bk[k] - bmin], 1u);
-        atomicMax(&bmaxe[bk[k] - bmin], (unsigned long long)ev[k]);
+      unsigned long long todo = __ballot(bk[k] >= 0);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lb = __shfl(bk[k], leader, 64);
+        const bool in = bk[k] == lb;
+        const unsigned long long m = __ballot(in);
+        const unsigned long long emax = wave_red_maxu(in ? (unsigned long long)ev[k] : 0ull);
+        unsigned int b = 0;
+        if (lane == leader) {
+          b = atomicAdd(&hist[lb - bmin], (unsigned int)__popcll(m));
+          atomicMax(&bmaxe[lb - bmin], emax);
+        }
+        b = __shfl(b, leader, 64);
+        if (in) rk[k] = b + (unsigned int)__popcll(m & lt);
+        todo &= ~m;
       }
     }
     __syncthreads();

@@ -74,15 +74,15 @@ def test_mixed_equals_alone_equals_oracle(device):
     try:
         sids = [hp.hpop_server_open_session(srv, ranks, ranks, origin) for origin, _ in plan]
         torch.cuda.synchronize()
+        payloads = {(s, q): as_payload(plan[s][1][q][0], device) for q in range(n_queries)
+                    for s in range(n_sessions)}
+        keep.append(payloads)
+        torch.cuda.synchronize()
         tickets = {}
         for q in range(n_queries):
             for s in range(n_sessions):
                 chunks, t0, t1 = plan[s][1][q]
-                payload = as_payload(chunks, device)
-                keep.append(payload)
-                if device:
-                    torch.cuda.synchronize()
-                tickets[(s, q)] = hp.hpop_server_submit(srv, sids[s], payload,
+                tickets[(s, q)] = hp.hpop_server_submit(srv, sids[s], payloads[(s, q)],
                                                         hp.HPOP_MEM_DEVICE if device else hp.HPOP_MEM_HOST, t0, t1)
         mixed = {k: hp.hpop_server_wait(srv, t) for k, t in tickets.items()}
         stats = hp.hpop_server_get_stats(srv)
