@@ -67,7 +67,7 @@ class hpop_event_chunk(ctypes.Structure):
 
 class hpop_tuning(ctypes.Structure):
     _fields_ = [("bucket_target", ctypes.c_int32), ("bucket_cap", ctypes.c_int32),
-                ("tile_elems", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile_elems", ctypes.c_int32), ("scatter_slots", ctypes.c_int32)]
 
 
 class hpop_session_info(ctypes.Structure):
@@ -266,8 +266,8 @@ def hpop_session_get_info(s):
     return out
 
 
-def hpop_session_set_tuning(s, bucket_target=0, bucket_cap=0, tile_elems=0):
-    t = hpop_tuning(bucket_target, bucket_cap, tile_elems, 0)
+def hpop_session_set_tuning(s, bucket_target=0, bucket_cap=0, tile_elems=0, scatter_slots=0):
+    t = hpop_tuning(bucket_target, bucket_cap, tile_elems, scatter_slots)
     _check(lib().hpop_session_set_tuning(s, ctypes.byref(t)), s)
 
 

@@ -14,10 +14,12 @@
 // priority Useful > Offloading > MPI).
 //
 // Pipeline (one pass over the records per arrow):
-//   records --stats--> per-segment min start / max start / max end, validation
-//           --hist---> per-bucket record counts (bucket = start >> shift)
-//           --scan---> bucket offsets
-//           --scatter-> records regrouped by bucket (16 B each) + per-bucket max end
+//   records --stats--> per-segment min / max start
+//           --scatter-> validated records regrouped by bucket (16 B each, bucket
+//                       = (start - min) >> shift) + per-bucket max end; by default
+//                       into fixed slots per bucket, else after an exact
+//                       --hist--> count and --scan--> offset pass
+//           --scan---> bucket offsets of the merged intervals
 //   carry  : per-bucket running max end of all earlier buckets (per level)
 //   merge  : per bucket, sort by start in LDS, then a block-wide max-scan of
 //            ends with the carry finds merge breaks; each break starts a
@@ -95,6 +97,8 @@ struct Plan {
   int64_t n_tiles;
   int32_t tile_elems;
   int32_t cap;                       // records a bucket may hold for the LDS sort
+  int32_t slot_cap;                  // >0: single-pass scatter into fixed slots of this many records per bucket
+  int32_t pad1;
   const SegDesc* segs;
   SegStats* stats;
   int64_t n_buckets;
@@ -115,7 +119,7 @@ struct Plan {
   unsigned long long* scan_state;    // decoupled look-back words of the bucket scan
   unsigned int* ticket;              // [4]: scan ticket, block-path take counter, block-path queue length
   unsigned int* queue;               // [n_buckets] buckets handed to the block path
-  unsigned long long* oversized;     // [0] buckets above the on-chip capacity
+  unsigned long long* oversized;     // [0] buckets above the on-chip capacity, [1] buckets above slot_cap
 };
 
 }  // namespace hpop

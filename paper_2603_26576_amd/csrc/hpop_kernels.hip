@@ -29,13 +29,17 @@ __global__ void k_reset(Plan p) {
     p.stats[i].max_e = 0;
     p.stats[i].pad = 0;
   }
-  for (long long i = tid; i < p.n_buckets; i += stride) p.counts[i] = 0;
+  for (long long i = tid; i < p.n_buckets; i += stride) {
+    p.counts[i] = 0;
+    p.cursor[i] = 0;
+  }
   for (long long i = tid; i < 3 * p.n_buckets; i += stride) p.maxend[i] = 0;
   const long long nscan = (p.n_buckets + kScanTile - 1) / kScanTile + 1;
   for (long long i = tid; i < nscan; i += stride) p.scan_state[i] = 0;
   if (tid == 0) {
     p.err[0] = ULLONG_MAX;
     p.oversized[0] = 0;
+    p.oversized[1] = 0;
   }
   if (tid < 4) p.ticket[tid] = 0;
 }
@@ -46,51 +50,43 @@ __global__ void k_reset(Plan p) {
 
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
+  // The bucket grid needs only the range of starts; validation happens in the
+  // scatter, which reads both ends anyway. Starts outside [0, 2^62) belong to
+  // invalid records and are left out of the range.
   constexpr int NW = THREADS / 64;
   __shared__ int s_chunk;
-  __shared__ unsigned long long red[4][NW];
+  __shared__ unsigned long long red[2][NW];
   const long long tile = blockIdx.x;
   if (threadIdx.x == 0) s_chunk = upper_index_chunk(p.chunks, p.n_chunks, tile);
   __syncthreads();
   const ChunkDesc cd = p.chunks[s_chunk];
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
   const long long end = min((long long)cd.count, base + p.tile_elems);
-  unsigned long long mn = ULLONG_MAX, mxs = 0, mxe = 0, bad = ULLONG_MAX;
+  unsigned long long mn = ULLONG_MAX, mxs = 0;
   for (long long i = base + threadIdx.x; i < end; i += THREADS) {
-    const long long s = cd.s[i], e = cd.e[i];
-    if (!rec_valid(s, e)) {
-      bad = (unsigned long long)i < bad ? (unsigned long long)i : bad;
-    } else if (s < e) {
-      mn = (unsigned long long)s < mn ? (unsigned long long)s : mn;
-      mxs = (unsigned long long)s > mxs ? (unsigned long long)s : mxs;
-      mxe = (unsigned long long)e > mxe ? (unsigned long long)e : mxe;
+    const unsigned long long s = (unsigned long long)cd.s[i];
+    if (s < (unsigned long long)kTimeLimit) {
+      mn = s < mn ? s : mn;
+      mxs = s > mxs ? s : mxs;
     }
   }
   mn = wave_red_minu(mn);
   mxs = wave_red_maxu(mxs);
-  mxe = wave_red_maxu(mxe);
-  bad = wave_red_minu(bad);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
     red[0][wave] = mn;
     red[1][wave] = mxs;
-    red[2][wave] = mxe;
-    red[3][wave] = bad;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < NW; ++w) {
       mn = red[0][w] < mn ? red[0][w] : mn;
       mxs = red[1][w] > mxs ? red[1][w] : mxs;
-      mxe = red[2][w] > mxe ? red[2][w] : mxe;
-      bad = red[3][w] < bad ? red[3][w] : bad;
     }
     if (mn != ULLONG_MAX) {
       atomicMin(&p.stats[cd.seg].min_s, mn);
       atomicMax(&p.stats[cd.seg].max_s, mxs);
-      atomicMax(&p.stats[cd.seg].max_e, mxe);
     }
-    if (bad != ULLONG_MAX) atomicMin(p.err, ((unsigned long long)cd.chunk_id << 40) | bad);
   }
 }
 
@@ -179,9 +175,20 @@ __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
   const long long b0 = bid * kScanTile + (long long)threadIdx.x * IPT;
   unsigned int c[IPT];
   long long tsum = 0;
+  const bool slots = p.slot_cap > 0;
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
-    c[k] = (b0 + k < p.n_buckets) ? p.counts[b0 + k] : 0u;
+    c[k] = 0u;
+    if (b0 + k < p.n_buckets) {
+      if (slots) {
+        // counts of the single-pass scatter (capped: an overflow is redone exactly)
+        const unsigned long long cu = p.cursor[b0 + k];
+        c[k] = (unsigned int)(cu < (unsigned long long)p.slot_cap ? cu : (unsigned long long)p.slot_cap);
+        p.counts[b0 + k] = c[k];
+      } else {
+        c[k] = p.counts[b0 + k];
+      }
+    }
     tsum += c[k];
   }
   long long v[1] = {tsum}, ex[1], tot[1];
@@ -215,7 +222,7 @@ __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
   for (int k = 0; k < IPT; ++k) {
     if (b0 + k < p.n_buckets) {
       p.offsets[b0 + k] = run;
-      p.cursor[b0 + k] = run;
+      if (!slots) p.cursor[b0 + k] = run;
       if (c[k] > (unsigned)p.cap) atomicAdd(p.oversized, 1ull);
     }
     run += c[k];
@@ -252,7 +259,10 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
     if (i < end) {
       sv[k] = cd.s[i];
       ev[k] = cd.e[i];
-      if (rec_valid(sv[k], ev[k]) && sv[k] < ev[k]) {
+      if (!rec_valid(sv[k], ev[k])) {
+        // first bad record of the build: chunk << 40 | index (rare path)
+        atomicMin(p.err, ((unsigned long long)cd.chunk_id << 40) | (unsigned long long)i);
+      } else if (sv[k] < ev[k]) {
         bk[k] = bucket_of(sv[k], g);
         bmin = min(bmin, bk[k]);
         bmax = max(bmax, bk[k]);
@@ -264,6 +274,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
     bmax = max(bmax, __shfl_xor(bmax, d, 64));
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long scap = p.slot_cap;
   if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
   for (int i = threadIdx.x; i < kHistWin; i += THREADS) { hist[i] = 0; bmaxe[i] = 0; }
   __syncthreads();
@@ -309,11 +320,17 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
       if (bk[k] >= 0) {
-        const unsigned long long pos = bbase[bk[k] - bmin] + rk[k];
+        const long long pos = (long long)(bbase[bk[k] - bmin] + rk[k]);
         Elem el;
         el.s = sv[k];
         el.e_slot = (long long)((unsigned long long)ev[k] | slotbits);
-        p.elems[pos] = el;
+        if (scap == 0) {
+          p.elems[pos] = el;  // cursors started at the exact offsets
+        } else if (pos < scap) {
+          p.elems[(sd.bucket_begin + bk[k]) * scap + pos] = el;
+        } else {
+          atomicAdd(&p.oversized[1], 1ull);  // slot overflow: the build is redone with exact offsets
+        }
       }
     }
   } else {
@@ -321,12 +338,18 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
     for (int k = 0; k < IPT; ++k) {
       if (bk[k] >= 0) {
         const long long gb = sd.bucket_begin + bk[k];
-        const unsigned long long pos = atomicAdd(&p.cursor[gb], 1ull);
+        const long long pos = (long long)atomicAdd(&p.cursor[gb], 1ull);
         atomicMax(&gmax[gb * 3 + cd.slot], (unsigned long long)ev[k]);
         Elem el;
         el.s = sv[k];
         el.e_slot = (long long)((unsigned long long)ev[k] | slotbits);
-        p.elems[pos] = el;
+        if (scap == 0) {
+          p.elems[pos] = el;
+        } else if (pos < scap) {
+          p.elems[gb * scap + pos] = el;
+        } else {
+          atomicAdd(&p.oversized[1], 1ull);
+        }
       }
     }
   }
@@ -375,6 +398,8 @@ __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
       run[l] = all > run[l] ? all : run[l];
     }
   }
+  // largest end of the segment (level 2 holds every kind); no record: the min start
+  if (lane == 0) p.stats[seg].max_e = (unsigned long long)(run[2] > init ? run[2] : (init + 1 > 0 ? init + 1 : 0));
 }
 
 template <int THREADS>
@@ -436,7 +461,8 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
     const long long lo = g.min_s + (bl << g.shift);
     if (n <= CAP) {
       const int ni = (int)n;
-      for (int i = threadIdx.x; i < ni; i += THREADS) sm.E[i] = p.elems[off + i];  // coalesced 16 B per lane
+      const Elem* rec = p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + off;
+      for (int i = threadIdx.x; i < ni; i += THREADS) sm.E[i] = rec[i];  // coalesced 16 B per lane
       __syncthreads();
       const unsigned short* ord = sort_lds<THREADS, CAP>(sm, ni, lo);
       flatten_tile<THREADS>(sm.E, ord, ni, nlev, 0, comp, st, sm.lds_scan, nullptr);
@@ -547,8 +573,9 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
   const long long lo = g.min_s + ((gb - sd.bucket_begin) << g.shift);
   // load; find the highest varying key bit
   unsigned int kor = 0;
+  const Elem* rec = p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + off;
   for (int i = lane; i < ni; i += 64) {
-    const Elem el = p.elems[off + i];
+    const Elem el = rec[i];
     const unsigned int k = (unsigned int)(el.s - lo);
     W.key[i] = k;
     W.eslot[i] = el.e_slot;
@@ -838,11 +865,14 @@ hipError_t launch_carry(const Plan& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_merge(const Plan& p, int cap, hipStream_t st) {
+hipError_t launch_merge_wave(const Plan& p, hipStream_t st) {
   if (p.n_buckets == 0) return hipSuccess;
   hipLaunchKernelGGL(k_merge_wave, dim3((unsigned)((p.n_buckets + 3) / 4)), dim3(256), 0, st, p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_block(const Plan& p, int cap, hipStream_t st) {
+  if (p.n_buckets == 0) return hipSuccess;
   // persistent workgroups for the buckets the wave path handed over
   const unsigned grid = (unsigned)std::min<long long>(p.n_buckets, 1024);
   if (cap == 2048)

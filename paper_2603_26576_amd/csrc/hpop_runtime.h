@@ -66,7 +66,7 @@ struct Workspace {
   hipGraphExec_t graph_exec = nullptr;
   long long layout_gen = 0;
   hpop_status prepare(Alloc& a, long long n_chunks, long long n_segs, long long n_buckets, long long n_elems,
-                      long long n_regions, long long n_times, std::string& err);
+                      long long n_slots, long long n_regions, long long n_times, std::string& err);
   void release(Alloc& a);
 };
 
@@ -91,9 +91,11 @@ struct Engine {
   int graph_replays = 0;
   long long last_oversized = 0;
   // timing
+  bool exact_forced = false;  // a bucket outgrew its scatter slots: use exact offsets
+  std::vector<unsigned long long> forced_versions;
   std::vector<hipEvent_t> events;
+  std::vector<const char*> mark_names;
   int n_marks = 0;
-  bool marks_build = false;
   std::vector<std::pair<std::string, float>> stage_ms;
 
   hpop_status assemble(hpop_session* const* ss, int k, std::string& err);

@@ -142,7 +142,8 @@ static T* carve(char*& cur, size_t n) {
 static size_t carve_bytes(size_t n, size_t sz) { return (n * sz + 255) & ~size_t(255); }
 
 hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, long long n_buckets,
-                               long long n_elems, long long n_regions, long long n_times, std::string& err) {
+                               long long n_elems, long long n_slots, long long n_regions, long long n_times,
+                               std::string& err) {
   const size_t nscan = (size_t)((n_buckets + kScanTile - 1) / kScanTile + 1);
   size_t small = 0;
   small += carve_bytes(n_chunks, sizeof(ChunkDesc));
@@ -155,7 +156,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   small += carve_bytes(3 * n_buckets, sizeof(long long)) * 3;
   small += carve_bytes(3 * n_buckets, sizeof(unsigned int));
   small += carve_bytes(3 * n_segs, sizeof(long long));
-  small += carve_bytes(1, 8) + carve_bytes(nscan, 8) + carve_bytes(4, 4) + carve_bytes(1, 8);
+  small += carve_bytes(1, 8) + carve_bytes(nscan, 8) + carve_bytes(4, 4) + carve_bytes(2, 8);
   small += carve_bytes(n_buckets, sizeof(unsigned int));
   small += carve_bytes(n_regions, sizeof(RegionDesc)) + carve_bytes(n_regions, sizeof(Tree));
   small += carve_bytes(4 * n_times, sizeof(long long));
@@ -163,9 +164,12 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
     err = "device allocation of " + std::to_string(small) + " bytes (build metadata) failed";
     return HPOP_E_OOM;
   }
-  const size_t big_e = carve_bytes(n_elems, sizeof(Elem));
+  // bucketed records: fixed slots per bucket (n_slots > 0) or exact offsets,
+  // where oversized buckets also need a scratch copy for their global sort
+  const size_t big_e = carve_bytes(n_slots > 0 ? n_slots : n_elems, sizeof(Elem));
+  const size_t big_e2 = carve_bytes(n_slots > 0 ? 1 : n_elems, sizeof(Elem));
   const size_t big_c = carve_bytes(n_elems, sizeof(Comp));
-  if (!elems.reserve(a, big_e, false) || !elems2.reserve(a, big_e, false) || !comp[0].reserve(a, big_c, false) ||
+  if (!elems.reserve(a, big_e, false) || !elems2.reserve(a, big_e2, false) || !comp[0].reserve(a, big_c, false) ||
       !comp[1].reserve(a, big_c, false) || !comp[2].reserve(a, big_c, false)) {
     err = "device allocation for " + std::to_string(n_elems) + " records failed";
     return HPOP_E_OOM;
@@ -187,7 +191,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   p.err = carve<unsigned long long>(cur, 1);
   p.scan_state = carve<unsigned long long>(cur, nscan);
   p.ticket = carve<unsigned int>(cur, 4);
-  p.oversized = carve<unsigned long long>(cur, 1);
+  p.oversized = carve<unsigned long long>(cur, 2);
   p.queue = carve<unsigned int>(cur, n_buckets);
   d_regions = carve<RegionDesc>(cur, n_regions);
   d_trees = carve<Tree>(cur, n_regions);
@@ -228,18 +232,29 @@ static hpop_status hip_fail(std::string& err, const char* what, hipError_t e) {
     if (e_ != hipSuccess) return hip_fail(err, what, e_);    \
   } while (0)
 
-static void tuned(const hpop_tuning& t, int& target, int& cap, int& tile) {
+static int pow2ceil(int x) {
+  int v = 1;
+  while (v < x) v <<= 1;
+  return v;
+}
+
+static void tuned(const hpop_tuning& t, int& target, int& cap, int& tile, int& slots) {
   target = t.bucket_target > 0 ? std::min(4096, std::max(16, t.bucket_target)) : 256;
   cap = t.bucket_cap == 4096 ? 4096 : 2048;
   tile = t.tile_elems == 2048 || t.tile_elems == 8192 ? t.tile_elems : 4096;
+  // single-pass scatter slots: 4x the mean bucket, within the on-chip capacity
+  if (t.scatter_slots < 0) slots = 0;
+  else if (t.scatter_slots > 0) slots = std::min(cap, pow2ceil(std::max(64, t.scatter_slots)));
+  else slots = std::min(cap, pow2ceil(4 * target));
 }
 
 // The k sessions of `ss` become one plan: segments are session by session,
 // hosts before devices; regions likewise.
 hpop_status Engine::assemble(hpop_session* const* ss, int k, std::string& err) {
   const hpop_tuning& tun = ss[0]->tuning;
-  int target, cap, tile;
-  tuned(tun, target, cap, tile);
+  int target, cap, tile, slots;
+  tuned(tun, target, cap, tile, slots);
+  if (exact_forced) slots = 0;
   h_chunks.clear();
   h_segs.clear();
   h_regions.clear();
@@ -301,16 +316,17 @@ hpop_status Engine::assemble(hpop_session* const* ss, int k, std::string& err) {
     return HPOP_E_ARG;
   }
   hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), seg_base, buckets, elems,
-                              (long long)h_regions.size(), times, err);
+                              slots > 0 ? buckets * (long long)slots : 0, (long long)h_regions.size(), times, err);
   if (st != HPOP_OK) return st;
   ws.plan.n_tiles = tiles;
   ws.plan.tile_elems = tile;
   ws.plan.cap = cap;
+  ws.plan.slot_cap = slots;
+  ws.plan.pad1 = 0;
   n_times = times;
   return HPOP_OK;
 }
 
-static const char* kStageNames[] = {"reset", "stats", "hist", "scan", "scatter", "carry", "merge", "base", "region"};
 
 hpop_status Engine::upload(std::string& err) {
   // descriptors go through pinned memory so the copies are stream-ordered
@@ -337,57 +353,64 @@ hpop_status Engine::upload(std::string& err) {
 hpop_status Engine::enqueue(bool build, bool with_timing, std::string& err) {
   const Plan& p = ws.plan;
   hipStream_t st = alloc.stream;
-  const int cap = p.cap;
   const int nreg = (int)h_regions.size();
   if (with_timing && events.empty()) {
-    events.resize(10);
+    events.resize(12);
     for (auto& e : events) HPOP_HIP(hipEventCreate(&e), "hipEventCreate");
   }
+  mark_names.clear();
   int ev = 0;
-  auto mark = [&]() -> hipError_t {
+  auto mark = [&](const char* name) -> hipError_t {
     if (!with_timing) return hipSuccess;
+    if (name) mark_names.push_back(name);
     return hipEventRecord(events[ev++], st);
   };
-  HPOP_HIP(mark(), "hipEventRecord");
+  HPOP_HIP(mark(nullptr), "hipEventRecord");
   if (build) {
     HPOP_HIP(launch_reset(p, st), "k_reset");
-    HPOP_HIP(mark(), "hipEventRecord");
+    HPOP_HIP(mark("reset"), "hipEventRecord");
     HPOP_HIP(launch_stats(p, st), "k_stats");
-    HPOP_HIP(mark(), "hipEventRecord");
-    HPOP_HIP(launch_hist(p, st), "k_hist");
-    HPOP_HIP(mark(), "hipEventRecord");
-    HPOP_HIP(launch_scan(p, st), "k_scan");
-    HPOP_HIP(mark(), "hipEventRecord");
-    HPOP_HIP(launch_scatter(p, st), "k_scatter");
-    HPOP_HIP(mark(), "hipEventRecord");
+    HPOP_HIP(mark("stats"), "hipEventRecord");
+    if (p.slot_cap == 0) {  // exact offsets: count, then scan, then scatter
+      HPOP_HIP(launch_hist(p, st), "k_hist");
+      HPOP_HIP(mark("hist"), "hipEventRecord");
+      HPOP_HIP(launch_scan(p, st), "k_scan");
+      HPOP_HIP(mark("scan"), "hipEventRecord");
+      HPOP_HIP(launch_scatter(p, st), "k_scatter");
+      HPOP_HIP(mark("scatter"), "hipEventRecord");
+    } else {  // fixed slots: scatter in one pass, then offsets of the merged intervals
+      HPOP_HIP(launch_scatter(p, st), "k_scatter");
+      HPOP_HIP(mark("scatter"), "hipEventRecord");
+      HPOP_HIP(launch_scan(p, st), "k_scan");
+      HPOP_HIP(mark("scan"), "hipEventRecord");
+    }
     HPOP_HIP(launch_carry(p, st), "k_carry");
-    HPOP_HIP(mark(), "hipEventRecord");
-    HPOP_HIP(launch_merge(p, cap, st), "k_merge");
-    HPOP_HIP(mark(), "hipEventRecord");
+    HPOP_HIP(mark("carry"), "hipEventRecord");
+    HPOP_HIP(launch_merge_wave(p, st), "k_merge_wave");
+    HPOP_HIP(mark("merge_wave"), "hipEventRecord");
+    HPOP_HIP(launch_merge_block(p, p.cap, st), "k_merge_block");
+    HPOP_HIP(mark("merge_block"), "hipEventRecord");
     HPOP_HIP(launch_base(p, st), "k_base");
-    HPOP_HIP(mark(), "hipEventRecord");
+    HPOP_HIP(mark("base"), "hipEventRecord");
   }
   HPOP_HIP(launch_region(p, ws.d_regions, nreg, ws.d_trees, ws.d_times, st), "k_region");
-  HPOP_HIP(mark(), "hipEventRecord");
+  HPOP_HIP(mark("region"), "hipEventRecord");
   n_marks = ev;
-  marks_build = build;
-  // results: trees, first bad record, oversized buckets
+  // results: trees, first bad record, oversized buckets, slot overflow
   const size_t bt = (size_t)nreg * sizeof(Tree);
   char* h = (char*)ws.pinned.ptr;
   if (bt) HPOP_HIP(hipMemcpyAsync(h, ws.d_trees, bt, hipMemcpyDeviceToHost, st), "copy trees");
   HPOP_HIP(hipMemcpyAsync(h + bt, p.err, 8, hipMemcpyDeviceToHost, st), "copy error word");
-  HPOP_HIP(hipMemcpyAsync(h + bt + 8, p.oversized, 8, hipMemcpyDeviceToHost, st), "copy counters");
+  HPOP_HIP(hipMemcpyAsync(h + bt + 8, p.oversized, 16, hipMemcpyDeviceToHost, st), "copy counters");
   return HPOP_OK;
 }
 
 hpop_status Engine::collect_timing(std::string& err) {
   stage_ms.clear();
-  if (n_marks < 2) return HPOP_OK;
-  int first = marks_build ? 0 : 8;
   for (int i = 1; i < n_marks; ++i) {
     float ms = 0.f;
     HPOP_HIP(hipEventElapsedTime(&ms, events[i - 1], events[i]), "hipEventElapsedTime");
-    stage_ms.push_back(std::make_pair(std::string(kStageNames[first + i - 1]), ms));
+    stage_ms.push_back(std::make_pair(mark_names[i - 1], ms));
   }
   return HPOP_OK;
 }
@@ -405,6 +428,15 @@ hpop_status Engine::run(hpop_session* const* ss, int k, uint32_t flags, hpop_met
         same = false;
   }
   const bool build = !same || (flags & HPOP_FORCE_REBUILD);
+  if (!same && exact_forced) {
+    // new records or another session set: try the single-pass scatter again
+    bool changed = (int)forced_versions.size() != k;
+    for (int i = 0; !changed && i < k; ++i) changed = forced_versions[i] != ss[i]->version;
+    if (changed) {
+      exact_forced = false;
+      forced_versions.clear();
+    }
+  }
   const size_t nreg_total = [&] {
     size_t t = 0;
     for (int i = 0; i < k; ++i) t += ss[i]->regions.size();
@@ -466,10 +498,19 @@ hpop_status Engine::run(hpop_session* const* ss, int k, uint32_t flags, hpop_met
   }
   const size_t bt = h_regions.size() * sizeof(Tree);
   const char* h = (const char*)ws.pinned.ptr;
-  unsigned long long bad, over;
+  unsigned long long bad, over, slot_over;
   memcpy(&bad, h + bt, 8);
   memcpy(&over, h + bt + 8, 8);
+  memcpy(&slot_over, h + bt + 16, 8);
   if (build) last_oversized = (long long)over;
+  if (build && bad == ULLONG_MAX && ws.plan.slot_cap > 0 && slot_over > 0) {
+    // a bucket outgrew its fixed slots: redo this plan with exact offsets
+    exact_forced = true;
+    forced_versions.clear();
+    for (int i = 0; i < k; ++i) forced_versions.push_back(ss[i]->version);
+    key_sessions.clear();
+    return run(ss, k, flags | HPOP_FORCE_REBUILD, out, timing, err);
+  }
   if (bad != ULLONG_MAX) {
     const unsigned long long cid = bad >> 40, idx = bad & ((1ull << 40) - 1);
     if (cid < chunk_owner.size()) {
@@ -515,7 +556,8 @@ void Engine::release() {
 }
 
 long long tuning_key(const hpop_tuning& t) {
-  return ((long long)t.bucket_target << 32) ^ ((long long)t.bucket_cap << 16) ^ (long long)t.tile_elems;
+  return ((long long)t.bucket_target << 40) ^ ((long long)t.bucket_cap << 24) ^ ((long long)t.tile_elems << 8) ^
+         (long long)(t.scatter_slots + 1);
 }
 
 }  // namespace hpop
@@ -846,19 +888,20 @@ hpop_status hpop_session_get_info(const hpop_session* s, hpop_session_info* out)
 
 hpop_status hpop_session_set_tuning(hpop_session* s, const hpop_tuning* t) {
   if (!s || !t) return HPOP_E_ARG;
-  if (t->bucket_target < 0 || t->bucket_cap < 0 || t->tile_elems < 0) return fail(s, HPOP_E_ARG, "negative tuning");
+  if (t->bucket_target < 0 || t->bucket_cap < 0 || t->tile_elems < 0 || t->scatter_slots < -1)
+    return fail(s, HPOP_E_ARG, "negative tuning");
   s->tuning = *t;
   return HPOP_OK;
 }
 
 hpop_status hpop_session_get_tuning(const hpop_session* s, hpop_tuning* out) {
   if (!s || !out) return HPOP_E_ARG;
-  int target, cap, tile;
-  tuned(s->tuning, target, cap, tile);
+  int target, cap, tile, slots;
+  tuned(s->tuning, target, cap, tile, slots);
   out->bucket_target = target;
   out->bucket_cap = cap;
   out->tile_elems = tile;
-  out->reserved = 0;
+  out->scatter_slots = slots > 0 ? slots : -1;
   return HPOP_OK;
 }
 

@@ -72,6 +72,8 @@ def test_device_pointer_input_matches_host_input():
     {"bucket_target": 256, "bucket_cap": 4096, "tile_elems": 8192},
     {"bucket_target": 4096, "bucket_cap": 2048, "tile_elems": 4096},
     {"bucket_target": 4096, "bucket_cap": 4096, "tile_elems": 2048},
+    {"bucket_target": 256, "scatter_slots": -1},
+    {"bucket_target": 64, "scatter_slots": 64},
 ])
 def test_tunings_agree(tuning):
     tr = tg.make_trace(22, 4, 4, 8, 20000, 5000, w_range=(0.5, 1.5), regions="nested", n_regions=6)
