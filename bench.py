@@ -33,10 +33,10 @@ METRIC = "trace events/sec reduced to full metric tree"
 # algorithmic bytes per unit of each build kernel (a unit is a record, except
 # where noted); the minimum each kernel must move for its role
 ALGO_BYTES = {
-    "stats": ("record", 16),      # read start + end
-    "hist": ("record", 8),        # read start
-    "scatter": ("record", 32),    # read start + end, write one 16 B bucketed record
-    "merge": ("record+comp", (16, 16)),  # read 16 B per record, write 16 B per merged interval
+    "stats": 8,          # read start
+    "hist": 16,          # read start + end (exact-count fallback only)
+    "scatter": 32,       # read start + end, write one 16 B bucketed record
+    "merge_wave": None,  # read 16 B per record, write 16 B per merged interval and level
 }
 
 
@@ -135,10 +135,10 @@ def bench_single(hp, trace, steps, warmup, workload):
         hp.hpop_session_destroy(s)
     stage_ms = {k: v / steps for k, v in stage_tot.items()}
     dom = max((k for k in stage_ms if k in ALGO_BYTES), key=lambda k: stage_ms[k])
-    if dom == "merge":
+    if dom == "merge_wave":
         algo = 16 * n_events + 16 * info.n_components
     else:
-        algo = ALGO_BYTES[dom][1] * n_events
+        algo = ALGO_BYTES[dom] * n_events
     achieved = algo / (stage_ms[dom] * 1e-3) / 1e9
     traffic = load_traffic(dom, workload)
     roof = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

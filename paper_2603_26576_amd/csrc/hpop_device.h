@@ -482,4 +482,40 @@ __device__ __forceinline__ void block_tree(long long (&v)[9], long long* lds) {
   __syncthreads();
 }
 
+// ----------------------------------------------------------------------------
+// wave-level scans with DPP lane shifts (no LDS round trips)
+// ----------------------------------------------------------------------------
+
+// DPP controls of the gfx9 family: row_shr:n, row_bcast:15 / :31, wave_shr:1
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+// v from the lane selected by CTRL, or `old` where that lane is outside the
+// row/bank masks or has no source lane
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ long long dpp64(long long old, long long v) {
+  const int lo = __builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(old >> 32), (int)(v >> 32), CTRL, ROW_MASK, BANK_MASK, false);
+  return (long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned long long)(unsigned int)lo);
+}
+
+__device__ __forceinline__ long long readlane64(long long v, int lane) {
+  const int lo = __builtin_amdgcn_readlane((int)v, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return (long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned long long)(unsigned int)lo);
+}
+
+// Exclusive scan over the 64 lanes (lane order) with identity `id`, and the total.
+template <class Op>
+__device__ __forceinline__ long long wave_excl_scan_dpp(long long x, long long id, long long& total) {
+  x = Op::apply(x, dpp64<kDppRowShr1, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowShr2, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowShr4, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowShr8, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowBcast15, 0xa, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowBcast31, 0xc, 0xf>(id, x));
+  total = readlane64(x, 63);
+  return dpp64<kDppWaveShr1, 0xf, 0xf>(id, x);
+}
+
 }  // namespace hpop

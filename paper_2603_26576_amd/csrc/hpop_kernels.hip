@@ -571,9 +571,9 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
   }
   const int ni = (int)n;
   const long long lo = g.min_s + ((gb - sd.bucket_begin) << g.shift);
+  const Elem* rec = p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + off;
   // load; find the highest varying key bit
   unsigned int kor = 0;
-  const Elem* rec = p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + off;
   for (int i = lane; i < ni; i += 64) {
     const Elem el = rec[i];
     const unsigned int k = (unsigned int)(el.s - lo);
@@ -581,71 +581,74 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
     W.eslot[i] = el.e_slot;
     kor |= k;
   }
-  for (int i = lane; i < kWaveBins / 2; i += 64) W.bins[i] = 0;
   for (int d = 32; d >= 1; d >>= 1) kor |= __shfl_xor(kor, d, 64);
+  // sub-bins: about two per record, 128 .. 1024; a lane owns bpl of them (two per LDS word)
+  int dbits = 7;
+  while ((1 << dbits) < 2 * ni && dbits < 10) ++dbits;
+  const int nbins = 1 << dbits, bpl = nbins >> 6, wpl = bpl >> 1;
+  for (int j = 0; j < wpl; ++j) W.bins[lane * wpl + j] = 0;
   wave_sync();
   const int hb = kor ? 32 - __clz((int)kor) : 0;
-  const int dsh = hb > 10 ? hb - 10 : 0;  // digit = key >> dsh, at most 1024 values
+  const int dsh = hb > dbits ? hb - dbits : 0;  // sub-bin = key >> dsh
   constexpr int RPL = kWaveCap / 64;
   unsigned int rank[RPL], dig[RPL];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
-    const int i = r * 64 + lane;
     rank[r] = 0;
     dig[r] = 0;
-    if (i < ni) {
-      const unsigned int d = W.key[i] >> dsh;
-      const unsigned int sh = 16u * (d & 1u);
-      rank[r] = (atomicAdd(&W.bins[d >> 1], 1u << sh) >> sh) & 0xFFFFu;
-      dig[r] = d;
+    if (r * 64 < ni) {  // wave-uniform
+      const int i = r * 64 + lane;
+      if (i < ni) {
+        const unsigned int d = W.key[i] >> dsh;
+        const unsigned int sh = 16u * (d & 1u);
+        rank[r] = (atomicAdd(&W.bins[d >> 1], 1u << sh) >> sh) & 0xFFFFu;
+        dig[r] = d;
+      }
     }
   }
   wave_sync();
-  // exclusive scan of the 1024 counters: lane owns bins 16*lane .. 16*lane+15
-  unsigned int cnt[16];
+  // exclusive scan of the sub-bin counters (lane order = sub-bin order)
   long long tot = 0;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const unsigned int w = W.bins[lane * 8 + j];
-    cnt[2 * j] = w & 0xFFFFu;
-    cnt[2 * j + 1] = w >> 16;
-    tot += cnt[2 * j] + cnt[2 * j + 1];
+  for (int j = 0; j < wpl; ++j) {
+    const unsigned int w = W.bins[lane * wpl + j];
+    tot += (w & 0xFFFFu) + (w >> 16);
   }
-  long long v1[1] = {tot}, e1[1], t1[1];
-  wave_excl_scan<1, OpSum>(v1, e1, t1, 0);
-  unsigned int run = (unsigned int)e1[0];
-  unsigned int start[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    start[j] = run;
-    run += cnt[j];
-  }
+  long long all;
+  unsigned int run = (unsigned int)wave_excl_scan_dpp<OpSum>(tot, 0, all);
   wave_sync();
-#pragma unroll
-  for (int j = 0; j < 8; ++j) W.bins[lane * 8 + j] = start[2 * j] | (start[2 * j + 1] << 16);
+  for (int j = 0; j < wpl; ++j) {
+    const unsigned int w = W.bins[lane * wpl + j];
+    const unsigned int a = run, b = run + (w & 0xFFFFu);
+    run = b + (w >> 16);
+    W.bins[lane * wpl + j] = a | (b << 16);
+  }
   wave_sync();
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
-    const int i = r * 64 + lane;
-    if (i < ni) {
-      const unsigned int d = dig[r];
-      const unsigned int st0 = (W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu;
-      W.ord[st0 + rank[r]] = (unsigned short)i;
+    if (r * 64 < ni) {
+      const int i = r * 64 + lane;
+      if (i < ni) {
+        const unsigned int d = dig[r];
+        const unsigned int st0 = (W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu;
+        W.ord[st0 + rank[r]] = (unsigned short)i;
+      }
     }
   }
   wave_sync();
   // order inside each sub-bin by the full key
   bool crowded = false;
   if (dsh > 0) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int c = (int)cnt[j];
+    for (int j = 0; j < bpl; ++j) {
+      const int d = lane * bpl + j;
+      const int st0 = (int)((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu);
+      const int st1 = d + 1 < nbins ? (int)((W.bins[(d + 1) >> 1] >> (16u * ((d + 1) & 1u))) & 0xFFFFu) : ni;
+      const int c = st1 - st0;
       if (c < 2) continue;
       if (c > 32) {
         crowded = true;
         continue;
       }
-      unsigned short* o = W.ord + start[j];
+      unsigned short* o = W.ord + st0;
       for (int a = 1; a < c; ++a) {
         const unsigned short x = o[a];
         const unsigned int kx = W.key[x];
@@ -663,82 +666,92 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
     return;
   }
   wave_sync();
-  // flatten: lane owns sorted positions [q0, q1)
+  // flatten: lane owns sorted positions [q0, q0 + cnt), held in registers
   const int ipl = (ni + 63) >> 6;
-  const int q0 = min(ni, lane * ipl), q1 = min(ni, q0 + ipl);
-  const long long EMASK = (1ll << kSlotShift) - 1;
+  const int q0 = lane * ipl;
+  const int cnt = min(max(ni - q0, 0), ipl);
+  constexpr long long EMASK = (1ll << kSlotShift) - 1;
+  long long sv[RPL], ev[RPL];
+  int sl[RPL];
   long long tmax[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
-  for (int q = q0; q < q1; ++q) {
-    const long long es = W.eslot[W.ord[q]];
-    const int slot = (int)((unsigned long long)es >> kSlotShift);
-    const long long e = es & EMASK;
 #pragma unroll
-    for (int l = 0; l < 3; ++l)
-      if (slot <= l && e > tmax[l]) tmax[l] = e;
+  for (int j = 0; j < RPL; ++j) {
+    sv[j] = 0;
+    ev[j] = 0;
+    sl[j] = 3;
+    if (j < cnt) {
+      const int i = W.ord[q0 + j];
+      const long long es = W.eslot[i];
+      sv[j] = lo + (long long)W.key[i];
+      ev[j] = es & EMASK;
+      sl[j] = (int)((unsigned long long)es >> kSlotShift);
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        if (sl[j] <= l && ev[j] > tmax[l]) tmax[l] = ev[j];
+    }
   }
-  long long exm[3], totm[3];
-  wave_excl_scan<3, OpMax>(tmax, exm, totm, LLONG_MIN);
-  long long M[3];
+  long long M[3], totm;
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
     const long long c = p.carry[gb * 3 + l];
-    M[l] = exm[l] > c ? exm[l] : c;
+    M[l] = c;
+    if (l < nlev) {
+      const long long ex = wave_excl_scan_dpp<OpMax>(tmax[l], LLONG_MIN, totm);
+      M[l] = ex > c ? ex : c;
+    }
   }
-  long long acc[6] = {0, 0, 0, 0, 0, 0};
+  // per-lane measure per level and the three break counts packed in 16-bit fields
+  long long acc[3] = {0, 0, 0};
+  long long nbrk = 0;
   {
     long long Mb[3] = {M[0], M[1], M[2]};
-    for (int q = q0; q < q1; ++q) {
-      const int i = W.ord[q];
-      const long long es = W.eslot[i];
-      const int slot = (int)((unsigned long long)es >> kSlotShift);
-      const long long e = es & EMASK;
-      const long long s = lo + (long long)W.key[i];
 #pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        if (l < nlev && slot <= l) {
-          const long long b = s > Mb[l] ? s : Mb[l];
-          if (e > b) acc[l] += e - b;
-          if (s > Mb[l]) acc[3 + l] += 1;
-          if (e > Mb[l]) Mb[l] = e;
+    for (int j = 0; j < RPL; ++j) {
+      if (j < cnt) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          if (l < nlev && sl[j] <= l) {
+            const long long b = sv[j] > Mb[l] ? sv[j] : Mb[l];
+            if (ev[j] > b) acc[l] += ev[j] - b;
+            if (sv[j] > Mb[l]) nbrk += 1ll << (16 * l);
+            if (ev[j] > Mb[l]) Mb[l] = ev[j];
+          }
         }
       }
     }
   }
-  long long exa[6], tota[6];
-  wave_excl_scan<6, OpSum>(acc, exa, tota, 0);
-  {
-    long long P[3], R[3];
+  long long P[3], totp[3] = {0, 0, 0};
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      P[l] = exa[l];
-      R[l] = exa[3 + l];
-    }
-    for (int q = q0; q < q1; ++q) {
-      const int i = W.ord[q];
-      const long long es = W.eslot[i];
-      const int slot = (int)((unsigned long long)es >> kSlotShift);
-      const long long e = es & EMASK;
-      const long long s = lo + (long long)W.key[i];
+  for (int l = 0; l < 3; ++l) {
+    P[l] = 0;
+    if (l < nlev) P[l] = wave_excl_scan_dpp<OpSum>(acc[l], 0, totp[l]);
+  }
+  long long totr;
+  const long long Rp = wave_excl_scan_dpp<OpSum>(nbrk, 0, totr);
+  long long R[3] = {Rp & 0xFFFF, (Rp >> 16) & 0xFFFF, (Rp >> 32) & 0xFFFF};
+#pragma unroll
+  for (int j = 0; j < RPL; ++j) {
+    if (j < cnt) {
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
-        if (l < nlev && slot <= l) {
-          if (s > M[l]) {
+        if (l < nlev && sl[j] <= l) {
+          if (sv[j] > M[l]) {
             Comp c;
-            c.cs = s;
+            c.cs = sv[j];
             c.pl = P[l];
             p.comp[l][off + R[l]] = c;
             R[l] += 1;
           }
-          const long long b = s > M[l] ? s : M[l];
-          if (e > b) P[l] += e - b;
-          if (e > M[l]) M[l] = e;
+          const long long b = sv[j] > M[l] ? sv[j] : M[l];
+          if (ev[j] > b) P[l] += ev[j] - b;
+          if (ev[j] > M[l]) M[l] = ev[j];
         }
       }
     }
   }
   if (lane < 3) {
-    p.bsum[gb * 3 + lane] = tota[lane];
-    p.ncomp[gb * 3 + lane] = (unsigned int)tota[3 + lane];
+    p.bsum[gb * 3 + lane] = lane == 0 ? totp[0] : lane == 1 ? totp[1] : totp[2];
+    p.ncomp[gb * 3 + lane] = (unsigned int)((totr >> (16 * lane)) & 0xFFFF);
   }
 }
 
