@@ -45,7 +45,7 @@ struct ChunkDesc {
   int32_t seg;         // global segment (resource) index
   int32_t slot;        // level rank of the kind: 0, 1 or 2
   int32_t chunk_id;    // index in the chunk table (error reports)
-  int32_t pad;
+  int32_t owner;       // session (or serving query) the records belong to
 };
 
 struct SegDesc {
@@ -120,6 +120,9 @@ struct Plan {
   unsigned int* ticket;              // [4]: scan ticket, block-path take counter, block-path queue length
   unsigned int* queue;               // [n_buckets] buckets handed to the block path
   unsigned long long* oversized;     // [0] buckets above the on-chip capacity, [1] buckets above slot_cap
+  unsigned int* owner_err;           // [n_owners] set when an owner has an invalid record
+  int32_t n_owners;
+  int32_t pad2;
 };
 
 }  // namespace hpop

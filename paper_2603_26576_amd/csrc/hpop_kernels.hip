@@ -42,6 +42,7 @@ __global__ void k_reset(Plan p) {
     p.oversized[1] = 0;
   }
   if (tid < 4) p.ticket[tid] = 0;
+  for (long long i = tid; i < p.n_owners; i += stride) p.owner_err[i] = 0;
 }
 
 // ----------------------------------------------------------------------------
@@ -262,6 +263,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
       if (!rec_valid(sv[k], ev[k])) {
         // first bad record of the build: chunk << 40 | index (rare path)
         atomicMin(p.err, ((unsigned long long)cd.chunk_id << 40) | (unsigned long long)i);
+        p.owner_err[cd.owner] = 1u;
       } else if (sv[k] < ev[k]) {
         bk[k] = bucket_of(sv[k], g);
         bmin = min(bmin, bk[k]);

@@ -66,7 +66,8 @@ struct Workspace {
   hipGraphExec_t graph_exec = nullptr;
   long long layout_gen = 0;
   hpop_status prepare(Alloc& a, long long n_chunks, long long n_segs, long long n_buckets, long long n_elems,
-                      long long n_slots, long long n_regions, long long n_times, std::string& err);
+                      long long n_slots, long long n_regions, long long n_times, long long n_owners,
+                      std::string& err);
   void release(Alloc& a);
 };
 
@@ -99,6 +100,8 @@ struct Engine {
   std::vector<std::pair<std::string, float>> stage_ms;
 
   hpop_status assemble(hpop_session* const* ss, int k, std::string& err);
+  hpop_status assemble_plan(const hpop_tuning& tun, const std::vector<long long>& seg_count,
+                            const std::vector<char>& seg_host, int n_owners, long long times, std::string& err);
   hpop_status upload(std::string& err);
   hpop_status enqueue(bool build, bool with_timing, std::string& err);
   hpop_status collect_timing(std::string& err);

@@ -143,7 +143,7 @@ static size_t carve_bytes(size_t n, size_t sz) { return (n * sz + 255) & ~size_t
 
 hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, long long n_buckets,
                                long long n_elems, long long n_slots, long long n_regions, long long n_times,
-                               std::string& err) {
+                               long long n_owners, std::string& err) {
   const size_t nscan = (size_t)((n_buckets + kScanTile - 1) / kScanTile + 1);
   size_t small = 0;
   small += carve_bytes(n_chunks, sizeof(ChunkDesc));
@@ -158,6 +158,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   small += carve_bytes(3 * n_segs, sizeof(long long));
   small += carve_bytes(1, 8) + carve_bytes(nscan, 8) + carve_bytes(4, 4) + carve_bytes(2, 8);
   small += carve_bytes(n_buckets, sizeof(unsigned int));
+  small += carve_bytes(n_owners, sizeof(unsigned int));
   small += carve_bytes(n_regions, sizeof(RegionDesc)) + carve_bytes(n_regions, sizeof(Tree));
   small += carve_bytes(4 * n_times, sizeof(long long));
   if (!meta.reserve(a, small, false)) {
@@ -193,6 +194,9 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   p.ticket = carve<unsigned int>(cur, 4);
   p.oversized = carve<unsigned long long>(cur, 2);
   p.queue = carve<unsigned int>(cur, n_buckets);
+  p.owner_err = carve<unsigned int>(cur, n_owners);
+  p.n_owners = (int32_t)n_owners;
+  p.pad2 = 0;
   d_regions = carve<RegionDesc>(cur, n_regions);
   d_trees = carve<Tree>(cur, n_regions);
   d_times = carve<long long>(cur, 4 * n_times);
@@ -251,23 +255,23 @@ static void tuned(const hpop_tuning& t, int& target, int& cap, int& tile, int& s
 // The k sessions of `ss` become one plan: segments are session by session,
 // hosts before devices; regions likewise.
 hpop_status Engine::assemble(hpop_session* const* ss, int k, std::string& err) {
-  const hpop_tuning& tun = ss[0]->tuning;
-  int target, cap, tile, slots;
-  tuned(tun, target, cap, tile, slots);
-  if (exact_forced) slots = 0;
   h_chunks.clear();
-  h_segs.clear();
   h_regions.clear();
+  chunk_owner.clear();
   seg_of_session.assign(k, 0);
   reg_of_session.assign(k, 0);
-  long long tiles = 0, buckets = 0, elems = 0, times = 0;
-  int seg_base = 0;
   std::vector<long long> seg_count;
+  std::vector<char> seg_host;
+  long long times = 0;
+  int seg_base = 0;
   for (int i = 0; i < k; ++i) {
     hpop_session* s = ss[i];
     const int R = s->n_hosts + s->n_devices;
     seg_of_session[i] = seg_base;
-    seg_count.assign(R, 0);
+    for (int r = 0; r < R; ++r) {
+      seg_count.push_back(0);
+      seg_host.push_back(r < s->n_hosts ? 1 : 0);
+    }
     for (size_t c = 0; c < s->chunks.size(); ++c) {
       const RecChunk& rc = s->chunks[c];
       if (rc.count == 0) continue;
@@ -275,26 +279,14 @@ hpop_status Engine::assemble(hpop_session* const* ss, int k, std::string& err) {
       d.s = (const int64_t*)((char*)s->arena.ptr + rc.off_s);
       d.e = (const int64_t*)((char*)s->arena.ptr + rc.off_e);
       d.count = rc.count;
-      d.tile_begin = tiles;
+      d.tile_begin = 0;
       d.seg = seg_base + rc.resource;
       d.slot = slot_of_kind(rc.kind);
       d.chunk_id = (int32_t)h_chunks.size();
-      d.pad = 0;
+      d.owner = i;
       h_chunks.push_back(d);
-      chunk_owner.resize(h_chunks.size());
-      chunk_owner.back() = std::make_pair(i, (int)c);
-      tiles += (rc.count + tile - 1) / tile;
-      seg_count[rc.resource] += rc.count;
-      elems += rc.count;
-    }
-    for (int r = 0; r < R; ++r) {
-      SegDesc sd;
-      sd.bucket_begin = buckets;
-      const long long want = (seg_count[r] + target - 1) / target;
-      sd.log_nb = std::min(24, ceil_log2(std::max(1ll, want)));
-      sd.n_levels = r < s->n_hosts ? 3 : 2;
-      buckets += 1ll << sd.log_nb;
-      h_segs.push_back(sd);
+      chunk_owner.push_back(std::make_pair(i, (int)c));
+      seg_count[seg_base + rc.resource] += rc.count;
     }
     reg_of_session[i] = (int)h_regions.size();
     for (size_t g = 0; g < s->regions.size(); ++g) {
@@ -311,12 +303,40 @@ hpop_status Engine::assemble(hpop_session* const* ss, int k, std::string& err) {
     }
     seg_base += R;
   }
-  if (seg_base > INT_MAX / 2 || h_chunks.size() > (size_t)INT_MAX / 2) {
+  return assemble_plan(ss[0]->tuning, seg_count, seg_host, k, times, err);
+}
+
+// Segments, tiles, buckets and the workspace for the chunks in h_chunks (their
+// seg and owner set) and the regions in h_regions.
+hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long long>& seg_count,
+                                  const std::vector<char>& seg_host, int n_owners, long long times, std::string& err) {
+  int target, cap, tile, slots;
+  tuned(tun, target, cap, tile, slots);
+  if (exact_forced) slots = 0;
+  const long long n_segs = (long long)seg_count.size();
+  if (n_segs > INT_MAX / 2 || h_chunks.size() > (size_t)INT_MAX / 2) {
     err = "too many resources or record batches in one build";
     return HPOP_E_ARG;
   }
-  hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), seg_base, buckets, elems,
-                              slots > 0 ? buckets * (long long)slots : 0, (long long)h_regions.size(), times, err);
+  long long tiles = 0, buckets = 0, elems = 0;
+  for (auto& d : h_chunks) {
+    d.tile_begin = tiles;
+    tiles += (d.count + tile - 1) / tile;
+    elems += d.count;
+  }
+  h_segs.clear();
+  for (long long r = 0; r < n_segs; ++r) {
+    SegDesc sd;
+    sd.bucket_begin = buckets;
+    const long long want = (seg_count[r] + target - 1) / target;
+    sd.log_nb = std::min(24, ceil_log2(std::max(1ll, want)));
+    sd.n_levels = seg_host[r] ? 3 : 2;
+    buckets += 1ll << sd.log_nb;
+    h_segs.push_back(sd);
+  }
+  hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), n_segs, buckets, elems,
+                              slots > 0 ? buckets * (long long)slots : 0, (long long)h_regions.size(), times,
+                              std::max(1, n_owners), err);
   if (st != HPOP_OK) return st;
   ws.plan.n_tiles = tiles;
   ws.plan.tile_elems = tile;
@@ -326,7 +346,6 @@ hpop_status Engine::assemble(hpop_session* const* ss, int k, std::string& err) {
   n_times = times;
   return HPOP_OK;
 }
-
 
 hpop_status Engine::upload(std::string& err) {
   // descriptors go through pinned memory so the copies are stream-ordered

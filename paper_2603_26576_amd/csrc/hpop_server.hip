@@ -7,17 +7,20 @@
 //
 // One device step serves up to max_inflight queued queries (at most one per
 // session, oldest first):
-//   pack   : the queries' records -> 16 B records per (query, resource) item,
-//            validated; the session's frontier (largest end) is advanced
-//   prep   : per item and level, the smallest new start x and the first list
-//            entry whose end reaches x (k0): entries before k0 cannot change;
-//            scratch space for the rest is reserved from a pool
-//   splice : per item and level, the list entries from k0 on plus the new
-//            records are sorted by start (LDS or global radix) and flattened
-//            again with the running state of entry k0-1, overwriting the
-//            list from k0 on
+//   build  : the records of all queries of the step go through the same
+//            bucketed build as a trace (validation, time buckets, LDS sort,
+//            flattening), one segment per (query, resource)
+//   prep   : per (query, resource, level): the first list entry whose end
+//            reaches the earliest new start (k0; entries before it cannot
+//            change), the list's largest end X and the last new bucket that
+//            starts at or before X; scratch for the overlap is reserved
+//   splice : the list entries from k0 on and the new records of buckets up to
+//            X's bucket are sorted (LDS or global radix) and flattened again
+//            from the running state of entry k0-1; the new merged intervals
+//            of the later buckets cannot touch the old list and are appended
+//            with their measures shifted
 //   region : per query, every resource clipped to the closing region and to
-//            [origin, frontier) by binary search, then reduced to the two trees
+//            [origin, frontier) by binary search, then reduced to two trees
 // Queries that arrive while a step runs wait for the next step.
 #include <hip/hip_runtime.h>
 
@@ -48,28 +51,17 @@ struct ListDev {
   long long cap;
 };
 
-struct ServChunk {
-  const int64_t* s;
-  const int64_t* e;
-  long long count;
-  long long dst;         // offset of the first packed record
-  long long tile_begin;  // first tile of the chunk
-  int32_t slot;
-  int32_t req;
+struct ServItem {
+  int32_t req;     // query index in the step
+  int32_t seg;     // segment of the step's build
+  int32_t list0;   // list index of level 0 (levels follow)
+  int32_t nlev;
   int32_t sid;
   int32_t pad;
-};
-
-struct ServItem {
-  long long rec_off;     // packed records [rec_off, rec_off + n)
-  long long n;
-  long long k0[3];       // prep output per level
-  long long scr_off[3];  // prep output: scratch offset per level
+  long long k0[3];       // prep: first list entry that may change (-1: nothing to do)
+  long long xb[3];       // prep: last new bucket (segment-relative) merged with the old entries, -1: none
+  long long scr_off[3];  // prep: scratch offset per level
   long long scr_len[3];
-  int32_t req;
-  int32_t list0;         // list index of level 0 (levels follow)
-  int32_t nlev;
-  int32_t pad;
 };
 
 struct ServReq {
@@ -89,7 +81,6 @@ struct ServCtl {
 
 constexpr int kServThreads = 256;
 constexpr int kServCap = 2048;
-constexpr int kServTile = 4096;
 
 __device__ __forceinline__ long long list_ce(const ListDev& L, long long k) {
   const Comp c = L.base[k];
@@ -110,141 +101,87 @@ __device__ __forceinline__ long long list_measure(const ListDev& L, long long t)
   return L.base[k].pl + (ce < t ? ce : t) - L.base[k].cs;
 }
 
-__global__ __launch_bounds__(256) void k_serv_pack(const ServChunk* chunks, int n_chunks, Elem* raw,
-                                                   long long* frontier, unsigned int* req_err) {
-  __shared__ int s_c;
-  const long long tile = blockIdx.x;
-  if (threadIdx.x == 0) {
-    int lo = 0, hi = n_chunks - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (chunks[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
-    }
-    s_c = lo;
-  }
-  __syncthreads();
-  const ServChunk c = chunks[s_c];
-  const long long b = (tile - c.tile_begin) * kServTile;
-  const long long end = min(c.count, b + kServTile);
-  const unsigned long long slotbits = (unsigned long long)c.slot << kSlotShift;
-  long long mx = LLONG_MIN;
-  bool bad = false;
-  for (long long i = b + threadIdx.x; i < end; i += 256) {
-    const long long s = (long long)c.s[i], e = (long long)c.e[i];
-    if (!rec_valid(s, e)) bad = true;
-    Elem el;
-    el.s = rec_valid(s, e) ? s : 0;
-    el.e_slot = (long long)((unsigned long long)(rec_valid(s, e) ? e : 0) | slotbits);
-    raw[c.dst + i] = el;
-    if (rec_valid(s, e) && e > mx) mx = e;
-  }
-  mx = wave_red_max(mx);
-  if ((threadIdx.x & 63) == 0 && mx != LLONG_MIN) atomicMax((unsigned long long*)&frontier[c.sid], (unsigned long long)mx);
-  if (bad) atomicOr(&req_err[c.req], 1u);
+__device__ __forceinline__ const Elem* bucket_records(const Plan& p, long long gb) {
+  return p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + (long long)p.offsets[gb];
 }
 
-__global__ __launch_bounds__(256) void k_serv_prep(ServItem* items, const Elem* raw, const ListDev* lists,
-                                                   const unsigned int* req_err, ServCtl* ctl) {
-  __shared__ long long red[3][4];
-  ServItem& it = items[blockIdx.x];
-  const bool skip = req_err[it.req] != 0;
-  long long xm[3] = {LLONG_MAX, LLONG_MAX, LLONG_MAX};
-  long long cnt[3] = {0, 0, 0};
-  if (!skip) {
-    for (long long i = threadIdx.x; i < it.n; i += 256) {
-      const Elem el = raw[it.rec_off + i];
-      const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
-      const long long e = el.e_slot & ((1ll << kSlotShift) - 1);
-      if (el.s >= e) continue;  // empty records cover nothing
-      for (int l = 0; l < 3; ++l)
-        if (slot <= l) {
-          xm[l] = el.s < xm[l] ? el.s : xm[l];
-          cnt[l] += 1;
-        }
+// one thread per (item, level)
+__global__ __launch_bounds__(64) void k_serv_prep(ServItem* items, int n_items, Plan p, const ListDev* lists,
+                                                  long long* frontier, ServCtl* ctl) {
+  const int t = blockIdx.x * 64 + threadIdx.x;
+  if (t >= n_items * 3) return;
+  ServItem& it = items[t / 3];
+  const int l = t % 3;
+  it.k0[l] = -1;
+  it.xb[l] = -1;
+  it.scr_len[l] = 0;
+  it.scr_off[l] = 0;
+  // a query with an invalid record is not applied; a build whose buckets
+  // outgrew their slots is redone before anything is applied
+  if (l >= it.nlev || p.owner_err[it.req] || p.oversized[1]) return;
+  const SegDesc sd = p.segs[it.seg];
+  const SegStats stt = p.stats[it.seg];
+  if (l == 0 && stt.max_e > stt.min_s) atomicMax((unsigned long long*)&frontier[it.sid], stt.max_e);
+  const long long nb = 1ll << sd.log_nb;
+  // first bucket with a new merged interval of this level
+  long long b0 = -1;
+  for (long long b = 0; b < nb; ++b)
+    if (p.ncomp[(sd.bucket_begin + b) * 3 + l]) {
+      b0 = b;
+      break;
+    }
+  if (b0 < 0) return;  // no new interval at this level
+  const ListDev L = lists[it.list0 + l];
+  const long long x = p.comp[l][p.offsets[sd.bucket_begin + b0]].cs;
+  long long lo = 0, hi = L.len;
+  while (lo < hi) {
+    const long long mid = (lo + hi) >> 1;
+    if (list_ce(L, mid) < x) lo = mid + 1; else hi = mid;
+  }
+  const long long k0 = lo;
+  // new buckets that may reach back into the old list: those starting at or before its largest end
+  long long xb = -1;
+  if (L.len > 0) {
+    const long long X = list_ce(L, L.len - 1);
+    const Geom g = seg_geom(stt, sd);
+    if (X >= g.min_s) {
+      const unsigned long long rel = (unsigned long long)(X - g.min_s) >> g.shift;
+      xb = rel < (unsigned long long)nb ? (long long)rel : nb - 1;
     }
   }
-  for (int l = 0; l < 3; ++l) {
-    xm[l] = wave_red_min(xm[l]);
-    cnt[l] = wave_red_sum(cnt[l]);
+  long long need = L.len - k0;
+  for (long long b = 0; b <= xb; ++b) need += p.counts[sd.bucket_begin + b];
+  const unsigned long long at = atomicAdd(&ctl->pool_used, (unsigned long long)(2 * need));
+  if (at + 2 * need > ctl->pool_cap) {
+    atomicAdd(&ctl->pool_overflow, (unsigned long long)(2 * need));
+    return;
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __shared__ long long rc[3][4];
-  if (lane == 0)
-    for (int l = 0; l < 3; ++l) {
-      red[l][wave] = xm[l];
-      rc[l][wave] = cnt[l];
-    }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int l = 0; l < 3; ++l) {
-      long long x = LLONG_MAX, c = 0;
-      for (int w = 0; w < 4; ++w) {
-        x = red[l][w] < x ? red[l][w] : x;
-        c += rc[l][w];
-      }
-      it.k0[l] = -1;
-      it.scr_len[l] = 0;
-      if (l >= it.nlev || c == 0) continue;
-      const ListDev L = lists[it.list0 + l];
-      // first entry whose end reaches x: ends increase along the list
-      long long lo = 0, hi = L.len;
-      while (lo < hi) {
-        const long long mid = (lo + hi) >> 1;
-        if (list_ce(L, mid) < x) lo = mid + 1; else hi = mid;
-      }
-      it.k0[l] = lo;
-      const long long need = (L.len - lo) + c;
-      it.scr_len[l] = need;
-      // two areas per level: the records and the sort's scratch
-      const unsigned long long at = atomicAdd(&ctl->pool_used, (unsigned long long)(2 * need));
-      if (at + 2 * need > ctl->pool_cap) {
-        atomicAdd(&ctl->pool_overflow, (unsigned long long)(2 * need));
-        it.k0[l] = -1;
-      } else {
-        it.scr_off[l] = (long long)at;
-      }
-    }
-  }
+  it.k0[l] = k0;
+  it.xb[l] = xb;
+  it.scr_off[l] = (long long)at;
+  it.scr_len[l] = need;
 }
 
-__global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* items, const Elem* raw,
-                                                              ListDev* lists, Elem* pool, const ServCtl* ctl) {
+// one workgroup per (item, level)
+__global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* items, Plan p, ListDev* lists,
+                                                              Elem* pool, const ServCtl* ctl) {
   __shared__ SortSmem<kServThreads, kServCap> sm;
+  __shared__ unsigned int s_fill;
+  __shared__ long long s_min[kServThreads / 64];
+  __shared__ long long s_run[kServThreads / 64];
+  if (ctl->pool_overflow || p.oversized[1]) return;  // the host redoes the step
   const ServItem it = items[blockIdx.x / 3];
   const int l = blockIdx.x % 3;
-  if (ctl->pool_overflow) return;  // the host grows the pool and runs the step again
   if (l >= it.nlev || it.k0[l] < 0) return;
   ListDev& Lr = lists[it.list0 + l];
   const ListDev L = Lr;
-  const long long k0 = it.k0[l];
+  const SegDesc sd = p.segs[it.seg];
+  const long long nb = 1ll << sd.log_nb;
+  const long long k0 = it.k0[l], xb = it.xb[l];
   const long long nS = L.len - k0;
   const long long total = it.scr_len[l];
   Elem* A = pool + it.scr_off[l];
   Elem* B = A + total;
-  // gather: list entries from k0 on, then the level's new records
-  for (long long i = threadIdx.x; i < nS; i += kServThreads) {
-    Elem el;
-    el.s = L.base[k0 + i].cs;
-    el.e_slot = list_ce(L, k0 + i);
-    A[i] = el;
-  }
-  __shared__ unsigned int s_fill;
-  if (threadIdx.x == 0) s_fill = 0;
-  __syncthreads();
-  for (long long i = threadIdx.x; i < it.n; i += kServThreads) {
-    const Elem el = raw[it.rec_off + i];
-    const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
-    const long long e = el.e_slot & ((1ll << kSlotShift) - 1);
-    if (slot <= l && el.s < e) {
-      const unsigned int p = atomicAdd(&s_fill, 1u);
-      Elem o;
-      o.s = el.s;
-      o.e_slot = e;
-      A[nS + p] = o;
-    }
-  }
-  __syncthreads();
-  // running state of the unchanged prefix
   FlatState st;
   for (int q = 0; q < 3; ++q) {
     st.M[q] = LLONG_MIN;
@@ -254,43 +191,98 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   st.M[0] = k0 > 0 ? list_ce(L, k0 - 1) : LLONG_MIN;
   st.P[0] = k0 < L.len ? L.base[k0].pl : L.total;
   st.R[0] = k0;
-  long long lo = LLONG_MAX;
-  {
-    long long m = LLONG_MAX;
-    for (long long i = threadIdx.x; i < total; i += kServThreads) m = A[i].s < m ? A[i].s : m;
-    m = wave_red_min(m);
-    __shared__ long long r4[4];
-    if ((threadIdx.x & 63) == 0) r4[threadIdx.x >> 6] = m;
-    __syncthreads();
-    for (int w = 0; w < 4; ++w) lo = r4[w] < lo ? r4[w] : lo;
-    __syncthreads();
-  }
   Comp* out[3] = {L.base, nullptr, nullptr};
-  if (total <= kServCap) {
-    const int ni = (int)total;
-    for (int i = threadIdx.x; i < ni; i += kServThreads) sm.E[i] = A[i];
+  if (total > 0) {
+    // old entries from k0 on, then the level's new records of buckets 0..xb
+    for (long long i = threadIdx.x; i < nS; i += kServThreads) {
+      Elem el;
+      el.s = L.base[k0 + i].cs;
+      el.e_slot = list_ce(L, k0 + i);
+      A[i] = el;
+    }
+    if (threadIdx.x == 0) s_fill = 0;
     __syncthreads();
-    const unsigned short* ord = sort_lds<kServThreads, kServCap>(sm, ni, lo);
-    flatten_tile<kServThreads>(sm.E, ord, ni, 1, 0, out, st, sm.lds_scan, nullptr);
-  } else {
-    const Elem* src = sort_global<kServThreads, kServCap>(sm, A, B, total, lo);
-    for (long long t0 = 0; t0 < total; t0 += kServCap) {
-      const int cnt = (int)min((long long)kServCap, total - t0);
-      for (int i = threadIdx.x; i < cnt; i += kServThreads) sm.E[i] = src[t0 + i];
+    for (long long b = 0; b <= xb; ++b) {
+      const long long gb = sd.bucket_begin + b;
+      const Elem* rec = bucket_records(p, gb);
+      const long long n = p.counts[gb];
+      for (long long i = threadIdx.x; i < n; i += kServThreads) {
+        const Elem el = rec[i];
+        const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
+        if (slot <= l) {
+          const unsigned int q = atomicAdd(&s_fill, 1u);
+          Elem o;
+          o.s = el.s;
+          o.e_slot = el.e_slot & ((1ll << kSlotShift) - 1);
+          A[nS + q] = o;
+        }
+      }
+    }
+    __syncthreads();
+    const long long cnt = nS + (long long)s_fill;
+    long long m = LLONG_MAX;
+    for (long long i = threadIdx.x; i < cnt; i += kServThreads) m = A[i].s < m ? A[i].s : m;
+    m = wave_red_min(m);
+    if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = m;
+    __syncthreads();
+    long long lo = LLONG_MAX;
+    for (int w = 0; w < kServThreads / 64; ++w) lo = s_min[w] < lo ? s_min[w] : lo;
+    __syncthreads();
+    if (cnt <= kServCap) {
+      const int ni = (int)cnt;
+      for (int i = threadIdx.x; i < ni; i += kServThreads) sm.E[i] = A[i];
       __syncthreads();
-      flatten_tile<kServThreads>(sm.E, nullptr, cnt, 1, 0, out, st, sm.lds_scan, nullptr);
-      __syncthreads();
+      const unsigned short* ord = sort_lds<kServThreads, kServCap>(sm, ni, lo);
+      flatten_tile<kServThreads>(sm.E, ord, ni, 1, 0, out, st, sm.lds_scan, nullptr);
+    } else if (cnt > 0) {
+      const Elem* src = sort_global<kServThreads, kServCap>(sm, A, B, cnt, lo);
+      for (long long t0 = 0; t0 < cnt; t0 += kServCap) {
+        const int c = (int)min((long long)kServCap, cnt - t0);
+        for (int i = threadIdx.x; i < c; i += kServThreads) sm.E[i] = src[t0 + i];
+        __syncthreads();
+        flatten_tile<kServThreads>(sm.E, nullptr, c, 1, 0, out, st, sm.lds_scan, nullptr);
+        __syncthreads();
+      }
     }
   }
+  // later buckets: their merged intervals start after the old list's end; append
+  // them with measures rebased from the new buckets' own prefix to the list's
+  long long R = st.R[0];
+  long long P = st.P[0];
+  const long long bt = xb + 1;
+  if (bt < nb) {
+    const long long shift = P - p.base[(sd.bucket_begin + bt) * 3 + l];
+    for (long long b0 = bt; b0 < nb; b0 += kServThreads) {
+      const long long b = b0 + threadIdx.x;
+      const long long gb = sd.bucket_begin + b;
+      const long long c = b < nb ? (long long)p.ncomp[gb * 3 + l] : 0;
+      // exclusive prefix of the component counts of this chunk of buckets
+      long long v[1] = {c}, ex[1], tot[1];
+      block_excl_scan<kServThreads, 1, OpSum>(v, ex, tot, 0, sm.lds_scan);
+      if (c) {
+        const Comp* src = p.comp[l] + p.offsets[gb];
+        const long long base = p.base[gb * 3 + l] + shift;
+        for (long long j = 0; j < c; ++j) {
+          Comp o;
+          o.cs = src[j].cs;
+          o.pl = src[j].pl + base;
+          L.base[R + ex[0] + j] = o;
+        }
+      }
+      R += tot[0];
+    }
+    P = p.seg_total[it.seg * 3 + l] + shift;
+  }
+  (void)s_run;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    Lr.len = st.R[0];
-    Lr.total = st.P[0];
+    Lr.len = R;
+    Lr.total = P;
   }
 }
 
 __global__ __launch_bounds__(256) void k_serv_region(const ServReq* reqs, const ListDev* lists,
-                                                     const long long* frontier, const unsigned int* req_err,
-                                                     Tree* trees) {
+                                                     const long long* frontier, Tree* trees) {
   __shared__ long long lds[4 * 10];
   const ServReq q = reqs[blockIdx.x >> 1];
   const bool global = blockIdx.x & 1;
@@ -382,7 +374,8 @@ struct hpop_server {
   std::string last_error;
   long long inflight_bytes = 0;
   // device buffers of a step
-  DevBuf d_lists, d_chunks, d_items, d_reqs, d_raw, d_pool, d_frontier, d_err, d_ctl, d_trees, d_stage;
+  Engine engine;  // the bucketed build of each step's records
+  DevBuf d_lists, d_items, d_reqs, d_pool, d_frontier, d_ctl, d_trees, d_stage;
   PinnedBuf h_stage, h_out;
   long long pool_cap = 0;
   // statistics
@@ -408,14 +401,10 @@ bool ensure(DevBuf& b, Alloc& a, size_t bytes) { return b.reserve(a, bytes, fals
 // status for the whole step; per-query failures are stored in the queries.
 hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& err) {
   Alloc& A = S->alloc;
+  Engine& En = S->engine;
   const int nq = (int)batch.size();
-  const int ns = (int)S->sessions.size();
-  // ---- host plan: chunks, items, requests
-  std::vector<ServChunk> chunks;
-  std::vector<ServItem> items;
-  std::vector<ServReq> reqs(nq);
-  std::vector<long long> level_new(S->lists.size(), 0);
-  long long tiles = 0, rec = 0;
+  hipStream_t st = S->stream;
+  // ---- stage host records (one copy), then describe every chunk to the build
   size_t host_bytes = 0;
   for (int q = 0; q < nq; ++q)
     if (batch[q]->mem_space == HPOP_MEM_HOST) host_bytes += batch[q]->host.size() * 8;
@@ -424,7 +413,15 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
       err = "staging allocation failed";
       return HPOP_E_OOM;
     }
+    // the previous step's copy out of the pinned buffer has completed (each step ends synchronised)
   }
+  En.h_chunks.clear();
+  En.h_regions.clear();
+  std::vector<long long> seg_count;
+  std::vector<char> seg_host;
+  std::vector<ServItem> items;
+  std::vector<ServReq> reqs(nq);
+  std::vector<long long> level_new(S->lists.size(), 0);
   size_t hoff = 0;
   for (int q = 0; q < nq; ++q) {
     Query* Q = batch[q];
@@ -438,55 +435,51 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     r.n_devices = ss.n_devices;
     r.list_begin = ss.list_begin;
     const int R = ss.n_hosts + ss.n_devices;
-    std::vector<long long> per_res(R, 0);
-    std::vector<std::vector<int>> res_chunks(R);
-    for (size_t c = 0; c < Q->chunks.size(); ++c) {
-      per_res[Q->chunks[c].resource] += Q->chunks[c].count;
-      res_chunks[Q->chunks[c].resource].push_back((int)c);
-    }
     const int64_t* dev_base = nullptr;
     if (Q->mem_space == HPOP_MEM_HOST && !Q->host.empty()) {
       memcpy((char*)S->h_stage.ptr + hoff, Q->host.data(), Q->host.size() * 8);
       dev_base = (const int64_t*)((char*)S->d_stage.ptr + hoff);
+      hoff += Q->host.size() * 8;
     }
-    for (int res = 0; res < R; ++res) {
-      if (per_res[res] == 0) continue;
-      ServItem it{};
-      it.rec_off = rec;
-      it.n = per_res[res];
-      it.req = q;
-      it.list0 = ss.list_begin + res * 3;
-      it.nlev = res < ss.n_hosts ? 3 : 2;
-      long long off = rec;
-      for (int c : res_chunks[res]) {
-        const hpop_event_chunk& ch = Q->chunks[c];
-        if (ch.count == 0) continue;
-        ServChunk sc{};
-        if (Q->mem_space == HPOP_MEM_HOST) {
-          // host chunks point into Q->host; rebase onto the device staging copy
-          sc.s = dev_base + (ch.start - Q->host.data());
-          sc.e = dev_base + (ch.end - Q->host.data());
-        } else {
-          sc.s = ch.start;
-          sc.e = ch.end;
-        }
-        sc.count = ch.count;
-        sc.dst = off;
-        sc.tile_begin = tiles;
-        sc.slot = slot_of_kind(ch.kind);
-        sc.req = q;
-        sc.sid = Q->sid;
-        chunks.push_back(sc);
-        tiles += (ch.count + kServTile - 1) / kServTile;
-        off += ch.count;
-        for (int l = sc.slot; l < it.nlev; ++l) level_new[it.list0 + l] += ch.count;
+    std::vector<int> seg_of_res(R, -1);
+    for (const hpop_event_chunk& ch : Q->chunks) {
+      if (ch.count == 0) continue;
+      int& sg = seg_of_res[ch.resource];
+      if (sg < 0) {
+        sg = (int)seg_count.size();
+        seg_count.push_back(0);
+        seg_host.push_back(ch.resource < ss.n_hosts ? 1 : 0);
+        ServItem it{};
+        it.req = q;
+        it.seg = sg;
+        it.list0 = ss.list_begin + ch.resource * 3;
+        it.nlev = ch.resource < ss.n_hosts ? 3 : 2;
+        it.sid = Q->sid;
+        items.push_back(it);
       }
-      rec = off;
-      items.push_back(it);
+      ChunkDesc d;
+      if (Q->mem_space == HPOP_MEM_HOST) {
+        d.s = dev_base + (ch.start - Q->host.data());
+        d.e = dev_base + (ch.end - Q->host.data());
+      } else {
+        d.s = ch.start;
+        d.e = ch.end;
+      }
+      d.count = ch.count;
+      d.tile_begin = 0;
+      d.seg = sg;
+      d.slot = slot_of_kind(ch.kind);
+      d.chunk_id = (int32_t)En.h_chunks.size();
+      d.owner = q;
+      En.h_chunks.push_back(d);
+      seg_count[sg] += ch.count;
+      const int nlev = ch.resource < ss.n_hosts ? 3 : 2;
+      for (int l = d.slot; l < nlev; ++l) level_new[ss.list_begin + ch.resource * 3 + l] += ch.count;
     }
-    if (Q->mem_space == HPOP_MEM_HOST) hoff += Q->host.size() * 8;
   }
-  hipStream_t st = S->stream;
+  hpop_tuning tun{};
+  hpop_status rc = En.assemble_plan(tun, seg_count, seg_host, std::max(1, nq), 0, err);
+  if (rc != HPOP_OK) return rc;
   // ---- list capacity: a list grows by at most its level's new records
   for (size_t i = 0; i < S->lists.size(); ++i) {
     if (!level_new[i]) continue;
@@ -498,7 +491,6 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
       return HPOP_E_OOM;
     }
   }
-  // ---- uploads
   std::vector<ListDev> ld(S->lists.size());
   for (size_t i = 0; i < S->lists.size(); ++i) {
     ld[i].base = (Comp*)S->lists[i].buf.ptr;
@@ -506,102 +498,106 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     ld[i].total = S->lists[i].total;
     ld[i].cap = (long long)(S->lists[i].buf.bytes / sizeof(Comp));
   }
-  const size_t b_lists = ld.size() * sizeof(ListDev), b_chunks = chunks.size() * sizeof(ServChunk),
-               b_items = items.size() * sizeof(ServItem), b_reqs = reqs.size() * sizeof(ServReq);
-  const size_t b_out = 2 * nq * sizeof(Tree) + b_lists + nq * 4 + ns * 8 + sizeof(ServCtl) + 64;
-  if (!ensure(S->d_lists, A, b_lists + 64) || !ensure(S->d_chunks, A, b_chunks + 64) ||
-      !ensure(S->d_items, A, b_items + 64) || !ensure(S->d_reqs, A, b_reqs + 64) ||
-      !ensure(S->d_raw, A, (size_t)(rec + 1) * sizeof(Elem)) || !ensure(S->d_err, A, nq * 4 + 64) ||
-      !ensure(S->d_ctl, A, sizeof(ServCtl)) ||
-      !ensure(S->d_trees, A, 2 * nq * sizeof(Tree) + 64) || !S->h_out.reserve(b_lists + b_chunks + b_items + b_reqs + b_out)) {
+  const int ni = (int)items.size();
+  const size_t b_lists = ld.size() * sizeof(ListDev), b_items = items.size() * sizeof(ServItem),
+               b_reqs = reqs.size() * sizeof(ServReq), b_trees = 2 * (size_t)nq * sizeof(Tree);
+  if (!ensure(S->d_lists, A, b_lists + 64) || !ensure(S->d_items, A, b_items + 64) ||
+      !ensure(S->d_reqs, A, b_reqs + 64) || !ensure(S->d_ctl, A, sizeof(ServCtl)) ||
+      !ensure(S->d_trees, A, b_trees + 64) || !S->h_out.reserve(b_lists + b_items + b_reqs + b_trees + 256)) {
     err = "device allocation for a serving step failed";
     return HPOP_E_OOM;
   }
-  const size_t want_pool = (size_t)std::max<long long>(1 << 20, 4 * rec + 4096);
-  if ((long long)want_pool > S->pool_cap) {
-    if (!ensure(S->d_pool, A, want_pool * sizeof(Elem))) {
+  long long total_rec = 0;
+  for (long long c : seg_count) total_rec += c;
+  const long long want_pool = std::max<long long>(1 << 20, 4 * total_rec + 4096);
+  if (want_pool > S->pool_cap) {
+    S->d_pool.release(A);
+    if (!ensure(S->d_pool, A, (size_t)want_pool * sizeof(Elem))) {
       err = "scratch pool allocation failed";
       return HPOP_E_OOM;
     }
     S->pool_cap = (long long)(S->d_pool.bytes / sizeof(Elem));
   }
+  // ---- the build of the step's records (no regions: the trees come from the lists)
   if (host_bytes) {
     hipError_t e = hipMemcpyAsync(S->d_stage.ptr, S->h_stage.ptr, host_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return err = hipGetErrorString(e), HPOP_E_HIP;
   }
+  if (!En.ws.pinned.reserve(64)) {
+    err = "pinned host allocation failed";
+    return HPOP_E_OOM;
+  }
+  rc = En.upload(err);
+  if (rc == HPOP_OK) rc = En.enqueue(true, false, err);
+  if (rc != HPOP_OK) return rc;
   char* h = (char*)S->h_out.ptr;
   memcpy(h, ld.data(), b_lists);
-  memcpy(h + b_lists, chunks.data(), b_chunks);
-  memcpy(h + b_lists + b_chunks, items.data(), b_items);
-  memcpy(h + b_lists + b_chunks + b_items, reqs.data(), b_reqs);
-  char* hres = h + b_lists + b_chunks + b_items + b_reqs;
+  memcpy(h + b_lists, items.data(), b_items);
+  memcpy(h + b_lists + b_items, reqs.data(), b_reqs);
+  char* hres = h + b_lists + b_items + b_reqs;
   hipError_t e = hipSuccess;
   if (b_lists) e = hipMemcpyAsync(S->d_lists.ptr, h, b_lists, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && b_chunks) e = hipMemcpyAsync(S->d_chunks.ptr, h + b_lists, b_chunks, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && b_items)
-    e = hipMemcpyAsync(S->d_items.ptr, h + b_lists + b_chunks, b_items, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(S->d_reqs.ptr, h + b_lists + b_chunks + b_items, b_reqs, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && b_items) e = hipMemcpyAsync(S->d_items.ptr, h + b_lists, b_items, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->d_reqs.ptr, h + b_lists + b_items, b_reqs, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return err = hipGetErrorString(e), HPOP_E_HIP;
+  const Plan& P = En.ws.plan;
   for (int attempt = 0; attempt < 4; ++attempt) {
-    // per-step control words
     ServCtl ctl{0, (unsigned long long)S->pool_cap, 0, 0};
     memcpy(hres, &ctl, sizeof ctl);
     e = hipMemcpyAsync(S->d_ctl.ptr, hres, sizeof ctl, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemsetAsync(S->d_err.ptr, 0, nq * 4, st);
     if (e != hipSuccess) return err = hipGetErrorString(e), HPOP_E_HIP;
-    if (tiles > 0)
-      hipLaunchKernelGGL(k_serv_pack, dim3((unsigned)tiles), dim3(256), 0, st, (const ServChunk*)S->d_chunks.ptr,
-                         (int)chunks.size(), (Elem*)S->d_raw.ptr, (long long*)S->d_frontier.ptr,
-                         (unsigned int*)S->d_err.ptr);
-    if (!items.empty()) {
-      hipLaunchKernelGGL(k_serv_prep, dim3((unsigned)items.size()), dim3(256), 0, st, (ServItem*)S->d_items.ptr,
-                         (const Elem*)S->d_raw.ptr, (const ListDev*)S->d_lists.ptr,
-                         (const unsigned int*)S->d_err.ptr, (ServCtl*)S->d_ctl.ptr);
-      hipLaunchKernelGGL(k_serv_splice, dim3((unsigned)items.size() * 3), dim3(kServThreads), 0, st,
-                         (const ServItem*)S->d_items.ptr, (const Elem*)S->d_raw.ptr, (ListDev*)S->d_lists.ptr,
-                         (Elem*)S->d_pool.ptr, (const ServCtl*)S->d_ctl.ptr);
+    if (ni > 0) {
+      hipLaunchKernelGGL(k_serv_prep, dim3((unsigned)((3 * ni + 63) / 64)), dim3(64), 0, st,
+                         (ServItem*)S->d_items.ptr, ni, P, (const ListDev*)S->d_lists.ptr,
+                         (long long*)S->d_frontier.ptr, (ServCtl*)S->d_ctl.ptr);
+      hipLaunchKernelGGL(k_serv_splice, dim3((unsigned)(3 * ni)), dim3(kServThreads), 0, st,
+                         (const ServItem*)S->d_items.ptr, P, (ListDev*)S->d_lists.ptr, (Elem*)S->d_pool.ptr,
+                         (const ServCtl*)S->d_ctl.ptr);
     }
     e = hipGetLastError();
-    if (e != hipSuccess) return err = std::string("serving kernels: ") + hipGetErrorString(e), HPOP_E_HIP;
-    e = hipMemcpyAsync(hres, S->d_ctl.ptr, sizeof(ServCtl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(hres, S->d_ctl.ptr, sizeof(ServCtl), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return err = hipGetErrorString(e), HPOP_E_HIP;
+    if (e != hipSuccess) return err = std::string("serving step: ") + hipGetErrorString(e), HPOP_E_HIP;
     ServCtl got;
     memcpy(&got, hres, sizeof got);
     if (!got.pool_overflow) break;
-    // a long suffix needed more scratch: grow the pool and redo the step (no list was written)
-    const size_t np = (size_t)(got.pool_used + got.pool_overflow + 4096) * 2;
+    // a long overlap needed more scratch: grow the pool and redo prep and splice (no list was written)
+    const long long np = (long long)(got.pool_used + got.pool_overflow + 4096) * 2;
     S->d_pool.release(A);
-    if (!ensure(S->d_pool, A, np * sizeof(Elem))) {
+    if (!ensure(S->d_pool, A, (size_t)np * sizeof(Elem))) {
       err = "scratch pool allocation failed";
       return HPOP_E_OOM;
     }
     S->pool_cap = (long long)(S->d_pool.bytes / sizeof(Elem));
-    // the frontier advanced by pack is idempotent (a max); records are packed again
     if (attempt == 3) {
       err = "scratch pool kept overflowing";
       return HPOP_E_OOM;
     }
   }
   hipLaunchKernelGGL(k_serv_region, dim3((unsigned)(2 * nq)), dim3(256), 0, st, (const ServReq*)S->d_reqs.ptr,
-                     (const ListDev*)S->d_lists.ptr, (const long long*)S->d_frontier.ptr,
-                     (const unsigned int*)S->d_err.ptr, (Tree*)S->d_trees.ptr);
+                     (const ListDev*)S->d_lists.ptr, (const long long*)S->d_frontier.ptr, (Tree*)S->d_trees.ptr);
   e = hipGetLastError();
   char* o = hres;
-  if (e == hipSuccess) e = hipMemcpyAsync(o, S->d_trees.ptr, 2 * nq * sizeof(Tree), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess && b_lists)
-    e = hipMemcpyAsync(o + 2 * nq * sizeof(Tree), S->d_lists.ptr, b_lists, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(o + 2 * nq * sizeof(Tree) + b_lists, S->d_err.ptr, nq * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(o, S->d_trees.ptr, b_trees, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && b_lists) e = hipMemcpyAsync(o + b_trees, S->d_lists.ptr, b_lists, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(o + b_trees + b_lists, P.owner_err, nq * 4, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return err = std::string("serving step: ") + hipGetErrorString(e), HPOP_E_HIP;
-  const ListDev* lo = (const ListDev*)(o + 2 * nq * sizeof(Tree));
+  unsigned long long slot_over;
+  memcpy(&slot_over, (const char*)En.ws.pinned.ptr + 16, 8);
+  if (slot_over && !En.exact_forced) {
+    // a bucket outgrew its scatter slots: no list was touched; redo with exact counts
+    En.exact_forced = true;
+    rc = run_step(S, batch, err);
+    En.exact_forced = false;
+    return rc;
+  }
+  const ListDev* lo = (const ListDev*)(o + b_trees);
   for (size_t i = 0; i < S->lists.size(); ++i) {
     S->lists[i].len = lo[i].len;
     S->lists[i].total = lo[i].total;
   }
-  const unsigned int* re = (const unsigned int*)(o + 2 * nq * sizeof(Tree) + b_lists);
+  const unsigned int* re = (const unsigned int*)(o + b_trees + b_lists);
   for (int q = 0; q < nq; ++q) {
     Query* Q = batch[q];
     if (re[q]) {
@@ -681,6 +677,8 @@ hpop_status hpop_server_create(const hpop_server_config* cfg, hpop_server** out)
       return srv_fail(nullptr, HPOP_E_HIP, "stream creation failed");
     }
     S->alloc.stream = S->stream;
+    S->engine.alloc = S->alloc;
+    S->engine.use_graphs = false;
     S->worker = std::thread(worker_loop, S);
     *out = S;
     return HPOP_OK;
@@ -699,8 +697,9 @@ hpop_status hpop_server_destroy(hpop_server* S) {
   if (S->worker.joinable()) S->worker.join();
   (void)hipStreamSynchronize(S->stream);
   for (auto& L : S->lists) L.buf.release(S->alloc);
-  for (DevBuf* b : {&S->d_lists, &S->d_chunks, &S->d_items, &S->d_reqs, &S->d_raw, &S->d_pool, &S->d_frontier,
-                    &S->d_err, &S->d_ctl, &S->d_trees, &S->d_stage})
+  S->engine.release();
+  for (DevBuf* b : {&S->d_lists, &S->d_items, &S->d_reqs, &S->d_pool, &S->d_frontier, &S->d_ctl, &S->d_trees,
+                    &S->d_stage})
     b->release(S->alloc);
   S->h_stage.release();
   S->h_out.release();
