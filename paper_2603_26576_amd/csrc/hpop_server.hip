@@ -503,7 +503,9 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
                b_reqs = reqs.size() * sizeof(ServReq), b_trees = 2 * (size_t)nq * sizeof(Tree);
   if (!ensure(S->d_lists, A, b_lists + 64) || !ensure(S->d_items, A, b_items + 64) ||
       !ensure(S->d_reqs, A, b_reqs + 64) || !ensure(S->d_ctl, A, sizeof(ServCtl)) ||
-      !ensure(S->d_trees, A, b_trees + 64) || !S->h_out.reserve(b_lists + b_items + b_reqs + b_trees + 256)) {
+      !ensure(S->d_trees, A, b_trees + 64) ||
+      // pinned layout: lists, items, requests (uploads), then trees, lists, error flags (results)
+      !S->h_out.reserve(b_lists + b_items + b_reqs + b_trees + b_lists + 4 * (size_t)nq + sizeof(ServCtl) + 256)) {
     err = "device allocation for a serving step failed";
     return HPOP_E_OOM;
   }
