@@ -54,18 +54,22 @@ def kernel_source_hash():
 
 
 def load_traffic(kernel, workload):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel sources."""
-    p = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this
+    kernel and workload, if it was taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
     if not os.path.exists(p):
         return None
-    try:
-        d = json.load(open(p))
-    except Exception:
-        return None
+    d = {}
+    for line in open(p):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
     if d.get("source_hash") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    try:
+        return int(d["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def upload_session(hp, trace):
@@ -390,9 +394,12 @@ def import_traffic(kernel, workload, fetch_csv, write_csv, cal_fetch_csv, cal_wr
            "calibration_fetch_kib": cal_f, "calibration_write_kib": cal_w,
            "fetch_scale": sf, "write_scale": sw,
            "bytes_per_launch": int(f * 1024 * sf + w * 1024 * sw)}
-    path = os.path.join(out_dir, "traffic_%s_%s.json" % (kernel.replace("k_", ""), workload))
+    path = os.path.join(out_dir, "traffic_%s_%s.txt" % (kernel.replace("k_", ""), workload))
     with open(path, "w") as fo:
-        json.dump(rec, fo, indent=1)
+        fo.write("# HBM traffic of %s on the %s workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE\n" % (kernel, workload))
+        fo.write("# (KiB per dispatch), each scaled by the same counter's reading for a plain 1 GiB copy\n")
+        for k, v in rec.items():
+            fo.write("%s: %s\n" % (k, v))
     print(path, rec)
 
 

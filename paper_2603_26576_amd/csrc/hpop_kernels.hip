@@ -520,6 +520,7 @@ struct WaveSmem {
   unsigned int key[kWaveCap];
   long long eslot[kWaveCap];
   unsigned short ord[kWaveCap];
+  unsigned short rank[kWaveCap];     // rank of a record inside its sub-bin
   unsigned int bins[kWaveBins / 2];  // two 16-bit counters per word
 };
 
@@ -545,6 +546,105 @@ __device__ __forceinline__ void wave_excl_scan(const long long (&v)[K], long lon
     if (lane == 0) e = ident;
     ex[k] = e;
     tot[k] = __shfl(x, 63, 64);
+  }
+}
+
+// Flatten of one sorted bucket by one wave: lane owns sorted positions
+// [lane*IPL, lane*IPL + cnt), kept in registers through the three phases
+// (running max of ends, measures and break counts, component writes).
+template <int IPL, int NLEV>
+__device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, long long gb, long long off, int ni,
+                                             long long lo) {
+  const int lane = threadIdx.x & 63;
+  const int ipl = (ni + 63) >> 6;
+  const int q0 = lane * ipl;
+  const int cnt = min(max(ni - q0, 0), ipl);
+  constexpr long long EMASK = (1ll << kSlotShift) - 1;
+  long long sv[IPL], ev[IPL];
+  int sl[IPL];
+  long long tmax[NLEV];
+#pragma unroll
+  for (int l = 0; l < NLEV; ++l) tmax[l] = LLONG_MIN;
+#pragma unroll
+  for (int j = 0; j < IPL; ++j) {
+    sv[j] = 0;
+    ev[j] = 0;
+    sl[j] = 3;
+    if (j < cnt) {
+      const int i = W.ord[q0 + j];
+      const long long es = W.eslot[i];
+      sv[j] = lo + (long long)W.key[i];
+      ev[j] = es & EMASK;
+      sl[j] = (int)((unsigned long long)es >> kSlotShift);
+#pragma unroll
+      for (int l = 0; l < NLEV; ++l)
+        if (sl[j] <= l && ev[j] > tmax[l]) tmax[l] = ev[j];
+    }
+  }
+  long long M[NLEV];
+#pragma unroll
+  for (int l = 0; l < NLEV; ++l) {
+    long long tot;
+    const long long ex = wave_excl_scan_dpp<OpMax>(tmax[l], LLONG_MIN, tot);
+    const long long c = p.carry[gb * 3 + l];
+    M[l] = ex > c ? ex : c;
+  }
+  // per-lane measure per level; the break counts packed in 16-bit fields
+  long long acc[NLEV];
+  long long nbrk = 0;
+  {
+    long long Mb[NLEV];
+#pragma unroll
+    for (int l = 0; l < NLEV; ++l) {
+      Mb[l] = M[l];
+      acc[l] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) {
+#pragma unroll
+      for (int l = 0; l < NLEV; ++l) {
+        if (j < cnt && sl[j] <= l) {
+          const long long b = sv[j] > Mb[l] ? sv[j] : Mb[l];
+          if (ev[j] > b) acc[l] += ev[j] - b;
+          if (sv[j] > Mb[l]) nbrk += 1ll << (16 * l);
+          if (ev[j] > Mb[l]) Mb[l] = ev[j];
+        }
+      }
+    }
+  }
+  long long P[NLEV], totp[NLEV];
+#pragma unroll
+  for (int l = 0; l < NLEV; ++l) P[l] = wave_excl_scan_dpp<OpSum>(acc[l], 0, totp[l]);
+  long long totr;
+  const long long Rp = wave_excl_scan_dpp<OpSum>(nbrk, 0, totr);
+  long long R[NLEV];
+#pragma unroll
+  for (int l = 0; l < NLEV; ++l) R[l] = (Rp >> (16 * l)) & 0xFFFF;
+#pragma unroll
+  for (int j = 0; j < IPL; ++j) {
+#pragma unroll
+    for (int l = 0; l < NLEV; ++l) {
+      if (j < cnt && sl[j] <= l) {
+        if (sv[j] > M[l]) {
+          Comp c;
+          c.cs = sv[j];
+          c.pl = P[l];
+          p.comp[l][off + R[l]] = c;
+          R[l] += 1;
+        }
+        const long long b = sv[j] > M[l] ? sv[j] : M[l];
+        if (ev[j] > b) P[l] += ev[j] - b;
+        if (ev[j] > M[l]) M[l] = ev[j];
+      }
+    }
+  }
+  if (lane < 3) {
+    long long bs = 0;
+#pragma unroll
+    for (int l = 0; l < NLEV; ++l)
+      if (lane == l) bs = totp[l];
+    p.bsum[gb * 3 + lane] = bs;
+    p.ncomp[gb * 3 + lane] = (unsigned int)((totr >> (16 * lane)) & 0xFFFF);
   }
 }
 
@@ -592,21 +692,10 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
   wave_sync();
   const int hb = kor ? 32 - __clz((int)kor) : 0;
   const int dsh = hb > dbits ? hb - dbits : 0;  // sub-bin = key >> dsh
-  constexpr int RPL = kWaveCap / 64;
-  unsigned int rank[RPL], dig[RPL];
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    rank[r] = 0;
-    dig[r] = 0;
-    if (r * 64 < ni) {  // wave-uniform
-      const int i = r * 64 + lane;
-      if (i < ni) {
-        const unsigned int d = W.key[i] >> dsh;
-        const unsigned int sh = 16u * (d & 1u);
-        rank[r] = (atomicAdd(&W.bins[d >> 1], 1u << sh) >> sh) & 0xFFFFu;
-        dig[r] = d;
-      }
-    }
+  for (int i = lane; i < ni; i += 64) {
+    const unsigned int d = W.key[i] >> dsh;
+    const unsigned int sh = 16u * (d & 1u);
+    W.rank[i] = (unsigned short)((atomicAdd(&W.bins[d >> 1], 1u << sh) >> sh) & 0xFFFFu);
   }
   wave_sync();
   // exclusive scan of the sub-bin counters (lane order = sub-bin order)
@@ -625,16 +714,10 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
     W.bins[lane * wpl + j] = a | (b << 16);
   }
   wave_sync();
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    if (r * 64 < ni) {
-      const int i = r * 64 + lane;
-      if (i < ni) {
-        const unsigned int d = dig[r];
-        const unsigned int st0 = (W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu;
-        W.ord[st0 + rank[r]] = (unsigned short)i;
-      }
-    }
+  for (int i = lane; i < ni; i += 64) {
+    const unsigned int d = W.key[i] >> dsh;
+    const unsigned int st0 = (W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu;
+    W.ord[st0 + W.rank[i]] = (unsigned short)i;
   }
   wave_sync();
   // order inside each sub-bin by the full key
@@ -668,92 +751,18 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
     return;
   }
   wave_sync();
-  // flatten: lane owns sorted positions [q0, q0 + cnt), held in registers
+  // flatten: lane owns sorted positions [q0, q0 + cnt); specialised by records per lane and levels
   const int ipl = (ni + 63) >> 6;
-  const int q0 = lane * ipl;
-  const int cnt = min(max(ni - q0, 0), ipl);
-  constexpr long long EMASK = (1ll << kSlotShift) - 1;
-  long long sv[RPL], ev[RPL];
-  int sl[RPL];
-  long long tmax[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
-#pragma unroll
-  for (int j = 0; j < RPL; ++j) {
-    sv[j] = 0;
-    ev[j] = 0;
-    sl[j] = 3;
-    if (j < cnt) {
-      const int i = W.ord[q0 + j];
-      const long long es = W.eslot[i];
-      sv[j] = lo + (long long)W.key[i];
-      ev[j] = es & EMASK;
-      sl[j] = (int)((unsigned long long)es >> kSlotShift);
-#pragma unroll
-      for (int l = 0; l < 3; ++l)
-        if (sl[j] <= l && ev[j] > tmax[l]) tmax[l] = ev[j];
-    }
-  }
-  long long M[3], totm;
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    const long long c = p.carry[gb * 3 + l];
-    M[l] = c;
-    if (l < nlev) {
-      const long long ex = wave_excl_scan_dpp<OpMax>(tmax[l], LLONG_MIN, totm);
-      M[l] = ex > c ? ex : c;
-    }
-  }
-  // per-lane measure per level and the three break counts packed in 16-bit fields
-  long long acc[3] = {0, 0, 0};
-  long long nbrk = 0;
-  {
-    long long Mb[3] = {M[0], M[1], M[2]};
-#pragma unroll
-    for (int j = 0; j < RPL; ++j) {
-      if (j < cnt) {
-#pragma unroll
-        for (int l = 0; l < 3; ++l) {
-          if (l < nlev && sl[j] <= l) {
-            const long long b = sv[j] > Mb[l] ? sv[j] : Mb[l];
-            if (ev[j] > b) acc[l] += ev[j] - b;
-            if (sv[j] > Mb[l]) nbrk += 1ll << (16 * l);
-            if (ev[j] > Mb[l]) Mb[l] = ev[j];
-          }
-        }
-      }
-    }
-  }
-  long long P[3], totp[3] = {0, 0, 0};
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    P[l] = 0;
-    if (l < nlev) P[l] = wave_excl_scan_dpp<OpSum>(acc[l], 0, totp[l]);
-  }
-  long long totr;
-  const long long Rp = wave_excl_scan_dpp<OpSum>(nbrk, 0, totr);
-  long long R[3] = {Rp & 0xFFFF, (Rp >> 16) & 0xFFFF, (Rp >> 32) & 0xFFFF};
-#pragma unroll
-  for (int j = 0; j < RPL; ++j) {
-    if (j < cnt) {
-#pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        if (l < nlev && sl[j] <= l) {
-          if (sv[j] > M[l]) {
-            Comp c;
-            c.cs = sv[j];
-            c.pl = P[l];
-            p.comp[l][off + R[l]] = c;
-            R[l] += 1;
-          }
-          const long long b = sv[j] > M[l] ? sv[j] : M[l];
-          if (ev[j] > b) P[l] += ev[j] - b;
-          if (ev[j] > M[l]) M[l] = ev[j];
-        }
-      }
-    }
-  }
-  if (lane < 3) {
-    p.bsum[gb * 3 + lane] = lane == 0 ? totp[0] : lane == 1 ? totp[1] : totp[2];
-    p.ncomp[gb * 3 + lane] = (unsigned int)((totr >> (16 * lane)) & 0xFFFF);
+  if (nlev == 2) {
+    if (ipl <= 1) wave_flatten<1, 2>(p, W, gb, off, ni, lo);
+    else if (ipl <= 2) wave_flatten<2, 2>(p, W, gb, off, ni, lo);
+    else if (ipl <= 4) wave_flatten<4, 2>(p, W, gb, off, ni, lo);
+    else wave_flatten<8, 2>(p, W, gb, off, ni, lo);
+  } else {
+    if (ipl <= 1) wave_flatten<1, 3>(p, W, gb, off, ni, lo);
+    else if (ipl <= 2) wave_flatten<2, 3>(p, W, gb, off, ni, lo);
+    else if (ipl <= 4) wave_flatten<4, 3>(p, W, gb, off, ni, lo);
+    else wave_flatten<8, 3>(p, W, gb, off, ni, lo);
   }
 }
 

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   __shared__ SortSmem<kServThreads, kServCap> sm;
   __shared__ unsigned int s_fill;
   __shared__ long long s_min[kServThreads / 64];
-  __shared__ long long s_run[kServThreads / 64];
+  __shared__ long long s_pref[kServThreads + 1];
   if (ctl->pool_overflow || p.oversized[1]) return;  // the host redoes the step
   const ServItem it = items[blockIdx.x / 3];
   const int l = blockIdx.x % 3;
@@ -253,27 +253,33 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   if (bt < nb) {
     const long long shift = P - p.base[(sd.bucket_begin + bt) * 3 + l];
     for (long long b0 = bt; b0 < nb; b0 += kServThreads) {
+      // component counts of a chunk of buckets -> prefix in LDS, then one
+      // thread per component copies it (coalesced) with its measure rebased
       const long long b = b0 + threadIdx.x;
-      const long long gb = sd.bucket_begin + b;
-      const long long c = b < nb ? (long long)p.ncomp[gb * 3 + l] : 0;
-      // exclusive prefix of the component counts of this chunk of buckets
+      const long long c = b < nb ? (long long)p.ncomp[(sd.bucket_begin + b) * 3 + l] : 0;
       long long v[1] = {c}, ex[1], tot[1];
       block_excl_scan<kServThreads, 1, OpSum>(v, ex, tot, 0, sm.lds_scan);
-      if (c) {
-        const Comp* src = p.comp[l] + p.offsets[gb];
-        const long long base = p.base[gb * 3 + l] + shift;
-        for (long long j = 0; j < c; ++j) {
-          Comp o;
-          o.cs = src[j].cs;
-          o.pl = src[j].pl + base;
-          L.base[R + ex[0] + j] = o;
+      s_pref[threadIdx.x] = ex[0];
+      if (threadIdx.x == 0) s_pref[kServThreads] = tot[0];
+      __syncthreads();
+      for (long long j = threadIdx.x; j < tot[0]; j += kServThreads) {
+        int a = 0, z = kServThreads - 1;  // last chunk bucket whose prefix is <= j
+        while (a < z) {
+          const int mid = (a + z + 1) >> 1;
+          if (s_pref[mid] <= j) a = mid; else z = mid - 1;
         }
+        const long long gb = sd.bucket_begin + b0 + a;
+        const Comp src = p.comp[l][p.offsets[gb] + (j - s_pref[a])];
+        Comp o;
+        o.cs = src.cs;
+        o.pl = src.pl + p.base[gb * 3 + l] + shift;
+        L.base[R + j] = o;
       }
       R += tot[0];
+      __syncthreads();
     }
     P = p.seg_total[it.seg * 3 + l] + shift;
   }
-  (void)s_run;
   __syncthreads();
   if (threadIdx.x == 0) {
     Lr.len = R;
