@@ -109,11 +109,15 @@ def load_trace_cache(path, tg):
     return tg.Trace(n, m, chunks, [tuple(int(v) for v in r) for r in z["regions"]], info)
 
 
-def bench_single(hp, trace, steps, warmup, workload):
+def bench_single(hp, trace, steps, warmup, workload, tune_cache=None):
     import torch
     s = upload_session(hp, trace)
     n_events = trace.n_events
     try:
+        t = time.time()
+        tun = hp.hpop_autotune([s], tune_cache)  # bucket size, on-chip capacity, tile; cached per size class
+        log("autotune: %.1f s -> target %d cap %d tile %d slots %d" % (time.time() - t, tun.bucket_target,
+                                                                   tun.bucket_cap, tun.tile_elems, tun.scatter_slots))
         for _ in range(warmup):
             hp.hpop_metrics_compute_all(s, hp.HPOP_FORCE_REBUILD)
         hp.hpop_session_enable_timing(s, True)
@@ -148,7 +152,8 @@ def bench_single(hp, trace, steps, warmup, workload):
     roof = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(stage_ms[dom], 4)}
-    return {"ms_per_step": dt * 1e3, "ms_per_step_graph": dt_graph * 1e3, "events": n_events,
+    tuning = {"bucket_target": tun.bucket_target, "bucket_cap": tun.bucket_cap, "tile_elems": tun.tile_elems}
+    return {"tuning": tuning, "ms_per_step": dt * 1e3, "ms_per_step_graph": dt_graph * 1e3, "events": n_events,
             "value": n_events / dt, "value_graph": n_events / dt_graph, "stage_ms": stage_ms, "roofline": roof,
             "components": int(info.n_components), "buckets": int(info.n_buckets),
             "oversized_buckets": int(info.n_oversized), "trees": trees}
@@ -460,7 +465,7 @@ def main():
     log("generated %d records in %.1f s" % (trace.n_events, time.time() - t))
 
     log("single-trace leg: %d warmup + %d timed steps" % (args.warmup, args.steps))
-    r = bench_single(hp, trace, args.steps, args.warmup, args.workload)
+    r = bench_single(hp, trace, args.steps, args.warmup, args.workload, args.tune_cache)
     log("single-trace: %.3f ms/step, %.3e events/s, stages %s" % (r["ms_per_step"], r["value"],
                                                                   {k: round(v, 3) for k, v in r["stage_ms"].items()}))
     out = {"metric": METRIC, "value": r["value"], "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -469,7 +474,8 @@ def main():
            "roofline": r["roofline"],
            "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
            "graph_replay": {"ms_per_step": round(r["ms_per_step_graph"], 4), "events_per_s": r["value_graph"]},
-           "components": r["components"], "buckets": r["buckets"], "oversized_buckets": r["oversized_buckets"]}
+           "components": r["components"], "buckets": r["buckets"], "oversized_buckets": r["oversized_buckets"],
+           "tuning": r["tuning"]}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(trace)

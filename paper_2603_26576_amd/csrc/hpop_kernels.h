@@ -7,7 +7,7 @@
 namespace hpop {
 
 constexpr int kScanTile = 4096;  // bucket counts per workgroup of the offset scan
-constexpr int kHistWin = 2048;   // LDS bucket window of one streaming tile
+constexpr int kHistWin = 512;    // LDS bucket window of one streaming tile
 constexpr int kWaveCap = 512;    // records one wave sorts and flattens on its own
 constexpr int kWaveBins = 1024;  // sub-bins of the wave path's counting sort
 
