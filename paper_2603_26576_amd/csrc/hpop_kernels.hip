@@ -387,16 +387,9 @@ __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
     }
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      long long x = v[l];
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        long long y = __shfl_up(x, d, 64);
-        if (lane >= d) x = x > y ? x : y;
-      }
-      long long ex = __shfl_up(x, 1, 64);
-      if (lane == 0) ex = LLONG_MIN;
+      long long all;
+      const long long ex = wave_excl_scan_dpp<OpMax>(v[l], LLONG_MIN, all);
       if (ok) p.carry[(sd.bucket_begin + b) * 3 + l] = ex > run[l] ? ex : run[l];
-      const long long all = __shfl(x, 63, 64);
       run[l] = all > run[l] ? all : run[l];
     }
   }
@@ -417,16 +410,10 @@ __global__ __launch_bounds__(THREADS) void k_base(Plan p) {
     const bool ok = b < nb;
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-      long long x = ok ? p.bsum[(sd.bucket_begin + b) * 3 + l] : 0;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        long long y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-      }
-      long long ex = __shfl_up(x, 1, 64);
-      if (lane == 0) ex = 0;
+      long long all;
+      const long long ex = wave_excl_scan_dpp<OpSum>(ok ? p.bsum[(sd.bucket_begin + b) * 3 + l] : 0, 0, all);
       if (ok) p.base[(sd.bucket_begin + b) * 3 + l] = run[l] + ex;
-      run[l] += __shfl(x, 63, 64);
+      run[l] += all;
     }
   }
   if (lane == 0) {
