@@ -701,21 +701,26 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
     W.bins[lane * wpl + j] = a | (b << 16);
   }
   wave_sync();
-  for (int i = lane; i < ni; i += 64) {
+  unsigned int fix = 0;  // bit r: the record of round r is the second one of its sub-bin
+  for (int i = lane, r = 0; i < ni; i += 64, ++r) {
     const unsigned int d = W.key[i] >> dsh;
     const unsigned int st0 = (W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu;
-    W.ord[st0 + W.rank[i]] = (unsigned short)i;
+    const unsigned int rk = W.rank[i];
+    W.ord[st0 + rk] = (unsigned short)i;
+    if (rk == 1) fix |= 1u << r;
   }
   wave_sync();
-  // order inside each sub-bin by the full key
+  // order inside each sub-bin by the full key: one lane per sub-bin holding
+  // two or more records (the lane that placed its second record)
   bool crowded = false;
   if (dsh > 0) {
-    for (int j = 0; j < bpl; ++j) {
-      const int d = lane * bpl + j;
+    while (fix) {
+      const int r = __ffs((int)fix) - 1;
+      fix &= fix - 1;
+      const unsigned int d = W.key[r * 64 + lane] >> dsh;
       const int st0 = (int)((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu);
-      const int st1 = d + 1 < nbins ? (int)((W.bins[(d + 1) >> 1] >> (16u * ((d + 1) & 1u))) & 0xFFFFu) : ni;
+      const int st1 = (int)d + 1 < nbins ? (int)((W.bins[(d + 1) >> 1] >> (16u * ((d + 1) & 1u))) & 0xFFFFu) : ni;
       const int c = st1 - st0;
-      if (c < 2) continue;
       if (c > 32) {
         crowded = true;
         continue;
