@@ -419,6 +419,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-traces", type=int, default=1000)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true", help="profiling aid: run only the serving leg")
     ap.add_argument("--serving-queries", type=int, default=400)
     ap.add_argument("--serving-lambdas", default="2000,10000")
     ap.add_argument("--json-out", default=None)
@@ -444,6 +445,10 @@ def main():
         return
     hp.lib()
 
+    if args.serving_only:
+        lams = [int(x) for x in args.serving_lambdas.split(",") if x]
+        print(json.dumps({"serving": serving_leg(hp, lams, args.serving_queries)}), flush=True)
+        return
     log("generating workload %s (scale %g)" % (args.workload, args.scale))
     t = time.time()
     if args.workload == "large":
