@@ -263,48 +263,20 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
                 plan.append((sids[i], arr, k, closes[i], t1, int(sizes[q])))
                 closes[i] = t1
             arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_queries))
-            tickets = []
-            done = []
-
-            lat = []
-
-            def waiter():
-                for t, t_sub in iter(tickets_q.get, None):
-                    hp.hpop_server_wait(srv, t)
-                    now = time.perf_counter()
-                    done.append(now)
-                    lat.append(now - t_sub)
-
-            import queue as _q
-            tickets_q = _q.Queue()
-            th = threading.Thread(target=waiter)
-            th.start()
-            t_start = time.perf_counter()
-            busy = 0
-            for q, (sid, arr, k, a, b, n_rec) in enumerate(plan):
-                while time.perf_counter() - t_start < arrivals[q]:
-                    pass
-                tk = ctypes.c_uint64()
-                while True:
-                    rc = lib.hpop_server_submit(srv, sid, arr, k, hp.HPOP_MEM_DEVICE, a, b, ctypes.byref(tk))
-                    if rc != hp.HPOP_E_BUSY:
-                        break
-                    busy += 1
-                assert rc == 0, rc
-                tickets_q.put((tk.value, t_start + arrivals[q]))
-            tickets_q.put(None)
-            th.join()
-            t_end = max(done)
+            queries = [(sid, (arr, k), a, b, int(arrivals[q] * 1e9))
+                       for q, (sid, arr, k, a, b, n_rec) in enumerate(plan)]
+            _, _, lat_ns, wall_ns, busy = hp.hpop_server_replay(srv, queries, hp.HPOP_MEM_DEVICE)
             st = hp.hpop_server_get_stats(srv)
         finally:
             hp.hpop_server_destroy(srv)
+        wall = wall_ns * 1e-9
         ev = int(sizes.sum())
-        lat_us = np.sort(np.array(lat)) * 1e6
+        lat_us = np.sort(lat_ns) * 1e-3
         steps_run = max(1, st.device_steps - base.device_steps)
         results.append({"lambda_req_s": lam, "queries": n_queries, "events": ev,
                         "offered_events_per_s": ev / float(arrivals[-1]),
-                        "events_per_s": ev / (t_end - t_start),
-                        "achieved_req_s": n_queries / (t_end - t_start),
+                        "events_per_s": ev / wall,
+                        "achieved_req_s": n_queries / wall,
                         "p50_us": round(float(np.percentile(lat_us, 50)), 1),
                         "p99_us": round(float(np.percentile(lat_us, 99)), 1),
                         "max_us": round(float(lat_us[-1]), 1),

@@ -258,6 +258,30 @@ hpop_status hpop_server_submit(hpop_server* srv, int32_t sid, const hpop_event_c
 hpop_status hpop_server_wait(hpop_server* srv, uint64_t ticket, int64_t timeout_ns,
                              hpop_metric_tree* out_region, hpop_metric_tree* out_global);
 hpop_status hpop_server_get_stats(hpop_server* srv, hpop_server_stats* out);
+
+/* One query of an arrival schedule replayed by hpop_server_replay. */
+typedef struct {
+    int32_t sid;
+    int32_t n_chunks;
+    const hpop_event_chunk* chunks;
+    int64_t t0, t1;             /* the query's region, as for hpop_server_submit */
+    int64_t arrival_ns;         /* arrival after the start of the replay; non-decreasing */
+} hpop_replay_query;
+
+/* Load generator without a host language in the loop: submits qs[0..n) from
+ * the calling thread, each at its arrival time (retrying while the server
+ * answers HPOP_E_BUSY), then waits for all of them. Per query (arrays of n
+ * entries, each optional): the two trees as hpop_server_wait writes them,
+ * and latency_ns = time from the scheduled arrival until the worker had the
+ * trees on the host. out_wall_ns: start of the replay to the last completion;
+ * out_busy: submissions refused with HPOP_E_BUSY. All queries are waited for
+ * even when one fails; the first failing status is returned (its message in
+ * hpop_server_last_error) and the trees of failed queries are left unchanged.
+ * Record buffers follow the rules of hpop_server_submit for `mem_space`. */
+hpop_status hpop_server_replay(hpop_server* srv, const hpop_replay_query* qs, int32_t n,
+                               int32_t mem_space, hpop_metric_tree* out_region,
+                               hpop_metric_tree* out_global, int64_t* latency_ns,
+                               int64_t* out_wall_ns, int64_t* out_busy);
 const char* hpop_server_last_error(const hpop_server* srv);
 
 #ifdef __cplusplus

@@ -88,6 +88,12 @@ class hpop_server_stats(ctypes.Structure):
                 ("max_us", ctypes.c_double)]
 
 
+class hpop_replay_query(ctypes.Structure):
+    _fields_ = [("sid", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
+                ("chunks", ctypes.POINTER(hpop_event_chunk)), ("t0", ctypes.c_int64), ("t1", ctypes.c_int64),
+                ("arrival_ns", ctypes.c_int64)]
+
+
 class HpopError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("hpop status %d: %s" % (status, message))
@@ -133,6 +139,9 @@ _SIGS = {
                                 ctypes.POINTER(hpop_metric_tree)]),
     "hpop_server_get_stats": (_I32, [_P, ctypes.POINTER(hpop_server_stats)]),
     "hpop_server_last_error": (ctypes.c_char_p, [_P]),
+    "hpop_server_replay": (_I32, [_P, ctypes.POINTER(hpop_replay_query), _I32, _I32,
+                                  ctypes.POINTER(hpop_metric_tree), ctypes.POINTER(hpop_metric_tree),
+                                  ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
 }
 
 _lib = None
@@ -344,6 +353,35 @@ def hpop_server_get_stats(srv):
     out = hpop_server_stats()
     _check_srv(lib().hpop_server_get_stats(srv, ctypes.byref(out)), srv)
     return out
+
+
+def hpop_server_replay(srv, queries, mem_space):
+    """queries: list of (sid, chunks, t0, t1, arrival_ns), chunks either a list of
+    (resource, kind, start, end) or a (hpop_event_chunk array, count) pair.
+    Returns (region trees, global trees, latency_ns array, wall_ns, busy)."""
+    n = len(queries)
+    arr = (hpop_replay_query * max(1, n))()
+    keep = []
+    for i, (sid, chunks, t0, t1, arrival) in enumerate(queries):
+        if isinstance(chunks, tuple):
+            ca, cnt = chunks
+        else:
+            cnt = len(chunks)
+            ca = (hpop_event_chunk * max(1, cnt))()
+            for j, (r, k, st, en) in enumerate(chunks):
+                ca[j] = hpop_event_chunk(r, k, _ptr(st)[0], _ptr(en)[0], len(st))
+        keep.append(ca)
+        arr[i] = hpop_replay_query(sid, cnt, ctypes.cast(ca, ctypes.POINTER(hpop_event_chunk)), int(t0), int(t1),
+                                   int(arrival))
+    reg = (hpop_metric_tree * max(1, n))()
+    glob = (hpop_metric_tree * max(1, n))()
+    lat = np.zeros(max(1, n), np.int64)
+    wall = _I64()
+    busy = _I64()
+    _check_srv(lib().hpop_server_replay(srv, arr, n, mem_space, reg, glob,
+                                        lat.ctypes.data_as(ctypes.POINTER(_I64)), ctypes.byref(wall),
+                                        ctypes.byref(busy)), srv)
+    return list(reg)[:n], list(glob)[:n], lat[:n], wall.value, busy.value
 
 
 # ---------------------------------------------------------------------------

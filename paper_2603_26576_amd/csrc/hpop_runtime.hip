@@ -64,12 +64,40 @@ static int ceil_log2(long long x) {
 // device memory
 // ----------------------------------------------------------------------------
 
+// The library's own stream-ordered pool per device. Memory freed back to it
+// stays cached (release threshold = all), so the grow-and-copy of session
+// lists and workspaces does not return memory to the driver and map it again.
+static hipMemPool_t library_pool(int dev) {
+  static std::mutex mu;
+  static std::vector<hipMemPool_t> pools;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)pools.size() <= dev) pools.resize(dev + 1, nullptr);
+  if (!pools[dev]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    unsigned long long keep = ~0ull;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    pools[dev] = pool;
+  }
+  return pools[dev];
+}
+
 void* Alloc::get(size_t bytes) {
   if (bytes == 0) bytes = 256;
   void* p = nullptr;
-  if (fn_alloc) {
-    p = fn_alloc(ctx, bytes, (void*)stream);
-  } else if (hipMallocAsync(&p, bytes, stream) != hipSuccess) {
+  if (fn_alloc) return fn_alloc(ctx, bytes, (void*)stream);
+  int dev = 0;
+  hipMemPool_t pool = hipGetDevice(&dev) == hipSuccess ? library_pool(dev) : nullptr;
+  const hipError_t e = pool ? hipMallocFromPoolAsync(&p, bytes, pool, stream) : hipMallocAsync(&p, bytes, stream);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     p = nullptr;
   }

@@ -340,7 +340,7 @@ struct Query {
   std::vector<hpop_event_chunk> chunks;  // device pointers, or pointers into `host`
   std::vector<int64_t> host;             // copied host records (start arrays then end arrays)
   long long n_records = 0;
-  std::chrono::steady_clock::time_point submitted;
+  std::chrono::steady_clock::time_point submitted, finished;
   bool done = false;
   hpop_status status = HPOP_OK;
   std::string error;
@@ -549,6 +549,8 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   if (e == hipSuccess) e = hipMemcpyAsync(S->d_reqs.ptr, h + b_lists + b_items, b_reqs, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return err = hipGetErrorString(e), HPOP_E_HIP;
   const Plan& P = En.ws.plan;
+  char* o = hres + sizeof(ServCtl);  // results: trees, lists, error flags
+  // one synchronisation per step: the scratch check travels back with the results
   for (int attempt = 0; attempt < 4; ++attempt) {
     ServCtl ctl{0, (unsigned long long)S->pool_cap, 0, 0};
     memcpy(hres, &ctl, sizeof ctl);
@@ -562,14 +564,21 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
                          (const ServItem*)S->d_items.ptr, P, (ListDev*)S->d_lists.ptr, (Elem*)S->d_pool.ptr,
                          (const ServCtl*)S->d_ctl.ptr);
     }
+    // on a scratch overflow no list was written and these trees are discarded
+    hipLaunchKernelGGL(k_serv_region, dim3((unsigned)(2 * nq)), dim3(256), 0, st, (const ServReq*)S->d_reqs.ptr,
+                       (const ListDev*)S->d_lists.ptr, (const long long*)S->d_frontier.ptr, (Tree*)S->d_trees.ptr);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(hres, S->d_ctl.ptr, sizeof(ServCtl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(o, S->d_trees.ptr, b_trees, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && b_lists)
+      e = hipMemcpyAsync(o + b_trees, S->d_lists.ptr, b_lists, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(o + b_trees + b_lists, P.owner_err, nq * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return err = std::string("serving step: ") + hipGetErrorString(e), HPOP_E_HIP;
     ServCtl got;
     memcpy(&got, hres, sizeof got);
     if (!got.pool_overflow) break;
-    // a long overlap needed more scratch: grow the pool and redo prep and splice (no list was written)
+    // a long overlap needed more scratch: grow the pool and redo prep, splice and region
     const long long np = (long long)(got.pool_used + got.pool_overflow + 4096) * 2;
     S->d_pool.release(A);
     if (!ensure(S->d_pool, A, (size_t)np * sizeof(Elem))) {
@@ -582,15 +591,6 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
       return HPOP_E_OOM;
     }
   }
-  hipLaunchKernelGGL(k_serv_region, dim3((unsigned)(2 * nq)), dim3(256), 0, st, (const ServReq*)S->d_reqs.ptr,
-                     (const ListDev*)S->d_lists.ptr, (const long long*)S->d_frontier.ptr, (Tree*)S->d_trees.ptr);
-  e = hipGetLastError();
-  char* o = hres;
-  if (e == hipSuccess) e = hipMemcpyAsync(o, S->d_trees.ptr, b_trees, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess && b_lists) e = hipMemcpyAsync(o + b_trees, S->d_lists.ptr, b_lists, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(o + b_trees + b_lists, P.owner_err, nq * 4, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return err = std::string("serving step: ") + hipGetErrorString(e), HPOP_E_HIP;
   unsigned long long slot_over;
   memcpy(&slot_over, (const char*)En.ws.pinned.ptr + 16, 8);
   if (slot_over && !En.exact_forced) {
@@ -655,6 +655,7 @@ void worker_loop(hpop_server* S) {
         Q->error = err;
       }
       Q->done = true;
+      Q->finished = now;
       S->inflight_bytes -= Q->n_records * 16;
       if (Q->status == HPOP_OK) {
         ++S->completed;
@@ -664,6 +665,35 @@ void worker_loop(hpop_server* S) {
     }
     S->cv_done.notify_all();
   }
+}
+
+// Waits for a ticket and releases it; `finished` receives its completion time.
+hpop_status wait_ticket(hpop_server* S, uint64_t ticket, int64_t timeout_ns, hpop_metric_tree* out_region,
+                        hpop_metric_tree* out_global, std::chrono::steady_clock::time_point* finished) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end()) {
+    S->last_error = "unknown ticket";
+    return HPOP_E_ARG;
+  }
+  Query* Q = it->second;
+  if (timeout_ns < 0) {
+    S->cv_done.wait(lk, [&] { return Q->done; });
+  } else if (!S->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [&] { return Q->done; })) {
+    S->last_error = "timed out";
+    return HPOP_E_TIMEOUT;
+  }
+  const hpop_status st = Q->status;
+  if (st == HPOP_OK) {
+    if (out_region) *out_region = Q->region;
+    if (out_global) *out_global = Q->global;
+  } else {
+    S->last_error = Q->error;
+  }
+  if (finished) *finished = Q->finished;
+  S->tickets.erase(it);
+  delete Q;
+  return st;
 }
 
 }  // namespace
@@ -849,29 +879,7 @@ hpop_status hpop_server_submit(hpop_server* S, int32_t sid, const hpop_event_chu
 hpop_status hpop_server_wait(hpop_server* S, uint64_t ticket, int64_t timeout_ns, hpop_metric_tree* out_region,
                              hpop_metric_tree* out_global) {
   if (!S) return srv_fail(nullptr, HPOP_E_ARG, "null server");
-  std::unique_lock<std::mutex> lk(S->mu);
-  auto it = S->tickets.find(ticket);
-  if (it == S->tickets.end()) {
-    S->last_error = "unknown ticket";
-    return HPOP_E_ARG;
-  }
-  Query* Q = it->second;
-  if (timeout_ns < 0) {
-    S->cv_done.wait(lk, [&] { return Q->done; });
-  } else if (!S->cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), [&] { return Q->done; })) {
-    S->last_error = "timed out";
-    return HPOP_E_TIMEOUT;
-  }
-  const hpop_status st = Q->status;
-  if (st == HPOP_OK) {
-    if (out_region) *out_region = Q->region;
-    if (out_global) *out_global = Q->global;
-  } else {
-    S->last_error = Q->error;
-  }
-  S->tickets.erase(it);
-  delete Q;
-  return st;
+  return wait_ticket(S, ticket, timeout_ns, out_region, out_global, nullptr);
 }
 
 hpop_status hpop_server_get_stats(hpop_server* S, hpop_server_stats* out) {
@@ -888,6 +896,67 @@ hpop_status hpop_server_get_stats(hpop_server* S, hpop_server_stats* out) {
   out->p99_us = pct(0.99);
   out->max_us = v.empty() ? 0.0 : v.back();
   return HPOP_OK;
+}
+
+hpop_status hpop_server_replay(hpop_server* S, const hpop_replay_query* qs, int32_t n, int32_t mem_space,
+                               hpop_metric_tree* out_region, hpop_metric_tree* out_global, int64_t* latency_ns,
+                               int64_t* out_wall_ns, int64_t* out_busy) {
+  using clk = std::chrono::steady_clock;
+  if (!S || n < 0 || (n > 0 && !qs)) return srv_fail(S, HPOP_E_ARG, "bad arguments");
+  for (int32_t i = 1; i < n; ++i)
+    if (qs[i].arrival_ns < qs[i - 1].arrival_ns) return srv_fail(S, HPOP_E_ARG, "arrival times must not decrease");
+  std::vector<uint64_t> tickets((size_t)n, 0);
+  std::vector<char> submitted((size_t)n, 0);
+  hpop_status first = HPOP_OK;
+  std::string first_err;
+  long long busy = 0;
+  const clk::time_point t_start = clk::now();
+  for (int32_t i = 0; i < n; ++i) {
+    const clk::time_point due = t_start + std::chrono::nanoseconds(qs[i].arrival_ns);
+    // sleep while the arrival is far, spin for the last stretch
+    while (true) {
+      const auto left = due - clk::now();
+      if (left <= std::chrono::nanoseconds(0)) break;
+      if (left > std::chrono::microseconds(200)) std::this_thread::sleep_for(left - std::chrono::microseconds(100));
+    }
+    hpop_status st;
+    while ((st = hpop_server_submit(S, qs[i].sid, qs[i].chunks, qs[i].n_chunks, mem_space, qs[i].t0, qs[i].t1,
+                                    &tickets[i])) == HPOP_E_BUSY) {
+      ++busy;
+      std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    if (st == HPOP_OK) {
+      submitted[i] = 1;
+    } else if (first == HPOP_OK) {
+      first = st;
+      first_err = hpop_server_last_error(S);
+    }
+  }
+  clk::time_point last = t_start;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!submitted[i]) continue;
+    clk::time_point fin;
+    const hpop_status st = wait_ticket(S, tickets[i], -1, out_region ? out_region + i : nullptr,
+                                       out_global ? out_global + i : nullptr, &fin);
+    if (st != HPOP_OK) {
+      if (first == HPOP_OK) {
+        first = st;
+        first_err = hpop_server_last_error(S);
+      }
+      continue;
+    }
+    last = std::max(last, fin);
+    if (latency_ns)
+      latency_ns[i] = std::chrono::duration_cast<std::chrono::nanoseconds>(
+                          fin - (t_start + std::chrono::nanoseconds(qs[i].arrival_ns))).count();
+  }
+  if (out_wall_ns) *out_wall_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(last - t_start).count();
+  if (out_busy) *out_busy = busy;
+  if (first != HPOP_OK) {
+    std::lock_guard<std::mutex> g(S->mu);
+    S->last_error = first_err;
+  }
+  return first;
 }
 
 const char* hpop_server_last_error(const hpop_server* S) {

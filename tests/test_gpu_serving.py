@@ -183,3 +183,29 @@ def test_backpressure_busy():
             hp.hpop_server_wait(srv, t)
     finally:
         hp.hpop_server_destroy(srv)
+
+
+def test_replay_equals_oracle():
+    """The native load generator returns the same trees as submit/wait, with a
+    latency per query and a wall time covering every completion."""
+    ranks, n_sessions, n_queries = 2, 3, 4
+    plan = make_queries(41, n_sessions, ranks, n_queries)
+    srv = hp.hpop_server_create(max_sessions=4, max_inflight=4)
+    try:
+        sids = [hp.hpop_server_open_session(srv, ranks, ranks, origin) for origin, _ in plan]
+        queries, keys = [], []
+        for q in range(n_queries):
+            for s in range(n_sessions):
+                chunks, t0, t1 = plan[s][1][q]
+                queries.append((sids[s], as_payload(chunks, False), t0, t1, 200_000 * len(queries)))
+                keys.append((s, q))
+        reg, glob, lat, wall, busy = hp.hpop_server_replay(srv, queries, hp.HPOP_MEM_HOST)
+    finally:
+        hp.hpop_server_destroy(srv)
+    assert busy == 0
+    assert (lat > 0).all() and wall >= queries[-1][4] + lat[-1] - 1
+    for (s, q), r, g in zip(keys, reg, glob):
+        origin, qs = plan[s]
+        want = expected(ranks, origin, qs, q)
+        check_tree(r, want, 0, "replay session %d query %d region" % (s, q))
+        check_tree(g, want, 1, "replay session %d query %d global" % (s, q))
