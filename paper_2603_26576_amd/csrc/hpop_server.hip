@@ -72,6 +72,13 @@ struct ServReq {
   int32_t list_begin;  // list index of (resource 0, level 0); 3 slots per resource
 };
 
+// a list that moves to a new place in the list heap
+struct ListMove {
+  const Comp* src;
+  Comp* dst;
+  long long len;
+};
+
 struct ServCtl {
   unsigned long long pool_used;  // scratch records reserved by prep
   unsigned long long pool_cap;
@@ -287,6 +294,12 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   }
 }
 
+// grid (moves, k): workgroup y of a move copies every k-th run of 256 entries
+__global__ __launch_bounds__(256) void k_list_move(const ListMove* mv) {
+  const ListMove m = mv[blockIdx.x];
+  for (long long i = (long long)blockIdx.y * 256 + threadIdx.x; i < m.len; i += 256ll * gridDim.y) m.dst[i] = m.src[i];
+}
+
 __global__ __launch_bounds__(256) void k_serv_region(const ServReq* reqs, const ListDev* lists,
                                                      const long long* frontier, Tree* trees) {
   __shared__ long long lds[4 * 10];
@@ -354,8 +367,10 @@ struct SessionState {
   bool busy = false;  // a query of this session is in the current step
 };
 
+// A session list: `cap` entries from `off` in the server's list heap.
 struct ListHost {
-  DevBuf buf;
+  long long off = 0;
+  long long cap = 0;
   long long len = 0;
   long long total = 0;
 };
@@ -381,7 +396,9 @@ struct hpop_server {
   long long inflight_bytes = 0;
   // device buffers of a step
   Engine engine;  // the bucketed build of each step's records
-  DevBuf d_lists, d_items, d_reqs, d_pool, d_frontier, d_ctl, d_trees, d_stage;
+  DevBuf d_lists, d_items, d_reqs, d_pool, d_frontier, d_ctl, d_trees, d_stage, d_moves;
+  DevBuf heap;  // every session list, Comp entries; bump-allocated, compacted when full
+  long long heap_cap = 0, heap_used = 0;
   PinnedBuf h_stage, h_out;
   long long pool_cap = 0;
   // statistics
@@ -486,34 +503,107 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   hpop_tuning tun{};
   hpop_status rc = En.assemble_plan(tun, seg_count, seg_host, std::max(1, nq), 0, err);
   if (rc != HPOP_OK) return rc;
-  // ---- list capacity: a list grows by at most its level's new records
-  for (size_t i = 0; i < S->lists.size(); ++i) {
+  // ---- list capacity: a list grows by at most its level's new records. A list
+  // that outgrows its place moves to the end of the heap (at least doubling);
+  // when the heap is full, every list moves into a new heap twice the live
+  // size. All moves of a step are one kernel; the host tables change only
+  // once it is enqueued.
+  const size_t nl = S->lists.size();
+  std::vector<long long> n_off(nl), n_cap(nl);
+  long long grow = 0;
+  for (size_t i = 0; i < nl; ++i) {
+    const ListHost& L = S->lists[i];
+    n_off[i] = L.off;
+    n_cap[i] = L.cap;
     if (!level_new[i]) continue;
-    ListHost& L = S->lists[i];
-    const size_t need = (size_t)(L.len + level_new[i] + 1) * sizeof(Comp);
-    L.buf.used = (size_t)L.len * sizeof(Comp);
-    if (!L.buf.reserve(A, need, true)) {
-      err = "device allocation for a session list failed";
-      return HPOP_E_OOM;
+    const long long need = L.len + level_new[i] + 1;
+    if (need <= L.cap) continue;
+    n_cap[i] = (std::max({need, 2 * L.cap, 1024ll}) + 63) & ~63ll;
+    n_off[i] = -1;  // placed below
+    grow += n_cap[i];
+  }
+  std::vector<ListMove> moves;
+  DevBuf new_heap;
+  long long new_heap_cap = S->heap_cap, new_used = S->heap_used;
+  if (grow) {
+    Comp* old_base = (Comp*)S->heap.ptr;
+    if (S->heap_used + grow <= S->heap_cap) {
+      for (size_t i = 0; i < nl; ++i)
+        if (n_off[i] < 0) {
+          n_off[i] = new_used;
+          new_used += n_cap[i];
+          if (S->lists[i].len) moves.push_back({old_base + S->lists[i].off, old_base + n_off[i], S->lists[i].len});
+        }
+    } else {
+      long long live = 0;
+      for (size_t i = 0; i < nl; ++i) live += n_cap[i];
+      new_heap_cap = std::max(2 * live, 1ll << 16);
+      if (!new_heap.reserve(A, (size_t)new_heap_cap * sizeof(Comp), false)) {
+        err = "device allocation for the session lists failed";
+        return HPOP_E_OOM;
+      }
+      Comp* nb = (Comp*)new_heap.ptr;
+      new_used = 0;
+      for (size_t i = 0; i < nl; ++i) {
+        if (S->lists[i].len) moves.push_back({old_base + S->lists[i].off, nb + new_used, S->lists[i].len});
+        n_off[i] = new_used;
+        new_used += n_cap[i];
+      }
     }
   }
-  std::vector<ListDev> ld(S->lists.size());
-  for (size_t i = 0; i < S->lists.size(); ++i) {
-    ld[i].base = (Comp*)S->lists[i].buf.ptr;
+  if (!moves.empty() && !ensure(S->d_moves, A, moves.size() * sizeof(ListMove) + 64)) {
+    new_heap.release(A);
+    err = "device allocation for a serving step failed";
+    return HPOP_E_OOM;
+  }
+  Comp* heap_base = (Comp*)(new_heap.ptr ? new_heap.ptr : S->heap.ptr);
+  std::vector<ListDev> ld(nl);
+  for (size_t i = 0; i < nl; ++i) {
+    ld[i].base = heap_base + n_off[i];
     ld[i].len = S->lists[i].len;
     ld[i].total = S->lists[i].total;
-    ld[i].cap = (long long)(S->lists[i].buf.bytes / sizeof(Comp));
+    ld[i].cap = n_cap[i];
   }
   const int ni = (int)items.size();
   const size_t b_lists = ld.size() * sizeof(ListDev), b_items = items.size() * sizeof(ServItem),
-               b_reqs = reqs.size() * sizeof(ServReq), b_trees = 2 * (size_t)nq * sizeof(Tree);
+               b_reqs = reqs.size() * sizeof(ServReq), b_trees = 2 * (size_t)nq * sizeof(Tree),
+               b_moves = moves.size() * sizeof(ListMove);
   if (!ensure(S->d_lists, A, b_lists + 64) || !ensure(S->d_items, A, b_items + 64) ||
       !ensure(S->d_reqs, A, b_reqs + 64) || !ensure(S->d_ctl, A, sizeof(ServCtl)) ||
       !ensure(S->d_trees, A, b_trees + 64) ||
-      // pinned layout: lists, items, requests (uploads), then trees, lists, error flags (results)
-      !S->h_out.reserve(b_lists + b_items + b_reqs + b_trees + b_lists + 4 * (size_t)nq + sizeof(ServCtl) + 256)) {
+      // pinned layout: lists, items, requests, moves (uploads), then control, trees, lists, error flags
+      !S->h_out.reserve(b_lists + b_items + b_reqs + b_moves + sizeof(ServCtl) + b_trees + b_lists + 4 * (size_t)nq +
+                        256)) {
+    new_heap.release(A);
     err = "device allocation for a serving step failed";
     return HPOP_E_OOM;
+  }
+  // ---- list moves, then the new placement becomes the server's
+  if (!moves.empty()) {
+    char* hm = (char*)S->h_out.ptr + b_lists + b_items + b_reqs;
+    memcpy(hm, moves.data(), b_moves);
+    hipError_t e = hipMemcpyAsync(S->d_moves.ptr, hm, b_moves, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_list_move, dim3((unsigned)moves.size(), 8), dim3(256), 0, st,
+                         (const ListMove*)S->d_moves.ptr);
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(st);
+      new_heap.release(A);
+      err = std::string("list move: ") + hipGetErrorString(e);
+      return HPOP_E_HIP;
+    }
+  }
+  if (new_heap.ptr) {
+    S->heap.release(A);  // stream-ordered: after the moves out of it
+    S->heap = new_heap;
+    S->heap_cap = new_heap_cap;
+  }
+  S->heap_used = new_used;
+  for (size_t i = 0; i < nl; ++i) {
+    S->lists[i].off = n_off[i];
+    S->lists[i].cap = n_cap[i];
   }
   long long total_rec = 0;
   for (long long c : seg_count) total_rec += c;
@@ -542,7 +632,7 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   memcpy(h, ld.data(), b_lists);
   memcpy(h + b_lists, items.data(), b_items);
   memcpy(h + b_lists + b_items, reqs.data(), b_reqs);
-  char* hres = h + b_lists + b_items + b_reqs;
+  char* hres = h + b_lists + b_items + b_reqs + b_moves;
   hipError_t e = hipSuccess;
   if (b_lists) e = hipMemcpyAsync(S->d_lists.ptr, h, b_lists, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && b_items) e = hipMemcpyAsync(S->d_items.ptr, h + b_lists, b_items, hipMemcpyHostToDevice, st);
@@ -734,10 +824,10 @@ hpop_status hpop_server_destroy(hpop_server* S) {
   S->cv_work.notify_all();
   if (S->worker.joinable()) S->worker.join();
   (void)hipStreamSynchronize(S->stream);
-  for (auto& L : S->lists) L.buf.release(S->alloc);
+  S->heap.release(S->alloc);
   S->engine.release();
   for (DevBuf* b : {&S->d_lists, &S->d_items, &S->d_reqs, &S->d_pool, &S->d_frontier, &S->d_ctl, &S->d_trees,
-                    &S->d_stage})
+                    &S->d_stage, &S->d_moves})
     b->release(S->alloc);
   S->h_stage.release();
   S->h_out.release();
