@@ -497,19 +497,50 @@ __global__ __launch_bounds__(THREADS) void k_merge_block(Plan p) {
   }
 }
 
-// Wave path: each wave flattens one bucket of at most kWaveCap records whose
-// time width fits 32 bits, with no workgroup barrier. The sort is a counting
-// sort on the top bits of the start offset into 1024 sub-bins followed by an
-// insertion sort inside each sub-bin (records with equal starts may end in
-// any order: the flattened result does not depend on it). Buckets that do not
-// fit, or whose sub-bins are too crowded, go to the block path's queue.
-struct WaveSmem {
-  unsigned int key[kWaveCap];
-  long long eslot[kWaveCap];
-  unsigned short ord[kWaveCap];
-  unsigned short rank[kWaveCap];     // rank of a record inside its sub-bin
-  unsigned int bins[kWaveBins / 2];  // two 16-bit counters per word
+// Wave path: each wave sorts and flattens one bucket of at most kWaveCap
+// records with no workgroup barrier, in 32-bit arithmetic relative to the
+// bucket's first time `lo`. A record enters as
+//   key = (start - lo) << 2 | slot    (start - lo < 2^30: bucket width <= 2^30)
+//   end = end - lo + 1                (< 2^32; 0 stands for "before the bucket")
+// Comparisons, maxima and measure differences are unchanged by the common
+// shift, and the union measure of one bucket's records stays below 2^32, so
+// every quantity of the flatten fits 32 bits. The sort is a counting sort on
+// the top bits of the start into 128-1024 sub-bins, writing keys and ends to
+// their sorted places in LDS, then an insertion sort inside each sub-bin that
+// received two or more records (equal starts may end in any order: the merged
+// result does not depend on it). Buckets that do not fit (more records, a
+// wider bucket, an end 2^32 or more past lo, a crowded sub-bin) go to the
+// block path's queue.
+struct alignas(16) WaveSmem {
+  unsigned int key[kWaveCap];        // sorted keys
+  unsigned int end[kWaveCap];        // ends of the sorted records
+  unsigned int bins[kWaveBins / 2];  // two 16-bit counters (then sub-bin starts) per word
 };
+
+struct OpMaxU {
+  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a > b ? a : b; }
+};
+struct OpSumU {
+  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a + b; }
+};
+
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ unsigned int dpp32(unsigned int old, unsigned int v) {
+  return (unsigned int)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+}
+
+// Exclusive scan over the 64 lanes (lane order) with identity `id`, and the total.
+template <class Op>
+__device__ __forceinline__ unsigned int wave_excl_scan_u32(unsigned int x, unsigned int id, unsigned int& total) {
+  x = Op::apply(x, dpp32<kDppRowShr1, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr2, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr4, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr8, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowBcast15, 0xa, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowBcast31, 0xc, 0xf>(id, x));
+  total = (unsigned int)__builtin_amdgcn_readlane((int)x, 63);
+  return dpp32<kDppWaveShr1, 0xf, 0xf>(id, x);
+}
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -517,22 +548,24 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int K, class Op>
-__device__ __forceinline__ void wave_excl_scan(const long long (&v)[K], long long (&ex)[K], long long (&tot)[K],
-                                               long long ident) {
-  const int lane = threadIdx.x & 63;
+// N consecutive LDS words from a position that is a multiple of N
+template <int N>
+__device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (&dst)[N]) {
+  if constexpr (N == 1) {
+    dst[0] = src[0];
+  } else if constexpr (N == 2) {
+    const uint2 v = *(const uint2*)src;
+    dst[0] = v.x;
+    dst[1] = v.y;
+  } else {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    long long x = v[k];
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const long long y = __shfl_up(x, d, 64);
-      if (lane >= d) x = Op::apply(x, y);
+    for (int j = 0; j < N; j += 4) {
+      const uint4 v = *(const uint4*)(src + j);
+      dst[j] = v.x;
+      dst[j + 1] = v.y;
+      dst[j + 2] = v.z;
+      dst[j + 3] = v.w;
     }
-    long long e = __shfl_up(x, 1, 64);
-    if (lane == 0) e = ident;
-    ex[k] = e;
-    tot[k] = __shfl(x, 63, 64);
   }
 }
 
@@ -543,44 +576,39 @@ template <int IPL, int NLEV>
 __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, long long gb, long long off, int ni,
                                              long long lo) {
   const int lane = threadIdx.x & 63;
-  const int ipl = (ni + 63) >> 6;
-  const int q0 = lane * ipl;
-  const int cnt = min(max(ni - q0, 0), ipl);
-  constexpr long long EMASK = (1ll << kSlotShift) - 1;
-  long long sv[IPL], ev[IPL];
+  const int q0 = lane * IPL;
+  const int cnt = min(max(ni - q0, 0), IPL);
+  unsigned int kv[IPL], ev[IPL];
+  lds_load<IPL>(W.key + q0, kv);
+  lds_load<IPL>(W.end + q0, ev);
+  unsigned int sv[IPL];
   int sl[IPL];
-  long long tmax[NLEV];
+  unsigned int tmax[NLEV];
 #pragma unroll
-  for (int l = 0; l < NLEV; ++l) tmax[l] = LLONG_MIN;
+  for (int l = 0; l < NLEV; ++l) tmax[l] = 0;
 #pragma unroll
   for (int j = 0; j < IPL; ++j) {
-    sv[j] = 0;
-    ev[j] = 0;
-    sl[j] = 3;
-    if (j < cnt) {
-      const int i = W.ord[q0 + j];
-      const long long es = W.eslot[i];
-      sv[j] = lo + (long long)W.key[i];
-      ev[j] = es & EMASK;
-      sl[j] = (int)((unsigned long long)es >> kSlotShift);
+    sv[j] = (kv[j] >> 2) + 1;  // start - lo + 1, the same shift as the ends
+    sl[j] = j < cnt ? (int)(kv[j] & 3u) : 3;
 #pragma unroll
-      for (int l = 0; l < NLEV; ++l)
-        if (sl[j] <= l && ev[j] > tmax[l]) tmax[l] = ev[j];
-    }
+    for (int l = 0; l < NLEV; ++l)
+      if (sl[j] <= l && ev[j] > tmax[l]) tmax[l] = ev[j];
   }
-  long long M[NLEV];
+  // the largest end before each lane: earlier lanes, else the earlier buckets
+  unsigned int M[NLEV];
 #pragma unroll
   for (int l = 0; l < NLEV; ++l) {
-    long long tot;
-    const long long ex = wave_excl_scan_dpp<OpMax>(tmax[l], LLONG_MIN, tot);
+    unsigned int tot;
+    const unsigned int ex = wave_excl_scan_u32<OpMaxU>(tmax[l], 0u, tot);
     const long long c = p.carry[gb * 3 + l];
-    M[l] = ex > c ? ex : c;
+    const unsigned int cr = c < lo ? 0u : (c - lo >= 0xFFFFFFFFll ? 0xFFFFFFFFu : (unsigned int)(c - lo + 1));
+    M[l] = ex > cr ? ex : cr;
   }
-  // per-lane measure per level; the break counts packed in 16-bit fields
-  long long acc[NLEV];
-  long long nbrk = 0;
+  // per-lane measure per level; break counts packed in 10-bit fields (<= 512 each)
+  unsigned int acc[NLEV];
+  unsigned int nbrk = 0;
   {
-    long long Mb[NLEV];
+    unsigned int Mb[NLEV];
 #pragma unroll
     for (int l = 0; l < NLEV; ++l) {
       Mb[l] = M[l];
@@ -590,49 +618,159 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, l
     for (int j = 0; j < IPL; ++j) {
 #pragma unroll
       for (int l = 0; l < NLEV; ++l) {
-        if (j < cnt && sl[j] <= l) {
-          const long long b = sv[j] > Mb[l] ? sv[j] : Mb[l];
+        if (sl[j] <= l) {
+          const unsigned int b = sv[j] > Mb[l] ? sv[j] : Mb[l];
           if (ev[j] > b) acc[l] += ev[j] - b;
-          if (sv[j] > Mb[l]) nbrk += 1ll << (16 * l);
+          if (sv[j] > Mb[l]) nbrk += 1u << (10 * l);
           if (ev[j] > Mb[l]) Mb[l] = ev[j];
         }
       }
     }
   }
-  long long P[NLEV], totp[NLEV];
+  unsigned int P[NLEV], totp[NLEV];
 #pragma unroll
-  for (int l = 0; l < NLEV; ++l) P[l] = wave_excl_scan_dpp<OpSum>(acc[l], 0, totp[l]);
-  long long totr;
-  const long long Rp = wave_excl_scan_dpp<OpSum>(nbrk, 0, totr);
-  long long R[NLEV];
+  for (int l = 0; l < NLEV; ++l) P[l] = wave_excl_scan_u32<OpSumU>(acc[l], 0u, totp[l]);
+  unsigned int totr;
+  const unsigned int Rp = wave_excl_scan_u32<OpSumU>(nbrk, 0u, totr);
+  unsigned int R[NLEV];
 #pragma unroll
-  for (int l = 0; l < NLEV; ++l) R[l] = (Rp >> (16 * l)) & 0xFFFF;
+  for (int l = 0; l < NLEV; ++l) R[l] = (Rp >> (10 * l)) & 0x3FFu;
 #pragma unroll
   for (int j = 0; j < IPL; ++j) {
 #pragma unroll
     for (int l = 0; l < NLEV; ++l) {
-      if (j < cnt && sl[j] <= l) {
+      if (sl[j] <= l) {
         if (sv[j] > M[l]) {
           Comp c;
-          c.cs = sv[j];
-          c.pl = P[l];
+          c.cs = lo + (long long)(sv[j] - 1);
+          c.pl = (long long)P[l];
           p.comp[l][off + R[l]] = c;
           R[l] += 1;
         }
-        const long long b = sv[j] > M[l] ? sv[j] : M[l];
+        const unsigned int b = sv[j] > M[l] ? sv[j] : M[l];
         if (ev[j] > b) P[l] += ev[j] - b;
         if (ev[j] > M[l]) M[l] = ev[j];
       }
     }
   }
   if (lane < 3) {
-    long long bs = 0;
+    unsigned int bs = 0;
 #pragma unroll
     for (int l = 0; l < NLEV; ++l)
       if (lane == l) bs = totp[l];
-    p.bsum[gb * 3 + lane] = bs;
-    p.ncomp[gb * 3 + lane] = (unsigned int)((totr >> (16 * lane)) & 0xFFFF);
+    p.bsum[gb * 3 + lane] = (long long)bs;
+    p.ncomp[gb * 3 + lane] = (totr >> (10 * lane)) & 0x3FFu;
   }
+}
+
+// Sort of one bucket of ni <= 64*IPL records into W, then its flatten.
+// Returns false (nothing written) when the bucket must take the block path.
+template <int IPL>
+__device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
+                                            long long lo, const Elem* rec, int nlev) {
+  const int lane = threadIdx.x & 63;
+  constexpr long long EMASK = (1ll << kSlotShift) - 1;
+  unsigned int kr[IPL], er[IPL], rk[IPL];
+  unsigned int kor = 0;
+  bool far = false;
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    const int i = lane + 64 * r;
+    kr[r] = 0;
+    er[r] = 0;
+    if (i < ni) {
+      const Elem el = rec[i];
+      const unsigned int k = (unsigned int)(el.s - lo);
+      const long long e = (el.e_slot & EMASK) - lo;
+      far |= e >= 0xFFFFFFFFll;
+      kr[r] = (k << 2) | (unsigned int)((unsigned long long)el.e_slot >> kSlotShift);
+      er[r] = (unsigned int)(e + 1);
+      kor |= k;
+    }
+  }
+  if (__ballot(far)) return false;
+  for (int d = 32; d >= 1; d >>= 1) kor |= __shfl_xor(kor, d, 64);
+  // sub-bins: about two per record, 128 .. 1024; a lane owns bpl of them (two per LDS word)
+  int dbits = 7;
+  while ((1 << dbits) < 2 * ni && dbits < 10) ++dbits;
+  const int nbins = 1 << dbits, wpl = nbins >> 7;
+  for (int j = 0; j < wpl; ++j) W.bins[lane * wpl + j] = 0;
+  wave_sync();
+  const int hb = kor ? 32 - __clz((int)kor) : 0;
+  const int dsh = hb > dbits ? hb - dbits : 0;  // sub-bin = (key >> 2) >> dsh
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    if (lane + 64 * r < ni) {
+      const unsigned int d = (kr[r] >> 2) >> dsh;
+      const unsigned int sh = 16u * (d & 1u);
+      rk[r] = (atomicAdd(&W.bins[d >> 1], 1u << sh) >> sh) & 0xFFFFu;
+    }
+  }
+  wave_sync();
+  // exclusive scan of the sub-bin counters (lane order = sub-bin order)
+  unsigned int tot = 0;
+  for (int j = 0; j < wpl; ++j) {
+    const unsigned int w = W.bins[lane * wpl + j];
+    tot += (w & 0xFFFFu) + (w >> 16);
+  }
+  unsigned int all;
+  unsigned int run = wave_excl_scan_u32<OpSumU>(tot, 0u, all);
+  wave_sync();
+  for (int j = 0; j < wpl; ++j) {
+    const unsigned int w = W.bins[lane * wpl + j];
+    const unsigned int a = run, b = run + (w & 0xFFFFu);
+    run = b + (w >> 16);
+    W.bins[lane * wpl + j] = a | (b << 16);
+  }
+  wave_sync();
+  unsigned int fix = 0;  // bit r: the record of round r is the second one of its sub-bin
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    if (lane + 64 * r < ni) {
+      const unsigned int d = (kr[r] >> 2) >> dsh;
+      const unsigned int pos = ((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu) + rk[r];
+      W.key[pos] = kr[r];
+      W.end[pos] = er[r];
+      if (rk[r] == 1) fix |= 1u << r;
+    }
+  }
+  wave_sync();
+  // order inside each sub-bin by the full key: one lane per sub-bin holding
+  // two or more records (the lane that placed its second record)
+  bool crowded = false;
+  if (dsh > 0) {
+#pragma unroll
+    for (int r = 0; r < IPL; ++r) {
+      if (fix & (1u << r)) {
+        const unsigned int d = (kr[r] >> 2) >> dsh;
+        const int st0 = (int)((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu);
+        const int st1 = (int)d + 1 < nbins ? (int)((W.bins[(d + 1) >> 1] >> (16u * ((d + 1) & 1u))) & 0xFFFFu) : ni;
+        const int c = st1 - st0;
+        if (c > 32) {
+          crowded = true;
+        } else {
+          unsigned int* ko = W.key + st0;
+          unsigned int* eo = W.end + st0;
+          for (int a = 1; a < c; ++a) {
+            const unsigned int kx = ko[a], ex = eo[a];
+            int b = a - 1;
+            while (b >= 0 && ko[b] > kx) {
+              ko[b + 1] = ko[b];
+              eo[b + 1] = eo[b];
+              --b;
+            }
+            ko[b + 1] = kx;
+            eo[b + 1] = ex;
+          }
+        }
+      }
+    }
+  }
+  if (__ballot(crowded)) return false;
+  wave_sync();
+  if (nlev == 2) wave_flatten<IPL, 2>(p, W, gb, off, ni, lo);
+  else wave_flatten<IPL, 3>(p, W, gb, off, ni, lo);
+  return true;
 }
 
 __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
@@ -646,7 +784,6 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
   const Geom g = seg_geom(p.stats[seg], sd);
   const long long n = p.counts[gb];
   const long long off = (long long)p.offsets[gb];
-  const int nlev = sd.n_levels;
   if (n == 0) {
     if (lane < 3) {
       p.bsum[gb * 3 + lane] = 0;
@@ -654,108 +791,18 @@ __global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
     }
     return;
   }
-  if (n > kWaveCap || g.shift > 32) {
-    if (lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
-    return;
+  bool done = false;
+  if (n <= kWaveCap && g.shift <= 30) {
+    const int ni = (int)n;
+    const long long lo = g.min_s + ((gb - sd.bucket_begin) << g.shift);
+    const Elem* rec = p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + off;
+    const int nlev = sd.n_levels;
+    if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, lo, rec, nlev);
+    else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, lo, rec, nlev);
+    else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, lo, rec, nlev);
+    else done = wave_bucket<8>(p, W, gb, off, ni, lo, rec, nlev);
   }
-  const int ni = (int)n;
-  const long long lo = g.min_s + ((gb - sd.bucket_begin) << g.shift);
-  const Elem* rec = p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + off;
-  // load; find the highest varying key bit
-  unsigned int kor = 0;
-  for (int i = lane; i < ni; i += 64) {
-    const Elem el = rec[i];
-    const unsigned int k = (unsigned int)(el.s - lo);
-    W.key[i] = k;
-    W.eslot[i] = el.e_slot;
-    kor |= k;
-  }
-  for (int d = 32; d >= 1; d >>= 1) kor |= __shfl_xor(kor, d, 64);
-  // sub-bins: about two per record, 128 .. 1024; a lane owns bpl of them (two per LDS word)
-  int dbits = 7;
-  while ((1 << dbits) < 2 * ni && dbits < 10) ++dbits;
-  const int nbins = 1 << dbits, bpl = nbins >> 6, wpl = bpl >> 1;
-  for (int j = 0; j < wpl; ++j) W.bins[lane * wpl + j] = 0;
-  wave_sync();
-  const int hb = kor ? 32 - __clz((int)kor) : 0;
-  const int dsh = hb > dbits ? hb - dbits : 0;  // sub-bin = key >> dsh
-  for (int i = lane; i < ni; i += 64) {
-    const unsigned int d = W.key[i] >> dsh;
-    const unsigned int sh = 16u * (d & 1u);
-    W.rank[i] = (unsigned short)((atomicAdd(&W.bins[d >> 1], 1u << sh) >> sh) & 0xFFFFu);
-  }
-  wave_sync();
-  // exclusive scan of the sub-bin counters (lane order = sub-bin order)
-  long long tot = 0;
-  for (int j = 0; j < wpl; ++j) {
-    const unsigned int w = W.bins[lane * wpl + j];
-    tot += (w & 0xFFFFu) + (w >> 16);
-  }
-  long long all;
-  unsigned int run = (unsigned int)wave_excl_scan_dpp<OpSum>(tot, 0, all);
-  wave_sync();
-  for (int j = 0; j < wpl; ++j) {
-    const unsigned int w = W.bins[lane * wpl + j];
-    const unsigned int a = run, b = run + (w & 0xFFFFu);
-    run = b + (w >> 16);
-    W.bins[lane * wpl + j] = a | (b << 16);
-  }
-  wave_sync();
-  unsigned int fix = 0;  // bit r: the record of round r is the second one of its sub-bin
-  for (int i = lane, r = 0; i < ni; i += 64, ++r) {
-    const unsigned int d = W.key[i] >> dsh;
-    const unsigned int st0 = (W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu;
-    const unsigned int rk = W.rank[i];
-    W.ord[st0 + rk] = (unsigned short)i;
-    if (rk == 1) fix |= 1u << r;
-  }
-  wave_sync();
-  // order inside each sub-bin by the full key: one lane per sub-bin holding
-  // two or more records (the lane that placed its second record)
-  bool crowded = false;
-  if (dsh > 0) {
-    while (fix) {
-      const int r = __ffs((int)fix) - 1;
-      fix &= fix - 1;
-      const unsigned int d = W.key[r * 64 + lane] >> dsh;
-      const int st0 = (int)((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu);
-      const int st1 = (int)d + 1 < nbins ? (int)((W.bins[(d + 1) >> 1] >> (16u * ((d + 1) & 1u))) & 0xFFFFu) : ni;
-      const int c = st1 - st0;
-      if (c > 32) {
-        crowded = true;
-        continue;
-      }
-      unsigned short* o = W.ord + st0;
-      for (int a = 1; a < c; ++a) {
-        const unsigned short x = o[a];
-        const unsigned int kx = W.key[x];
-        int b = a - 1;
-        while (b >= 0 && W.key[o[b]] > kx) {
-          o[b + 1] = o[b];
-          --b;
-        }
-        o[b + 1] = x;
-      }
-    }
-  }
-  if (__ballot(crowded)) {
-    if (lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
-    return;
-  }
-  wave_sync();
-  // flatten: lane owns sorted positions [q0, q0 + cnt); specialised by records per lane and levels
-  const int ipl = (ni + 63) >> 6;
-  if (nlev == 2) {
-    if (ipl <= 1) wave_flatten<1, 2>(p, W, gb, off, ni, lo);
-    else if (ipl <= 2) wave_flatten<2, 2>(p, W, gb, off, ni, lo);
-    else if (ipl <= 4) wave_flatten<4, 2>(p, W, gb, off, ni, lo);
-    else wave_flatten<8, 2>(p, W, gb, off, ni, lo);
-  } else {
-    if (ipl <= 1) wave_flatten<1, 3>(p, W, gb, off, ni, lo);
-    else if (ipl <= 2) wave_flatten<2, 3>(p, W, gb, off, ni, lo);
-    else if (ipl <= 4) wave_flatten<4, 3>(p, W, gb, off, ni, lo);
-    else wave_flatten<8, 3>(p, W, gb, off, ni, lo);
-  }
+  if (!done && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
 }
 
 // ----------------------------------------------------------------------------

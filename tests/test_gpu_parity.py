@@ -122,6 +122,34 @@ def test_crowded_sub_bins_fall_back_to_block_path():
     check(tr2)
 
 
+def test_long_intervals_and_wide_buckets():
+    """Buckets the wave path's 32-bit form cannot hold: records ending 2^32 ns
+    or more after their bucket's start, and sparse resources whose buckets are
+    wider than 2^30 ns. They take the block path; the rest stays on the wave
+    path, and the carry between the two kinds of bucket must line up."""
+    rng = np.random.default_rng(13)
+    chunks = []
+    # dense resource with a few very long records sprinkled in
+    s = np.sort(rng.integers(0, 1 << 34, size=60000)).astype(np.int64)
+    e = s + rng.integers(0, 2000, size=s.size)
+    far = rng.random(s.size) < 0.002
+    e[far] = s[far] + rng.integers(1 << 32, 1 << 35, size=int(far.sum()))
+    k = rng.random(s.size) < 0.35
+    chunks += [tg.Chunk(0, tg.DEV_KERNEL, s[~k], e[~k]), tg.Chunk(0, tg.DEV_MEMOP, s[k], e[k])]
+    # sparse resource: 3000 records over 2^45 ns, buckets far wider than 2^30
+    s2 = np.sort(rng.integers(0, 1 << 45, size=3000)).astype(np.int64)
+    e2 = s2 + rng.integers(0, 1 << 40, size=s2.size)
+    chunks.append(tg.Chunk(1, tg.DEV_KERNEL, s2, e2))
+    # host with long MPI states next to short useful ones
+    s3 = np.sort(rng.integers(0, 1 << 36, size=20000)).astype(np.int64)
+    kinds = rng.integers(0, 3, size=s3.size)
+    e3 = s3 + np.where(kinds == 2, rng.integers(1 << 31, 1 << 33, size=s3.size), rng.integers(0, 5000, size=s3.size))
+    host = [tg.Chunk(0, kd, s3[kinds == kd], e3[kinds == kd]) for kd in (tg.HOST_USEFUL, tg.HOST_OFFLOAD, tg.HOST_MPI)]
+    regions = [(0, 1 << 46), (1 << 20, 1 << 33), (5 << 30, 7 << 30)]
+    check(tg.Trace(0, 2, chunks, regions))
+    check(tg.Trace(1, 0, host, regions))
+
+
 def test_identical_starts_and_degenerate_intervals():
     n = 5000
     s = np.full(n, 7_000_000, np.int64)
