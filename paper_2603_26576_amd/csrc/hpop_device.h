@@ -37,6 +37,40 @@ __device__ __forceinline__ Geom seg_geom(const SegStats& st, const SegDesc& sd) 
   return g;
 }
 
+// first time of bucket b (segment-relative) of a segment
+__device__ __forceinline__ long long bucket_lo(const Geom& g, long long b) { return g.min_s + (b << g.shift); }
+
+__device__ __forceinline__ bool seg_narrow(const Geom& g) { return g.shift <= kNarrowShift; }
+
+// The components of one bucket at one level, in either storage form.
+struct CompView {
+  const Comp* wide;     // wide segments
+  const CompN* narrow;  // narrow segments: relative to lo
+  long long lo;
+  __device__ __forceinline__ long long cs(long long k) const {
+    return narrow ? lo + (long long)narrow[k].cs : wide[k].cs;
+  }
+  __device__ __forceinline__ long long pl(long long k) const {
+    return narrow ? (long long)narrow[k].pl : wide[k].pl;
+  }
+};
+
+__device__ __forceinline__ CompView comp_view(const Plan& p, const Geom& g, long long bucket_begin, long long gb,
+                                              int l) {
+  CompView v;
+  const long long off = (long long)p.offsets[gb];
+  if (seg_narrow(g)) {
+    v.wide = nullptr;
+    v.narrow = p.compn[l] + off;
+    v.lo = bucket_lo(g, gb - bucket_begin);
+  } else {
+    v.wide = p.comp[l] + off;
+    v.narrow = nullptr;
+    v.lo = 0;
+  }
+  return v;
+}
+
 // bucket of a record start inside its segment (clamped; start >= min_s for valid records)
 __device__ __forceinline__ int bucket_of(long long s, const Geom& g) {
   unsigned long long rel = (unsigned long long)(s - g.min_s);
@@ -211,11 +245,12 @@ struct FlatState {
 };
 
 // Flatten one sorted tile: positions 0..n-1 in order ord (or identity).
-// Writes components of each level at comp[l][off + R], advances `st`.
+// Writes components of each level at comp[l][off + R], or in the narrow form
+// relative to `nlo` at compn[l][off + R] when compn is given; advances `st`.
 template <int THREADS>
 __device__ __forceinline__ void flatten_tile(const Elem* E, const unsigned short* ord, int n, int nlev,
-                                             long long off, Comp* const* comp, FlatState& st, long long* lds_scan,
-                                             long long* lds_bc) {
+                                             long long off, Comp* const* comp, CompN* const* compn, long long nlo,
+                                             FlatState& st, long long* lds_scan, long long* lds_bc) {
   const int ipt = (n + THREADS - 1) / THREADS;
   const int p0 = threadIdx.x * ipt;
   const int p1 = min(n, p0 + ipt);
@@ -274,10 +309,17 @@ __device__ __forceinline__ void flatten_tile(const Elem* E, const unsigned short
       for (int l = 0; l < 3; ++l) {
         if (l < nlev && slot <= l) {
           if (s > M[l]) {
-            Comp c;
-            c.cs = s;
-            c.pl = P[l];
-            comp[l][off + R[l]] = c;
+            if (compn) {
+              CompN c;
+              c.cs = (uint32_t)(s - nlo);
+              c.pl = (uint32_t)P[l];
+              compn[l][off + R[l]] = c;
+            } else {
+              Comp c;
+              c.cs = s;
+              c.pl = P[l];
+              comp[l][off + R[l]] = c;
+            }
             R[l] += 1;
           }
           const long long lo = s > M[l] ? s : M[l];

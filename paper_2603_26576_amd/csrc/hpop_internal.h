@@ -84,6 +84,15 @@ struct Comp {  // one merged component inside a bucket
   int64_t pl;  // measure of the level before cs, counted from the bucket's start (with carry)
 };
 
+// A component of a segment whose buckets are at most 2^kNarrowShift ns wide:
+// its start and its measure before it are both below the bucket width, so
+// both fit 32 bits relative to the bucket's first time (8 B instead of 16).
+struct CompN {
+  uint32_t cs;  // start - first time of the bucket
+  uint32_t pl;  // as Comp::pl
+};
+constexpr int kNarrowShift = 30;
+
 struct Elem {  // one record regrouped by bucket
   int64_t s;
   int64_t e_slot;  // end | slot << 62
@@ -113,7 +122,8 @@ struct Plan {
   long long* seg_total;              // [n_segs][3]
   Elem* elems;                       // [n_elems]
   Elem* elems2;                      // [n_elems] scratch for oversized buckets
-  Comp* comp[kLevels];               // [n_elems] each
+  Comp* comp[kLevels];               // [n_elems] each: components of wide segments
+  CompN* compn[kLevels];             // [n_elems] each: components of narrow segments
   int64_t n_elems;
   unsigned long long* err;           // [0] first bad record: chunk << 40 | index
   unsigned long long* scan_state;    // decoupled look-back words of the bucket scan

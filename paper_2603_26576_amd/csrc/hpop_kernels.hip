@@ -446,6 +446,8 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
     st.R[l] = 0;
   }
   Comp* comp[3] = {p.comp[0] + off, p.comp[1] + off, p.comp[2] + off};
+  CompN* compn_b[3] = {p.compn[0] + off, p.compn[1] + off, p.compn[2] + off};
+  CompN* const* compn = seg_narrow(g) ? compn_b : nullptr;
   if (n > 0) {
     const long long lo = g.min_s + (bl << g.shift);
     if (n <= CAP) {
@@ -454,7 +456,7 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
       for (int i = threadIdx.x; i < ni; i += THREADS) sm.E[i] = rec[i];  // coalesced 16 B per lane
       __syncthreads();
       const unsigned short* ord = sort_lds<THREADS, CAP>(sm, ni, lo);
-      flatten_tile<THREADS>(sm.E, ord, ni, nlev, 0, comp, st, sm.lds_scan, nullptr);
+      flatten_tile<THREADS>(sm.E, ord, ni, nlev, 0, comp, compn, lo, st, sm.lds_scan, nullptr);
     } else {
       // oversized bucket: stable LSD sort through global scratch, then flatten
       // CAP records at a time, carrying the running state across tiles
@@ -463,7 +465,7 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
         const int cnt = (int)min((long long)CAP, n - t0);
         for (int i = threadIdx.x; i < cnt; i += THREADS) sm.E[i] = src[t0 + i];
         __syncthreads();
-        flatten_tile<THREADS>(sm.E, nullptr, cnt, nlev, 0, comp, st, sm.lds_scan, nullptr);
+        flatten_tile<THREADS>(sm.E, nullptr, cnt, nlev, 0, comp, compn, lo, st, sm.lds_scan, nullptr);
         __syncthreads();
       }
     }
@@ -571,7 +573,10 @@ __device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (
 
 // Flatten of one sorted bucket by one wave: lane owns sorted positions
 // [lane*IPL, lane*IPL + cnt), kept in registers through the three phases
-// (running max of ends, measures and break counts, component writes).
+// (running max of ends, measures and break counts, component writes). A
+// record outside level l takes part as the empty pair (0, 0), which changes
+// no maximum, measure or break, so the phases need no branches; only the
+// component stores are conditional.
 template <int IPL, int NLEV>
 __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, long long gb, long long off, int ni,
                                              long long lo) {
@@ -581,76 +586,67 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, l
   unsigned int kv[IPL], ev[IPL];
   lds_load<IPL>(W.key + q0, kv);
   lds_load<IPL>(W.end + q0, ev);
-  unsigned int sv[IPL];
-  int sl[IPL];
-  unsigned int tmax[NLEV];
-#pragma unroll
-  for (int l = 0; l < NLEV; ++l) tmax[l] = 0;
+  unsigned int sv[IPL], sl[IPL];
 #pragma unroll
   for (int j = 0; j < IPL; ++j) {
-    sv[j] = (kv[j] >> 2) + 1;  // start - lo + 1, the same shift as the ends
-    sl[j] = j < cnt ? (int)(kv[j] & 3u) : 3;
-#pragma unroll
-    for (int l = 0; l < NLEV; ++l)
-      if (sl[j] <= l && ev[j] > tmax[l]) tmax[l] = ev[j];
+    sv[j] = (kv[j] >> 2) + 1;             // start - lo + 1, the same shift as the ends
+    sl[j] = j < cnt ? (kv[j] & 3u) : 3u;  // positions past the bucket belong to no level
   }
+  auto s_in = [&](int j, int l) { return sl[j] <= (unsigned int)l ? sv[j] : 0u; };
+  auto e_in = [&](int j, int l) { return sl[j] <= (unsigned int)l ? ev[j] : 0u; };
   // the largest end before each lane: earlier lanes, else the earlier buckets
   unsigned int M[NLEV];
 #pragma unroll
   for (int l = 0; l < NLEV; ++l) {
+    unsigned int tmax = 0;
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) tmax = max(tmax, e_in(j, l));
     unsigned int tot;
-    const unsigned int ex = wave_excl_scan_u32<OpMaxU>(tmax[l], 0u, tot);
+    const unsigned int ex = wave_excl_scan_u32<OpMaxU>(tmax, 0u, tot);
     const long long c = p.carry[gb * 3 + l];
     const unsigned int cr = c < lo ? 0u : (c - lo >= 0xFFFFFFFFll ? 0xFFFFFFFFu : (unsigned int)(c - lo + 1));
-    M[l] = ex > cr ? ex : cr;
+    M[l] = max(ex, cr);
   }
   // per-lane measure per level; break counts packed in 10-bit fields (<= 512 each)
   unsigned int acc[NLEV];
   unsigned int nbrk = 0;
-  {
-    unsigned int Mb[NLEV];
 #pragma unroll
-    for (int l = 0; l < NLEV; ++l) {
-      Mb[l] = M[l];
-      acc[l] = 0;
-    }
+  for (int l = 0; l < NLEV; ++l) {
+    unsigned int Mb = M[l], a = 0;
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
-#pragma unroll
-      for (int l = 0; l < NLEV; ++l) {
-        if (sl[j] <= l) {
-          const unsigned int b = sv[j] > Mb[l] ? sv[j] : Mb[l];
-          if (ev[j] > b) acc[l] += ev[j] - b;
-          if (sv[j] > Mb[l]) nbrk += 1u << (10 * l);
-          if (ev[j] > Mb[l]) Mb[l] = ev[j];
-        }
-      }
+      const unsigned int s = s_in(j, l), e = e_in(j, l);
+      const unsigned int b = max(s, Mb);
+      a += max(e, b) - b;
+      nbrk += s > Mb ? 1u << (10 * l) : 0u;
+      Mb = max(Mb, e);
     }
+    acc[l] = a;
   }
   unsigned int P[NLEV], totp[NLEV];
 #pragma unroll
   for (int l = 0; l < NLEV; ++l) P[l] = wave_excl_scan_u32<OpSumU>(acc[l], 0u, totp[l]);
   unsigned int totr;
   const unsigned int Rp = wave_excl_scan_u32<OpSumU>(nbrk, 0u, totr);
-  unsigned int R[NLEV];
 #pragma unroll
-  for (int l = 0; l < NLEV; ++l) R[l] = (Rp >> (10 * l)) & 0x3FFu;
+  for (int l = 0; l < NLEV; ++l) {
+    // byte offsets below 2^32 from a wave-uniform base
+    char* out = (char*)(p.compn[l] + off);
+    unsigned int rb = ((Rp >> (10 * l)) & 0x3FFu) << 3;
+    unsigned int Ml = M[l], Pl = P[l];
 #pragma unroll
-  for (int j = 0; j < IPL; ++j) {
-#pragma unroll
-    for (int l = 0; l < NLEV; ++l) {
-      if (sl[j] <= l) {
-        if (sv[j] > M[l]) {
-          Comp c;
-          c.cs = lo + (long long)(sv[j] - 1);
-          c.pl = (long long)P[l];
-          p.comp[l][off + R[l]] = c;
-          R[l] += 1;
-        }
-        const unsigned int b = sv[j] > M[l] ? sv[j] : M[l];
-        if (ev[j] > b) P[l] += ev[j] - b;
-        if (ev[j] > M[l]) M[l] = ev[j];
+    for (int j = 0; j < IPL; ++j) {
+      const unsigned int s = s_in(j, l), e = e_in(j, l);
+      if (s > Ml) {
+        CompN c;
+        c.cs = s - 1;
+        c.pl = Pl;
+        *(CompN*)(out + rb) = c;
+        rb += 8;
       }
+      const unsigned int b = max(s, Ml);
+      Pl += max(e, b) - b;
+      Ml = max(Ml, e);
     }
   }
   if (lane < 3) {
@@ -773,9 +769,10 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   return true;
 }
 
-__global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_merge_wave(Plan p) {
   __shared__ WaveSmem wsm[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // everything per bucket is wave-uniform
   const long long gb = (long long)blockIdx.x * 4 + wave;
   if (gb >= p.n_buckets) return;
   WaveSmem& W = wsm[wave];
@@ -824,23 +821,23 @@ __device__ long long measure_before(const Plan& p, int seg, int l, long long t) 
   const long long base = p.base[gb * 3 + l];
   const long long bs = p.bsum[gb * 3 + l];
   const long long cnt = p.ncomp[gb * 3 + l];
-  const Comp* c = p.comp[l] + p.offsets[gb];
+  const CompView c = comp_view(p, g, sd.bucket_begin, gb, l);
   // first component with start >= t
   long long lo = 0, hi = cnt;
   while (lo < hi) {
     const long long mid = (lo + hi) >> 1;
-    if (c[mid].cs < t) lo = mid + 1; else hi = mid;
+    if (c.cs(mid) < t) lo = mid + 1; else hi = mid;
   }
   const long long k = lo - 1;
   if (k < 0) {
     // only the component carried in from earlier buckets lies before t
-    const long long ext = carry + (cnt > 0 ? c[0].pl : bs);
+    const long long ext = carry + (cnt > 0 ? c.pl(0) : bs);
     return base + (ext < t ? ext : t) - carry;
   }
-  const Comp ck = c[k];
-  const long long next_pl = k + 1 < cnt ? c[k + 1].pl : bs;
-  const long long ce = ck.cs + (next_pl - ck.pl);
-  return base + ck.pl + (ce < t ? ce : t) - ck.cs;
+  const long long cs = c.cs(k), pl = c.pl(k);
+  const long long next_pl = k + 1 < cnt ? c.pl(k + 1) : bs;
+  const long long ce = cs + (next_pl - pl);
+  return base + pl + (ce < t ? ce : t) - cs;
 }
 
 template <int THREADS>

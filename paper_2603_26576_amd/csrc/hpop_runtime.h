@@ -54,7 +54,7 @@ struct RecChunk {
 
 // Device buffers of one build plan.
 struct Workspace {
-  DevBuf meta, elems, elems2, comp[3];
+  DevBuf meta, elems, elems2, comp[3], compn[3];
   PinnedBuf pinned;       // trees and status words copied back
   PinnedBuf pinned_desc;  // descriptor uploads
   Plan plan{};

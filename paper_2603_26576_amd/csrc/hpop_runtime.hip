@@ -197,9 +197,10 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   // where oversized buckets also need a scratch copy for their global sort
   const size_t big_e = carve_bytes(n_slots > 0 ? n_slots : n_elems, sizeof(Elem));
   const size_t big_e2 = carve_bytes(n_slots > 0 ? 1 : n_elems, sizeof(Elem));
-  const size_t big_c = carve_bytes(n_elems, sizeof(Comp));
+  const size_t big_c = carve_bytes(n_elems, sizeof(Comp)), big_n = carve_bytes(n_elems, sizeof(CompN));
   if (!elems.reserve(a, big_e, false) || !elems2.reserve(a, big_e2, false) || !comp[0].reserve(a, big_c, false) ||
-      !comp[1].reserve(a, big_c, false) || !comp[2].reserve(a, big_c, false)) {
+      !comp[1].reserve(a, big_c, false) || !comp[2].reserve(a, big_c, false) || !compn[0].reserve(a, big_n, false) ||
+      !compn[1].reserve(a, big_n, false) || !compn[2].reserve(a, big_n, false)) {
     err = "device allocation for " + std::to_string(n_elems) + " records failed";
     return HPOP_E_OOM;
   }
@@ -230,7 +231,10 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   d_times = carve<long long>(cur, 4 * n_times);
   p.elems = (Elem*)elems.ptr;
   p.elems2 = (Elem*)elems2.ptr;
-  for (int l = 0; l < 3; ++l) p.comp[l] = (Comp*)comp[l].ptr;
+  for (int l = 0; l < 3; ++l) {
+    p.comp[l] = (Comp*)comp[l].ptr;
+    p.compn[l] = (CompN*)compn[l].ptr;
+  }
   p.n_chunks = (int32_t)n_chunks;
   p.n_segs = (int32_t)n_segs;
   p.n_buckets = n_buckets;
@@ -244,6 +248,7 @@ void Workspace::release(Alloc& a) {
   elems.release(a);
   elems2.release(a);
   for (auto& c : comp) c.release(a);
+  for (auto& c : compn) c.release(a);
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   graph_exec = nullptr;
   pinned.release();

@@ -139,7 +139,8 @@ __global__ __launch_bounds__(64) void k_serv_prep(ServItem* items, int n_items, 
     }
   if (b0 < 0) return;  // no new interval at this level
   const ListDev L = lists[it.list0 + l];
-  const long long x = p.comp[l][p.offsets[sd.bucket_begin + b0]].cs;
+  const Geom g0 = seg_geom(stt, sd);
+  const long long x = comp_view(p, g0, sd.bucket_begin, sd.bucket_begin + b0, l).cs(0);
   long long lo = 0, hi = L.len;
   while (lo < hi) {
     const long long mid = (lo + hi) >> 1;
@@ -240,14 +241,14 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
       for (int i = threadIdx.x; i < ni; i += kServThreads) sm.E[i] = A[i];
       __syncthreads();
       const unsigned short* ord = sort_lds<kServThreads, kServCap>(sm, ni, lo);
-      flatten_tile<kServThreads>(sm.E, ord, ni, 1, 0, out, st, sm.lds_scan, nullptr);
+      flatten_tile<kServThreads>(sm.E, ord, ni, 1, 0, out, nullptr, 0, st, sm.lds_scan, nullptr);
     } else if (cnt > 0) {
       const Elem* src = sort_global<kServThreads, kServCap>(sm, A, B, cnt, lo);
       for (long long t0 = 0; t0 < cnt; t0 += kServCap) {
         const int c = (int)min((long long)kServCap, cnt - t0);
         for (int i = threadIdx.x; i < c; i += kServThreads) sm.E[i] = src[t0 + i];
         __syncthreads();
-        flatten_tile<kServThreads>(sm.E, nullptr, c, 1, 0, out, st, sm.lds_scan, nullptr);
+        flatten_tile<kServThreads>(sm.E, nullptr, c, 1, 0, out, nullptr, 0, st, sm.lds_scan, nullptr);
         __syncthreads();
       }
     }
@@ -257,6 +258,7 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   long long R = st.R[0];
   long long P = st.P[0];
   const long long bt = xb + 1;
+  const Geom gs = seg_geom(p.stats[it.seg], sd);
   if (bt < nb) {
     const long long shift = P - p.base[(sd.bucket_begin + bt) * 3 + l];
     for (long long b0 = bt; b0 < nb; b0 += kServThreads) {
@@ -276,10 +278,11 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
           if (s_pref[mid] <= j) a = mid; else z = mid - 1;
         }
         const long long gb = sd.bucket_begin + b0 + a;
-        const Comp src = p.comp[l][p.offsets[gb] + (j - s_pref[a])];
+        const CompView src = comp_view(p, gs, sd.bucket_begin, gb, l);
+        const long long k = j - s_pref[a];
         Comp o;
-        o.cs = src.cs;
-        o.pl = src.pl + p.base[gb * 3 + l] + shift;
+        o.cs = src.cs(k);
+        o.pl = src.pl(k) + p.base[gb * 3 + l] + shift;
         L.base[R + j] = o;
       }
       R += tot[0];
