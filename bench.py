@@ -36,7 +36,8 @@ ALGO_BYTES = {
     "stats": 8,          # read start
     "hist": 16,          # read start + end (exact-count fallback only)
     "scatter": 32,       # read start + end, write one 16 B bucketed record
-    "merge_wave": None,  # read 16 B per record, write 16 B per merged interval and level
+    "merge_wave": None,  # read 16 B per record, write 8 B per merged interval and level
+                         # (16 B on resources whose buckets are wider than 2^30 ns)
 }
 
 
@@ -144,7 +145,7 @@ def bench_single(hp, trace, steps, warmup, workload, tune_cache=None):
     stage_ms = {k: v / steps for k, v in stage_tot.items()}
     dom = max((k for k in stage_ms if k in ALGO_BYTES), key=lambda k: stage_ms[k])
     if dom == "merge_wave":
-        algo = 16 * n_events + 16 * info.n_components
+        algo = 16 * n_events + 8 * info.n_components + 8 * info.n_wide_components
     else:
         algo = ALGO_BYTES[dom] * n_events
     achieved = algo / (stage_ms[dom] * 1e-3) / 1e9
@@ -155,7 +156,8 @@ def bench_single(hp, trace, steps, warmup, workload, tune_cache=None):
     tuning = {"bucket_target": tun.bucket_target, "bucket_cap": tun.bucket_cap, "tile_elems": tun.tile_elems}
     return {"tuning": tuning, "ms_per_step": dt * 1e3, "ms_per_step_graph": dt_graph * 1e3, "events": n_events,
             "value": n_events / dt, "value_graph": n_events / dt_graph, "stage_ms": stage_ms, "roofline": roof,
-            "components": int(info.n_components), "buckets": int(info.n_buckets),
+            "components": int(info.n_components), "wide_components": int(info.n_wide_components),
+            "buckets": int(info.n_buckets),
             "oversized_buckets": int(info.n_oversized), "trees": trees}
 
 
@@ -451,7 +453,8 @@ def main():
            "roofline": r["roofline"],
            "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
            "graph_replay": {"ms_per_step": round(r["ms_per_step_graph"], 4), "events_per_s": r["value_graph"]},
-           "components": r["components"], "buckets": r["buckets"], "oversized_buckets": r["oversized_buckets"],
+           "components": r["components"], "wide_components": r["wide_components"], "buckets": r["buckets"],
+           "oversized_buckets": r["oversized_buckets"],
            "tuning": r["tuning"]}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")

@@ -124,6 +124,8 @@ typedef struct {
     int64_t n_components;   /* merged intervals written by the last build, all levels */
     int32_t n_regions;
     int32_t graph_replays;  /* builds served by replaying a captured HIP graph */
+    int64_t n_wide_components; /* of n_components, those stored in the 16 B form (resources
+                                  whose time buckets are wider than 2^30 ns); the rest take 8 B */
 } hpop_session_info;
 
 /* One batch of records of one kind on one resource (hpop_add_events_multi,

@@ -922,15 +922,31 @@ hpop_status hpop_session_get_info(const hpop_session* s, hpop_session_info* out)
   out->n_buckets = s->engine.ws.plan.n_buckets;
   out->n_oversized = s->engine.last_oversized;
   out->n_components = 0;
-  if (s->engine.built && s->engine.ws.plan.n_buckets > 0) {
-    // read back the per-bucket component counts (diagnostics, not on the hot path)
-    const long long nb = s->engine.ws.plan.n_buckets;
+  out->n_wide_components = 0;
+  const Engine& En = s->engine;
+  if (En.built && En.ws.plan.n_buckets > 0) {
+    // read back the per-bucket component counts and the segment ranges
+    // (diagnostics, not on the hot path)
+    const long long nb = En.ws.plan.n_buckets;
+    const size_t ns = En.h_segs.size();
     std::vector<unsigned int> nc((size_t)(3 * nb));
+    std::vector<SegStats> st(ns);
     if (hipStreamSynchronize(s->stream) == hipSuccess &&
-        hipMemcpy(nc.data(), s->engine.ws.plan.ncomp, nc.size() * 4, hipMemcpyDeviceToHost) == hipSuccess) {
-      long long t = 0;
+        hipMemcpy(nc.data(), En.ws.plan.ncomp, nc.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
+        (ns == 0 || hipMemcpy(st.data(), En.ws.plan.stats, ns * sizeof(SegStats), hipMemcpyDeviceToHost) == hipSuccess)) {
+      long long t = 0, w = 0;
       for (unsigned int v : nc) t += v;
+      for (size_t g = 0; g < ns; ++g) {
+        if (st[g].min_s > st[g].max_s) continue;
+        const unsigned long long span = st[g].max_s - st[g].min_s;
+        const int bl = span ? 64 - __builtin_clzll(span) : 0;
+        const int shift = bl > En.h_segs[g].log_nb ? bl - En.h_segs[g].log_nb : 0;
+        if (shift <= kNarrowShift) continue;
+        const long long b0 = En.h_segs[g].bucket_begin, b1 = b0 + (1ll << En.h_segs[g].log_nb);
+        for (long long b = b0; b < b1; ++b) w += (long long)nc[3 * b] + nc[3 * b + 1] + nc[3 * b + 2];
+      }
       out->n_components = t;
+      out->n_wide_components = w;
     }
   }
   out->n_regions = (int32_t)s->regions.size();
