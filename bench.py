@@ -334,10 +334,16 @@ def calibrate_copy(reps=5):
     a = torch.ones(CALIB_BYTES // 8, dtype=torch.int64, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.copy_(a)
+    t0.record()
     for _ in range(reps):
         b.copy_(a)
+    t1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"calibration_copy_bytes": CALIB_BYTES, "reps": reps}))
+    ms = t0.elapsed_time(t1) / reps
+    print(json.dumps({"calibration_copy_bytes": CALIB_BYTES, "reps": reps, "ms_per_copy": round(ms, 4),
+                      "read_plus_write_GBs": round(2 * CALIB_BYTES / (ms * 1e-3) / 1e9, 1)}))
 
 
 def _pmc_rows(path, counter):

@@ -104,6 +104,7 @@ struct Plan {
   int32_t n_chunks;
   int32_t n_segs;
   int64_t n_tiles;
+  int32_t* tile_chunk;               // [n_tiles] chunk of each streaming tile (filled by the reset kernel)
   int32_t tile_elems;
   int32_t cap;                       // records a bucket may hold for the LDS sort
   int32_t slot_cap;                  // >0: single-pass scatter into fixed slots of this many records per bucket
@@ -112,6 +113,7 @@ struct Plan {
   SegStats* stats;
   int64_t n_buckets;
   unsigned int* counts;              // [n_buckets]
+  int32_t* bucket_seg;               // [n_buckets] segment of each bucket (filled by the carry kernel)
   unsigned long long* offsets;       // [n_buckets + 1]
   unsigned long long* cursor;        // [n_buckets]
   unsigned long long* maxend;        // [n_buckets][3] per slot, 0 = none

@@ -43,6 +43,9 @@ __global__ void k_reset(Plan p) {
   }
   if (tid < 4) p.ticket[tid] = 0;
   for (long long i = tid; i < p.n_owners; i += stride) p.owner_err[i] = 0;
+  // tile -> chunk map of the streaming passes, so that their workgroups start
+  // with one load instead of a dependent binary search
+  for (long long t = tid; t < p.n_tiles; t += stride) p.tile_chunk[t] = upper_index_chunk(p.chunks, p.n_chunks, t);
 }
 
 // ----------------------------------------------------------------------------
@@ -55,12 +58,9 @@ __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
   // scatter, which reads both ends anyway. Starts outside [0, 2^62) belong to
   // invalid records and are left out of the range.
   constexpr int NW = THREADS / 64;
-  __shared__ int s_chunk;
   __shared__ unsigned long long red[2][NW];
   const long long tile = blockIdx.x;
-  if (threadIdx.x == 0) s_chunk = upper_index_chunk(p.chunks, p.n_chunks, tile);
-  __syncthreads();
-  const ChunkDesc cd = p.chunks[s_chunk];
+  const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
   const long long end = min((long long)cd.count, base + p.tile_elems);
   unsigned long long mn = ULLONG_MAX, mxs = 0;
@@ -102,13 +102,10 @@ __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
 template <int THREADS, int IPT>
 __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   constexpr int NW = THREADS / 64;
-  __shared__ int s_chunk;
   __shared__ int s_rng[2][NW];
   __shared__ unsigned int hist[kHistWin];
   const long long tile = blockIdx.x;
-  if (threadIdx.x == 0) s_chunk = upper_index_chunk(p.chunks, p.n_chunks, tile);
-  __syncthreads();
-  const ChunkDesc cd = p.chunks[s_chunk];
+  const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
   const Geom g = seg_geom(p.stats[cd.seg], sd);
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
@@ -235,15 +232,12 @@ __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
 template <int THREADS, int IPT>
 __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   constexpr int NW = THREADS / 64;
-  __shared__ int s_chunk;
   __shared__ int s_rng[2][NW];
   __shared__ unsigned int hist[kHistWin];
   __shared__ unsigned long long bbase[kHistWin];
   __shared__ unsigned long long bmaxe[kHistWin];
   const long long tile = blockIdx.x;
-  if (threadIdx.x == 0) s_chunk = upper_index_chunk(p.chunks, p.n_chunks, tile);
-  __syncthreads();
-  const ChunkDesc cd = p.chunks[s_chunk];
+  const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
   const Geom g = seg_geom(p.stats[cd.seg], sd);
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
@@ -377,6 +371,7 @@ __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
     const bool ok = b < nb;
     long long v[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
     if (ok) {
+      p.bucket_seg[sd.bucket_begin + b] = (int32_t)seg;
       const unsigned long long* m = p.maxend + (sd.bucket_begin + b) * 3;
       const long long m0 = m[0] ? (long long)m[0] : LLONG_MIN;
       const long long m1 = m[1] ? (long long)m[1] : LLONG_MIN;
@@ -429,7 +424,7 @@ __global__ __launch_bounds__(THREADS) void k_base(Plan p) {
 // records, global-memory radix sort beyond).
 template <int THREADS, int CAP>
 __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS, CAP>& sm, int* s_seg) {
-  if (threadIdx.x == 0) *s_seg = upper_index_seg(p.segs, p.n_segs, gb);
+  if (threadIdx.x == 0) *s_seg = p.bucket_seg[gb];
   __syncthreads();
   const int seg = *s_seg;
   const SegDesc sd = p.segs[seg];
@@ -776,7 +771,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   const long long gb = (long long)blockIdx.x * 4 + wave;
   if (gb >= p.n_buckets) return;
   WaveSmem& W = wsm[wave];
-  const int seg = upper_index_seg(p.segs, p.n_segs, gb);
+  const int seg = p.bucket_seg[gb];
   const SegDesc sd = p.segs[seg];
   const Geom g = seg_geom(p.stats[seg], sd);
   const long long n = p.counts[gb];
@@ -880,7 +875,7 @@ __global__ __launch_bounds__(THREADS) void k_region(Plan p, const RegionDesc* re
 // ----------------------------------------------------------------------------
 
 hipError_t launch_reset(const Plan& p, hipStream_t st) {
-  const long long work = 3 * p.n_buckets + p.n_segs + 64;
+  const long long work = max(3 * p.n_buckets + p.n_segs, p.n_tiles) + 64;
   int blocks = (int)min(2048ll, (work + 255) / 256);
   hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, st, p);
   return hipGetLastError();

@@ -65,7 +65,8 @@ struct Workspace {
   long long* d_times = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   long long layout_gen = 0;
-  hpop_status prepare(Alloc& a, long long n_chunks, long long n_segs, long long n_buckets, long long n_elems,
+  hpop_status prepare(Alloc& a, long long n_chunks, long long n_tiles, long long n_segs, long long n_buckets,
+                      long long n_elems,
                       long long n_slots, long long n_regions, long long n_times, long long n_owners,
                       std::string& err);
   void release(Alloc& a);

@@ -169,15 +169,16 @@ static T* carve(char*& cur, size_t n) {
 
 static size_t carve_bytes(size_t n, size_t sz) { return (n * sz + 255) & ~size_t(255); }
 
-hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, long long n_buckets,
-                               long long n_elems, long long n_slots, long long n_regions, long long n_times,
+hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, long long n_segs,
+                               long long n_buckets, long long n_elems, long long n_slots, long long n_regions, long long n_times,
                                long long n_owners, std::string& err) {
   const size_t nscan = (size_t)((n_buckets + kScanTile - 1) / kScanTile + 1);
   size_t small = 0;
   small += carve_bytes(n_chunks, sizeof(ChunkDesc));
+  small += carve_bytes(n_tiles, sizeof(int32_t));
   small += carve_bytes(n_segs, sizeof(SegDesc));
   small += carve_bytes(n_segs, sizeof(SegStats));
-  small += carve_bytes(n_buckets, sizeof(unsigned int));
+  small += carve_bytes(n_buckets, sizeof(unsigned int)) * 2;
   small += carve_bytes(n_buckets + 1, sizeof(unsigned long long));
   small += carve_bytes(n_buckets, sizeof(unsigned long long));
   small += carve_bytes(3 * n_buckets, sizeof(unsigned long long));
@@ -207,9 +208,11 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_segs, l
   char* cur = (char*)meta.ptr;
   Plan& p = plan;
   p.chunks = d_chunks = carve<ChunkDesc>(cur, n_chunks);
+  p.tile_chunk = carve<int32_t>(cur, n_tiles);
   p.segs = d_segs = carve<SegDesc>(cur, n_segs);
   p.stats = carve<SegStats>(cur, n_segs);
   p.counts = carve<unsigned int>(cur, n_buckets);
+  p.bucket_seg = carve<int32_t>(cur, n_buckets);
   p.offsets = carve<unsigned long long>(cur, n_buckets + 1);
   p.cursor = carve<unsigned long long>(cur, n_buckets);
   p.maxend = carve<unsigned long long>(cur, 3 * n_buckets);
@@ -367,7 +370,7 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
     buckets += 1ll << sd.log_nb;
     h_segs.push_back(sd);
   }
-  hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), n_segs, buckets, elems,
+  hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), tiles, n_segs, buckets, elems,
                               slots > 0 ? buckets * (long long)slots : 0, (long long)h_regions.size(), times,
                               std::max(1, n_owners), err);
   if (st != HPOP_OK) return st;
