@@ -71,6 +71,43 @@ __device__ __forceinline__ CompView comp_view(const Plan& p, const Geom& g, long
   return v;
 }
 
+// The records of one bucket: n8 in the 8 B form, n16 in the 16 B form.
+struct BucketRecs {
+  const uint2* narrow;
+  const Elem* wide;
+  int n8, n16;
+  bool overflow;  // more records than fixed slots: the build is redone with exact offsets
+};
+
+__device__ __forceinline__ BucketRecs bucket_recs(const Plan& p, long long gb) {
+  BucketRecs r;
+  const unsigned long long cu = p.cursor[gb];
+  r.n8 = (int)(unsigned int)cu;
+  r.n16 = (int)(cu >> 32);
+  long long ub, ucap;
+  if (p.slot_cap) {
+    ub = 2 * gb * (long long)p.slot_cap;
+    ucap = 2 * (long long)p.slot_cap;
+    r.overflow = (long long)r.n8 + r.n16 > (long long)p.slot_cap;
+  } else {
+    ub = 2 * (long long)p.offsets[gb];
+    ucap = 2 * ((long long)r.n8 + r.n16);
+    r.overflow = false;
+  }
+  const uint2* u = (const uint2*)p.elems;
+  r.narrow = u + ub;
+  r.wide = (const Elem*)(u + ub + ucap) - r.n16;
+  return r;
+}
+
+// the 16 B form of an 8 B record of the bucket starting at lo
+__device__ __forceinline__ Elem widen(uint2 x, long long lo) {
+  Elem el;
+  el.s = lo + (long long)(x.x >> 2);
+  el.e_slot = (long long)((unsigned long long)(lo + (long long)x.y - 1) | ((unsigned long long)(x.x & 3u) << kSlotShift));
+  return el;
+}
+
 // bucket of a record start inside its segment (clamped; start >= min_s for valid records)
 __device__ __forceinline__ int bucket_of(long long s, const Geom& g) {
   unsigned long long rel = (unsigned long long)(s - g.min_s);

@@ -93,11 +93,19 @@ struct CompN {
 };
 constexpr int kNarrowShift = 30;
 
-struct Elem {  // one record regrouped by bucket
+struct Elem {  // one record regrouped by bucket (the 16 B form)
   int64_t s;
   int64_t e_slot;  // end | slot << 62
 };
 
+// Records regrouped by bucket. A bucket owns a region of 2 x capacity 8 B
+// units (capacity = slot_cap with fixed slots, else its record count) at
+// unit 2 x (gb x slot_cap, or offsets[gb]). A record of a narrow segment whose
+// end lies less than 2^32 - 1 ns after the bucket's first time `lo` takes one
+// unit from the front, in the 8 B form
+//   x = (start - lo) << 2 | slot,  y = end - lo + 1;
+// any other record takes two units from the back in the 16 B form. cursor[gb]
+// counts both: 8 B records in the low 32 bits, 16 B records in the high 32.
 // Device pointers of one build plan.
 struct Plan {
   const ChunkDesc* chunks;
@@ -115,14 +123,14 @@ struct Plan {
   unsigned int* counts;              // [n_buckets]
   int32_t* bucket_seg;               // [n_buckets] segment of each bucket (filled by the carry kernel)
   unsigned long long* offsets;       // [n_buckets + 1]
-  unsigned long long* cursor;        // [n_buckets]
+  unsigned long long* cursor;        // [n_buckets] records placed: 8 B form | 16 B form << 32
   unsigned long long* maxend;        // [n_buckets][3] per slot, 0 = none
   long long* carry;                  // [n_buckets][3] per level
   long long* bsum;                    // [n_buckets][3] measure contributed by the bucket
   unsigned int* ncomp;               // [n_buckets][3]
   long long* base;                    // [n_buckets][3] measure of all earlier buckets
   long long* seg_total;              // [n_segs][3]
-  Elem* elems;                       // [n_elems]
+  Elem* elems;                       // bucket regions, 16 B per record slot (see above)
   Elem* elems2;                      // [n_elems] scratch for oversized buckets
   Comp* comp[kLevels];               // [n_elems] each: components of wide segments
   CompN* compn[kLevels];             // [n_elems] each: components of narrow segments

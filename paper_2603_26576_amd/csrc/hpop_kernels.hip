@@ -64,12 +64,29 @@ __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
   const long long end = min((long long)cd.count, base + p.tile_elems);
   unsigned long long mn = ULLONG_MAX, mxs = 0;
-  for (long long i = base + threadIdx.x; i < end; i += THREADS) {
-    const unsigned long long s = (unsigned long long)cd.s[i];
+  auto take = [&](unsigned long long s) {
     if (s < (unsigned long long)kTimeLimit) {
       mn = s < mn ? s : mn;
       mxs = s > mxs ? s : mxs;
     }
+  };
+  if ((((uintptr_t)cd.s) & 15) == 0 && end - base == p.tile_elems && (p.tile_elems & (2 * THREADS - 1)) == 0) {
+    // a full tile from a 16 B aligned array: pairs of starts, all loads issued first
+    const ulonglong2* v = (const ulonglong2*)(cd.s + base);
+    const int npairs = p.tile_elems / 2;
+    constexpr int U = 4;
+    for (int j0 = threadIdx.x; j0 < npairs; j0 += U * THREADS) {
+      ulonglong2 x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = j0 + u * THREADS < npairs ? v[j0 + u * THREADS] : make_ulonglong2(ULLONG_MAX, ULLONG_MAX);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        take(x[u].x);
+        take(x[u].y);
+      }
+    }
+  } else {
+    for (long long i = base + threadIdx.x; i < end; i += THREADS) take((unsigned long long)cd.s[i]);
   }
   mn = wave_red_minu(mn);
   mxs = wave_red_maxu(mxs);
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   }
 }
 
-// exclusive scan of bucket counts -> offsets and cursors (decoupled look-back)
+// exclusive scan of bucket counts -> offsets (decoupled look-back)
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
   constexpr int IPT = kScanTile / THREADS;
@@ -181,7 +198,8 @@ __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
       if (slots) {
         // counts of the single-pass scatter (capped: an overflow is redone exactly)
         const unsigned long long cu = p.cursor[b0 + k];
-        c[k] = (unsigned int)(cu < (unsigned long long)p.slot_cap ? cu : (unsigned long long)p.slot_cap);
+        const unsigned long long n = (cu & 0xFFFFFFFFull) + (cu >> 32);
+        c[k] = (unsigned int)(n < (unsigned long long)p.slot_cap ? n : (unsigned long long)p.slot_cap);
         p.counts[b0 + k] = c[k];
       } else {
         c[k] = p.counts[b0 + k];
@@ -219,8 +237,7 @@ __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     if (b0 + k < p.n_buckets) {
-      p.offsets[b0 + k] = run;
-      if (!slots) p.cursor[b0 + k] = run;
+      p.offsets[b0 + k] = run;  // cursors stay relative: the scatter adds the bucket's base
       if (c[k] > (unsigned)p.cap) atomicAdd(p.oversized, 1ull);
     }
     run += c[k];
@@ -233,22 +250,25 @@ template <int THREADS, int IPT>
 __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   constexpr int NW = THREADS / 64;
   __shared__ int s_rng[2][NW];
-  __shared__ unsigned int hist[kHistWin];
-  __shared__ unsigned long long bbase[kHistWin];
+  __shared__ unsigned long long hist[kHistWin];   // per window bucket: 8 B records | 16 B records << 32
+  __shared__ unsigned long long bbase[kHistWin];  // the same counts placed before this tile
   __shared__ unsigned long long bmaxe[kHistWin];
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
   const Geom g = seg_geom(p.stats[cd.seg], sd);
+  const bool seg_n = seg_narrow(g);
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
   const long long end = min((long long)cd.count, base + p.tile_elems);
   int bk[IPT];
+  bool nr[IPT];  // the record takes the 8 B form
   long long sv[IPT], ev[IPT];
   int bmin = INT_MAX, bmax = -1;
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     const long long i = base + threadIdx.x + (long long)k * THREADS;
     bk[k] = -1;
+    nr[k] = false;
     sv[k] = 0;
     ev[k] = 0;
     if (i < end) {
@@ -260,6 +280,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
         p.owner_err[cd.owner] = 1u;
       } else if (sv[k] < ev[k]) {
         bk[k] = bucket_of(sv[k], g);
+        nr[k] = seg_n && ev[k] - bucket_lo(g, bk[k]) < 0xFFFFFFFFll;
         bmin = min(bmin, bk[k]);
         bmax = max(bmax, bk[k]);
       }
@@ -279,13 +300,37 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   if (bmax < 0) return;
   const unsigned long long slotbits = (unsigned long long)cd.slot << kSlotShift;
   unsigned long long* gmax = p.maxend;
+  uint2* units = (uint2*)p.elems;
+  // place one record given its rank among the bucket's records of its form
+  auto place = [&](int k, long long gb, unsigned long long rank) {
+    long long ub, ucap;
+    if (scap) {
+      ub = 2 * gb * scap;
+      ucap = 2 * scap;
+    } else {
+      ub = 2 * (long long)p.offsets[gb];
+      ucap = 2 * (long long)p.counts[gb];
+    }
+    if (nr[k]) {
+      if ((long long)rank < ucap) {
+        const long long lo = bucket_lo(g, gb - sd.bucket_begin);
+        units[ub + rank] = make_uint2(((unsigned int)(sv[k] - lo) << 2) | (unsigned int)cd.slot,
+                                      (unsigned int)(ev[k] - lo + 1));
+      }
+    } else if (2 * ((long long)rank + 1) <= ucap) {
+      Elem el;
+      el.s = sv[k];
+      el.e_slot = (long long)((unsigned long long)ev[k] | slotbits);
+      *(Elem*)(units + ub + ucap - 2 * ((long long)rank + 1)) = el;
+    }
+  };
   if (bmax - bmin < kHistWin) {
     unsigned int rk[IPT];
     const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
       // lanes of one bucket share one LDS atomic: the leader reserves their
-      // ranks and folds their largest end in
+      // ranks (per form) and folds their largest end in
       rk[k] = 0;
       unsigned long long todo = __ballot(bk[k] >= 0);
       while (todo) {
@@ -293,40 +338,39 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
         const int lb = __shfl(bk[k], leader, 64);
         const bool in = bk[k] == lb;
         const unsigned long long m = __ballot(in);
+        const unsigned long long mn = __ballot(in && nr[k]);
         const unsigned long long emax = wave_red_maxu(in ? (unsigned long long)ev[k] : 0ull);
-        unsigned int b = 0;
+        unsigned long long b = 0;
         if (lane == leader) {
-          b = atomicAdd(&hist[lb - bmin], (unsigned int)__popcll(m));
+          const unsigned long long c8 = (unsigned long long)__popcll(mn), c16 = (unsigned long long)__popcll(m & ~mn);
+          b = atomicAdd(&hist[lb - bmin], c8 | (c16 << 32));
           atomicMax(&bmaxe[lb - bmin], emax);
         }
         b = __shfl(b, leader, 64);
-        if (in) rk[k] = b + (unsigned int)__popcll(m & lt);
+        if (in) rk[k] = nr[k] ? (unsigned int)b + (unsigned int)__popcll(mn & lt)
+                              : (unsigned int)(b >> 32) + (unsigned int)__popcll(m & ~mn & lt);
         todo &= ~m;
       }
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= bmax - bmin; i += THREADS) {
-      if (hist[i]) {
+      const unsigned long long h = hist[i];
+      if (h) {
         const long long gb = sd.bucket_begin + bmin + i;
-        bbase[i] = atomicAdd(&p.cursor[gb], (unsigned long long)hist[i]);
+        const unsigned long long old = atomicAdd(&p.cursor[gb], h);
+        bbase[i] = old;
         atomicMax(&gmax[gb * 3 + cd.slot], bmaxe[i]);
+        const unsigned long long tot = (old & 0xFFFFFFFFull) + (old >> 32) + (h & 0xFFFFFFFFull) + (h >> 32);
+        if (scap && tot > (unsigned long long)scap && tot - (h & 0xFFFFFFFFull) - (h >> 32) <= (unsigned long long)scap)
+          atomicAdd(&p.oversized[1], 1ull);  // slot overflow: the build is redone with exact offsets
       }
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
       if (bk[k] >= 0) {
-        const long long pos = (long long)(bbase[bk[k] - bmin] + rk[k]);
-        Elem el;
-        el.s = sv[k];
-        el.e_slot = (long long)((unsigned long long)ev[k] | slotbits);
-        if (scap == 0) {
-          p.elems[pos] = el;  // cursors started at the exact offsets
-        } else if (pos < scap) {
-          p.elems[(sd.bucket_begin + bk[k]) * scap + pos] = el;
-        } else {
-          atomicAdd(&p.oversized[1], 1ull);  // slot overflow: the build is redone with exact offsets
-        }
+        const unsigned long long bb = bbase[bk[k] - bmin];
+        place(k, sd.bucket_begin + bk[k], (nr[k] ? (bb & 0xFFFFFFFFull) : (bb >> 32)) + rk[k]);
       }
     }
   } else {
@@ -334,18 +378,11 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
     for (int k = 0; k < IPT; ++k) {
       if (bk[k] >= 0) {
         const long long gb = sd.bucket_begin + bk[k];
-        const long long pos = (long long)atomicAdd(&p.cursor[gb], 1ull);
+        const unsigned long long old = atomicAdd(&p.cursor[gb], nr[k] ? 1ull : (1ull << 32));
         atomicMax(&gmax[gb * 3 + cd.slot], (unsigned long long)ev[k]);
-        Elem el;
-        el.s = sv[k];
-        el.e_slot = (long long)((unsigned long long)ev[k] | slotbits);
-        if (scap == 0) {
-          p.elems[pos] = el;
-        } else if (pos < scap) {
-          p.elems[gb * scap + pos] = el;
-        } else {
+        if (scap && (old & 0xFFFFFFFFull) + (old >> 32) == (unsigned long long)scap)
           atomicAdd(&p.oversized[1], 1ull);
-        }
+        place(k, gb, nr[k] ? (old & 0xFFFFFFFFull) : (old >> 32));
       }
     }
   }
@@ -430,7 +467,9 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
   const SegDesc sd = p.segs[seg];
   const Geom g = seg_geom(p.stats[seg], sd);
   const long long bl = gb - sd.bucket_begin;
-  const long long n = p.counts[gb];
+  const BucketRecs br = bucket_recs(p, gb);
+  // a slot overflow makes the host redo the build: write an empty bucket
+  const long long n = br.overflow ? 0 : (long long)br.n8 + br.n16;
   const long long off = (long long)p.offsets[gb];
   const int nlev = sd.n_levels;
   FlatState st;
@@ -447,15 +486,22 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
     const long long lo = g.min_s + (bl << g.shift);
     if (n <= CAP) {
       const int ni = (int)n;
-      const Elem* rec = p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + off;
-      for (int i = threadIdx.x; i < ni; i += THREADS) sm.E[i] = rec[i];  // coalesced 16 B per lane
+      for (int i = threadIdx.x; i < br.n8; i += THREADS) sm.E[i] = widen(br.narrow[i], lo);
+      for (int i = threadIdx.x; i < br.n16; i += THREADS) sm.E[br.n8 + i] = br.wide[i];
       __syncthreads();
       const unsigned short* ord = sort_lds<THREADS, CAP>(sm, ni, lo);
       flatten_tile<THREADS>(sm.E, ord, ni, nlev, 0, comp, compn, lo, st, sm.lds_scan, nullptr);
     } else {
-      // oversized bucket: stable LSD sort through global scratch, then flatten
-      // CAP records at a time, carrying the running state across tiles
-      const Elem* src = sort_global<THREADS, CAP>(sm, p.elems + off, p.elems2 + off, n, lo);
+      // oversized bucket (exact offsets only): every record in the 16 B form
+      // into the scratch copy, a stable LSD sort between it and the bucket's
+      // own region (16 B per record), then flatten CAP records at a time,
+      // carrying the running state across tiles
+      Elem* a = p.elems2 + off;
+      for (long long i = threadIdx.x; i < br.n8; i += THREADS) a[i] = widen(br.narrow[i], lo);
+      for (long long i = threadIdx.x; i < br.n16; i += THREADS) a[br.n8 + i] = br.wide[i];
+      __threadfence_block();
+      __syncthreads();
+      const Elem* src = sort_global<THREADS, CAP>(sm, a, p.elems + off, n, lo);
       for (long long t0 = 0; t0 < n; t0 += CAP) {
         const int cnt = (int)min((long long)CAP, n - t0);
         for (int i = threadIdx.x; i < cnt; i += THREADS) sm.E[i] = src[t0 + i];
@@ -496,7 +542,8 @@ __global__ __launch_bounds__(THREADS) void k_merge_block(Plan p) {
 
 // Wave path: each wave sorts and flattens one bucket of at most kWaveCap
 // records with no workgroup barrier, in 32-bit arithmetic relative to the
-// bucket's first time `lo`. A record enters as
+// bucket's first time `lo`. It takes the buckets whose records are all in the
+// scatter's 8 B form:
 //   key = (start - lo) << 2 | slot    (start - lo < 2^30: bucket width <= 2^30)
 //   end = end - lo + 1                (< 2^32; 0 stands for "before the bucket")
 // Comparisons, maxima and measure differences are unchanged by the common
@@ -505,9 +552,8 @@ __global__ __launch_bounds__(THREADS) void k_merge_block(Plan p) {
 // the top bits of the start into 128-1024 sub-bins, writing keys and ends to
 // their sorted places in LDS, then an insertion sort inside each sub-bin that
 // received two or more records (equal starts may end in any order: the merged
-// result does not depend on it). Buckets that do not fit (more records, a
-// wider bucket, an end 2^32 or more past lo, a crowded sub-bin) go to the
-// block path's queue.
+// result does not depend on it). Other buckets (more records, any record in
+// the 16 B form, a crowded sub-bin) go to the block path's queue.
 struct alignas(16) WaveSmem {
   unsigned int key[kWaveCap];        // sorted keys
   unsigned int end[kWaveCap];        // ends of the sorted records
@@ -658,28 +704,23 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, l
 // Returns false (nothing written) when the bucket must take the block path.
 template <int IPL>
 __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
-                                            long long lo, const Elem* rec, int nlev) {
+                                            long long lo, const uint2* rec, int nlev) {
   const int lane = threadIdx.x & 63;
-  constexpr long long EMASK = (1ll << kSlotShift) - 1;
   unsigned int kr[IPL], er[IPL], rk[IPL];
   unsigned int kor = 0;
-  bool far = false;
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
     const int i = lane + 64 * r;
     kr[r] = 0;
     er[r] = 0;
     if (i < ni) {
-      const Elem el = rec[i];
-      const unsigned int k = (unsigned int)(el.s - lo);
-      const long long e = (el.e_slot & EMASK) - lo;
-      far |= e >= 0xFFFFFFFFll;
-      kr[r] = (k << 2) | (unsigned int)((unsigned long long)el.e_slot >> kSlotShift);
-      er[r] = (unsigned int)(e + 1);
-      kor |= k;
+      const uint2 x = rec[i];  // already relative to lo: (start - lo) << 2 | slot, end - lo + 1
+      kr[r] = x.x;
+      er[r] = x.y;
+      kor |= x.x;
     }
   }
-  if (__ballot(far)) return false;
+  kor >>= 2;
   for (int d = 32; d >= 1; d >>= 1) kor |= __shfl_xor(kor, d, 64);
   // sub-bins: about two per record, 128 .. 1024; a lane owns bpl of them (two per LDS word)
   int dbits = 7;
@@ -774,9 +815,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   const int seg = p.bucket_seg[gb];
   const SegDesc sd = p.segs[seg];
   const Geom g = seg_geom(p.stats[seg], sd);
-  const long long n = p.counts[gb];
+  const BucketRecs br = bucket_recs(p, gb);
+  const long long n = (long long)br.n8 + br.n16;
   const long long off = (long long)p.offsets[gb];
-  if (n == 0) {
+  if (n == 0 || br.overflow) {
+    // empty, or a slot overflow that makes the host redo the build
     if (lane < 3) {
       p.bsum[gb * 3 + lane] = 0;
       p.ncomp[gb * 3 + lane] = 0;
@@ -784,10 +827,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     return;
   }
   bool done = false;
-  if (n <= kWaveCap && g.shift <= 30) {
+  if (br.n16 == 0 && n <= kWaveCap) {
+    // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
     const int ni = (int)n;
-    const long long lo = g.min_s + ((gb - sd.bucket_begin) << g.shift);
-    const Elem* rec = p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + off;
+    const long long lo = bucket_lo(g, gb - sd.bucket_begin);
+    const uint2* rec = br.narrow;
     const int nlev = sd.n_levels;
     if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, lo, rec, nlev);
     else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, lo, rec, nlev);

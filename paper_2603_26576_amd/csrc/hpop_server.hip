@@ -108,10 +108,6 @@ __device__ __forceinline__ long long list_measure(const ListDev& L, long long t)
   return L.base[k].pl + (ce < t ? ce : t) - L.base[k].cs;
 }
 
-__device__ __forceinline__ const Elem* bucket_records(const Plan& p, long long gb) {
-  return p.slot_cap ? p.elems + gb * p.slot_cap : p.elems + (long long)p.offsets[gb];
-}
-
 // one thread per (item, level)
 __global__ __launch_bounds__(64) void k_serv_prep(ServItem* items, int n_items, Plan p, const ListDev* lists,
                                                   long long* frontier, ServCtl* ctl) {
@@ -200,6 +196,7 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   st.P[0] = k0 < L.len ? L.base[k0].pl : L.total;
   st.R[0] = k0;
   Comp* out[3] = {L.base, nullptr, nullptr};
+  const Geom gs = seg_geom(p.stats[it.seg], sd);
   if (total > 0) {
     // old entries from k0 on, then the level's new records of buckets 0..xb
     for (long long i = threadIdx.x; i < nS; i += kServThreads) {
@@ -212,10 +209,11 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
     __syncthreads();
     for (long long b = 0; b <= xb; ++b) {
       const long long gb = sd.bucket_begin + b;
-      const Elem* rec = bucket_records(p, gb);
-      const long long n = p.counts[gb];
+      const BucketRecs br = bucket_recs(p, gb);
+      const long long blo = bucket_lo(gs, b);
+      const long long n = (long long)br.n8 + br.n16;
       for (long long i = threadIdx.x; i < n; i += kServThreads) {
-        const Elem el = rec[i];
+        const Elem el = i < br.n8 ? widen(br.narrow[i], blo) : br.wide[i - br.n8];
         const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
         if (slot <= l) {
           const unsigned int q = atomicAdd(&s_fill, 1u);
@@ -258,7 +256,6 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   long long R = st.R[0];
   long long P = st.P[0];
   const long long bt = xb + 1;
-  const Geom gs = seg_geom(p.stats[it.seg], sd);
   if (bt < nb) {
     const long long shift = P - p.base[(sd.bucket_begin + bt) * 3 + l];
     for (long long b0 = bt; b0 < nb; b0 += kServThreads) {
