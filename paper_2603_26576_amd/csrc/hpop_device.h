@@ -597,4 +597,59 @@ __device__ __forceinline__ long long wave_excl_scan_dpp(long long x, long long i
   return dpp64<kDppWaveShr1, 0xf, 0xf>(id, x);
 }
 
+struct OpMaxU {
+  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a > b ? a : b; }
+};
+struct OpSumU {
+  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a + b; }
+};
+
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ unsigned int dpp32(unsigned int old, unsigned int v) {
+  return (unsigned int)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+}
+
+// Exclusive scan over the 64 lanes (lane order) with identity `id`, and the total.
+template <class Op>
+__device__ __forceinline__ unsigned int wave_excl_scan_u32(unsigned int x, unsigned int id, unsigned int& total) {
+  x = Op::apply(x, dpp32<kDppRowShr1, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr2, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr4, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr8, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowBcast15, 0xa, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowBcast31, 0xc, 0xf>(id, x));
+  total = (unsigned int)__builtin_amdgcn_readlane((int)x, 63);
+  return dpp32<kDppWaveShr1, 0xf, 0xf>(id, x);
+}
+
+struct OpMinI {
+  __device__ static int apply(int a, int b) { return a < b ? a : b; }
+};
+struct OpMaxI {
+  __device__ static int apply(int a, int b) { return a > b ? a : b; }
+};
+struct OpOrI {
+  __device__ static int apply(int a, int b) { return a | b; }
+};
+
+// Reduction over the 64 lanes with DPP row shifts (no LDS round trips); every
+// lane receives the result.
+template <class Op>
+__device__ __forceinline__ int wave_reduce_i32(int x, int id) {
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr1, 0xf, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr2, 0xf, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr4, 0xf, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr8, 0xf, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowBcast15, 0xa, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowBcast31, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
+template <class Op>
+__device__ __forceinline__ long long wave_reduce_i64(long long x, long long id) {
+  long long total;
+  (void)wave_excl_scan_dpp<Op>(x, id, total);
+  return total;
+}
+
 }  // namespace hpop

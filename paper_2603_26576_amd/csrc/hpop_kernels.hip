@@ -142,10 +142,8 @@ __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
       }
     }
   }
-  for (int d = 32; d >= 1; d >>= 1) {
-    bmin = min(bmin, __shfl_xor(bmin, d, 64));
-    bmax = max(bmax, __shfl_xor(bmax, d, 64));
-  }
+  bmin = wave_reduce_i32<OpMinI>(bmin, INT_MAX);
+  bmax = wave_reduce_i32<OpMaxI>(bmax, -1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
   for (int i = threadIdx.x; i < kHistWin; i += THREADS) hist[i] = 0;
@@ -161,7 +159,7 @@ __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
       unsigned long long todo = __ballot(bk[k] >= 0);
       while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
-        const int lb = __shfl(bk[k], leader, 64);
+        const int lb = __builtin_amdgcn_readlane(bk[k], leader);
         const unsigned long long m = __ballot(bk[k] == lb);
         if (lane == leader) atomicAdd(&hist[lb - bmin], (unsigned int)__popcll(m));
         todo &= ~m;
@@ -286,10 +284,8 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
       }
     }
   }
-  for (int d = 32; d >= 1; d >>= 1) {
-    bmin = min(bmin, __shfl_xor(bmin, d, 64));
-    bmax = max(bmax, __shfl_xor(bmax, d, 64));
-  }
+  bmin = wave_reduce_i32<OpMinI>(bmin, INT_MAX);
+  bmax = wave_reduce_i32<OpMaxI>(bmax, -1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long scap = p.slot_cap;
   if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
@@ -335,18 +331,18 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
       unsigned long long todo = __ballot(bk[k] >= 0);
       while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
-        const int lb = __shfl(bk[k], leader, 64);
+        const int lb = __builtin_amdgcn_readlane(bk[k], leader);
         const bool in = bk[k] == lb;
         const unsigned long long m = __ballot(in);
         const unsigned long long mn = __ballot(in && nr[k]);
-        const unsigned long long emax = wave_red_maxu(in ? (unsigned long long)ev[k] : 0ull);
+        const long long emax = wave_reduce_i64<OpMax>(in ? ev[k] : 0ll, 0ll);
         unsigned long long b = 0;
         if (lane == leader) {
           const unsigned long long c8 = (unsigned long long)__popcll(mn), c16 = (unsigned long long)__popcll(m & ~mn);
           b = atomicAdd(&hist[lb - bmin], c8 | (c16 << 32));
-          atomicMax(&bmaxe[lb - bmin], emax);
+          atomicMax(&bmaxe[lb - bmin], (unsigned long long)emax);
         }
-        b = __shfl(b, leader, 64);
+        b = (unsigned long long)readlane64((long long)b, leader);
         if (in) rk[k] = nr[k] ? (unsigned int)b + (unsigned int)__popcll(mn & lt)
                               : (unsigned int)(b >> 32) + (unsigned int)__popcll(m & ~mn & lt);
         todo &= ~m;
@@ -560,31 +556,6 @@ struct alignas(16) WaveSmem {
   unsigned int bins[kWaveBins / 2];  // two 16-bit counters (then sub-bin starts) per word
 };
 
-struct OpMaxU {
-  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a > b ? a : b; }
-};
-struct OpSumU {
-  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a + b; }
-};
-
-template <int CTRL, int ROW_MASK, int BANK_MASK>
-__device__ __forceinline__ unsigned int dpp32(unsigned int old, unsigned int v) {
-  return (unsigned int)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
-}
-
-// Exclusive scan over the 64 lanes (lane order) with identity `id`, and the total.
-template <class Op>
-__device__ __forceinline__ unsigned int wave_excl_scan_u32(unsigned int x, unsigned int id, unsigned int& total) {
-  x = Op::apply(x, dpp32<kDppRowShr1, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowShr2, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowShr4, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowShr8, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowBcast15, 0xa, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowBcast31, 0xc, 0xf>(id, x));
-  total = (unsigned int)__builtin_amdgcn_readlane((int)x, 63);
-  return dpp32<kDppWaveShr1, 0xf, 0xf>(id, x);
-}
-
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -721,7 +692,7 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
     }
   }
   kor >>= 2;
-  for (int d = 32; d >= 1; d >>= 1) kor |= __shfl_xor(kor, d, 64);
+  kor = (unsigned int)wave_reduce_i32<OpOrI>((int)kor, 0);
   // sub-bins: about two per record, 128 .. 1024; a lane owns bpl of them (two per LDS word)
   int dbits = 7;
   while ((1 << dbits) < 2 * ni && dbits < 10) ++dbits;
@@ -934,9 +905,9 @@ hipError_t launch_stats(const Plan& p, hipStream_t st) {
 hipError_t launch_hist(const Plan& p, hipStream_t st) {
   if (p.n_tiles == 0) return hipSuccess;
   switch (p.tile_elems) {
-    case 2048: hipLaunchKernelGGL((k_hist<256, 8>), dim3((unsigned)p.n_tiles), dim3(256), 0, st, p); break;
-    case 8192: hipLaunchKernelGGL((k_hist<512, 16>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
-    default: hipLaunchKernelGGL((k_hist<256, 16>), dim3((unsigned)p.n_tiles), dim3(256), 0, st, p); break;
+    case 2048: hipLaunchKernelGGL((k_hist<512, 4>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
+    case 8192: hipLaunchKernelGGL((k_hist<1024, 8>), dim3((unsigned)p.n_tiles), dim3(1024), 0, st, p); break;
+    default: hipLaunchKernelGGL((k_hist<512, 8>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
   }
   return hipGetLastError();
 }
@@ -951,9 +922,9 @@ hipError_t launch_scan(const Plan& p, hipStream_t st) {
 hipError_t launch_scatter(const Plan& p, hipStream_t st) {
   if (p.n_tiles == 0) return hipSuccess;
   switch (p.tile_elems) {
-    case 2048: hipLaunchKernelGGL((k_scatter<256, 8>), dim3((unsigned)p.n_tiles), dim3(256), 0, st, p); break;
-    case 8192: hipLaunchKernelGGL((k_scatter<512, 16>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
-    default: hipLaunchKernelGGL((k_scatter<256, 16>), dim3((unsigned)p.n_tiles), dim3(256), 0, st, p); break;
+    case 2048: hipLaunchKernelGGL((k_scatter<512, 4>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
+    case 8192: hipLaunchKernelGGL((k_scatter<1024, 8>), dim3((unsigned)p.n_tiles), dim3(1024), 0, st, p); break;
+    default: hipLaunchKernelGGL((k_scatter<512, 8>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
   }
   return hipGetLastError();
 }
