@@ -628,6 +628,9 @@ struct OpMinI {
 struct OpMaxI {
   __device__ static int apply(int a, int b) { return a > b ? a : b; }
 };
+struct OpMaxU32 {  // unsigned maximum on int lanes
+  __device__ static int apply(int a, int b) { return (unsigned int)a > (unsigned int)b ? a : b; }
+};
 struct OpOrI {
   __device__ static int apply(int a, int b) { return a | b; }
 };

@@ -250,7 +250,8 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   __shared__ int s_rng[2][NW];
   __shared__ unsigned long long hist[kHistWin];   // per window bucket: 8 B records | 16 B records << 32
   __shared__ unsigned long long bbase[kHistWin];  // the same counts placed before this tile
-  __shared__ unsigned long long bmaxe[kHistWin];
+  __shared__ unsigned long long bmaxe[kHistWin];  // largest end of the tile's records
+  __shared__ long long bunit[kHistWin];           // first unit of the bucket's region
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
@@ -258,27 +259,31 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   const bool seg_n = seg_narrow(g);
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
   const long long end = min((long long)cd.count, base + p.tile_elems);
+  // per record: bucket (-1: none), form, and the 8 B form itself; a record in
+  // the 16 B form is read again where it is needed (rare)
   int bk[IPT];
-  bool nr[IPT];  // the record takes the 8 B form
-  long long sv[IPT], ev[IPT];
+  bool nr[IPT];
+  unsigned int kx[IPT], ex[IPT];
   int bmin = INT_MAX, bmax = -1;
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     const long long i = base + threadIdx.x + (long long)k * THREADS;
     bk[k] = -1;
     nr[k] = false;
-    sv[k] = 0;
-    ev[k] = 0;
+    kx[k] = 0;
+    ex[k] = 0;
     if (i < end) {
-      sv[k] = cd.s[i];
-      ev[k] = cd.e[i];
-      if (!rec_valid(sv[k], ev[k])) {
+      const long long sv = cd.s[i], ev = cd.e[i];
+      if (!rec_valid(sv, ev)) {
         // first bad record of the build: chunk << 40 | index (rare path)
         atomicMin(p.err, ((unsigned long long)cd.chunk_id << 40) | (unsigned long long)i);
         p.owner_err[cd.owner] = 1u;
-      } else if (sv[k] < ev[k]) {
-        bk[k] = bucket_of(sv[k], g);
-        nr[k] = seg_n && ev[k] - bucket_lo(g, bk[k]) < 0xFFFFFFFFll;
+      } else if (sv < ev) {
+        bk[k] = bucket_of(sv, g);
+        const long long lo = bucket_lo(g, bk[k]);
+        nr[k] = seg_n && ev - lo < 0xFFFFFFFFll;
+        kx[k] = ((unsigned int)(sv - lo) << 2) | (unsigned int)cd.slot;
+        ex[k] = (unsigned int)(ev - lo + 1);
         bmin = min(bmin, bk[k]);
         bmax = max(bmax, bk[k]);
       }
@@ -297,9 +302,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   const unsigned long long slotbits = (unsigned long long)cd.slot << kSlotShift;
   unsigned long long* gmax = p.maxend;
   uint2* units = (uint2*)p.elems;
-  // place one record given its rank among the bucket's records of its form
-  auto place = [&](int k, long long gb, unsigned long long rank) {
-    long long ub, ucap;
+  auto region = [&](long long gb, long long& ub, long long& ucap) {
     if (scap) {
       ub = 2 * gb * scap;
       ucap = 2 * scap;
@@ -307,16 +310,13 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
       ub = 2 * (long long)p.offsets[gb];
       ucap = 2 * (long long)p.counts[gb];
     }
-    if (nr[k]) {
-      if ((long long)rank < ucap) {
-        const long long lo = bucket_lo(g, gb - sd.bucket_begin);
-        units[ub + rank] = make_uint2(((unsigned int)(sv[k] - lo) << 2) | (unsigned int)cd.slot,
-                                      (unsigned int)(ev[k] - lo + 1));
-      }
-    } else if (2 * ((long long)rank + 1) <= ucap) {
+  };
+  auto put_wide = [&](int k, long long ub, long long ucap, unsigned long long rank) {
+    if (2 * ((long long)rank + 1) <= ucap) {
+      const long long i = base + threadIdx.x + (long long)k * THREADS;
       Elem el;
-      el.s = sv[k];
-      el.e_slot = (long long)((unsigned long long)ev[k] | slotbits);
+      el.s = cd.s[i];
+      el.e_slot = (long long)((unsigned long long)cd.e[i] | slotbits);
       *(Elem*)(units + ub + ucap - 2 * ((long long)rank + 1)) = el;
     }
   };
@@ -335,7 +335,16 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
         const bool in = bk[k] == lb;
         const unsigned long long m = __ballot(in);
         const unsigned long long mn = __ballot(in && nr[k]);
-        const long long emax = wave_reduce_i64<OpMax>(in ? ev[k] : 0ll, 0ll);
+        long long emax;
+        if (mn == m) {
+          // all 8 B records: the largest end in 32 bits, relative to the bucket
+          const unsigned int e32 = (unsigned int)wave_reduce_i32<OpMaxU32>((int)(in ? ex[k] : 0u), 0);
+          emax = bucket_lo(g, lb) + (long long)e32 - 1;
+        } else {
+          long long ev = 0;
+          if (in) ev = nr[k] ? bucket_lo(g, lb) + (long long)ex[k] - 1 : cd.e[base + threadIdx.x + (long long)k * THREADS];
+          emax = wave_reduce_i64<OpMax>(ev, 0ll);
+        }
         unsigned long long b = 0;
         if (lane == leader) {
           const unsigned long long c8 = (unsigned long long)__popcll(mn), c16 = (unsigned long long)__popcll(m & ~mn);
@@ -355,6 +364,9 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
         const long long gb = sd.bucket_begin + bmin + i;
         const unsigned long long old = atomicAdd(&p.cursor[gb], h);
         bbase[i] = old;
+        long long ub, ucap;
+        region(gb, ub, ucap);
+        bunit[i] = ub;
         atomicMax(&gmax[gb * 3 + cd.slot], bmaxe[i]);
         const unsigned long long tot = (old & 0xFFFFFFFFull) + (old >> 32) + (h & 0xFFFFFFFFull) + (h >> 32);
         if (scap && tot > (unsigned long long)scap && tot - (h & 0xFFFFFFFFull) - (h >> 32) <= (unsigned long long)scap)
@@ -365,8 +377,18 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
       if (bk[k] >= 0) {
-        const unsigned long long bb = bbase[bk[k] - bmin];
-        place(k, sd.bucket_begin + bk[k], (nr[k] ? (bb & 0xFFFFFFFFull) : (bb >> 32)) + rk[k]);
+        const int w = bk[k] - bmin;
+        const unsigned long long bb = bbase[w];
+        const long long ub = bunit[w];
+        if (nr[k]) {
+          const unsigned long long rank = (bb & 0xFFFFFFFFull) + rk[k];
+          const long long ucap = scap ? 2 * scap : 2 * (long long)p.counts[sd.bucket_begin + bk[k]];
+          if ((long long)rank < ucap) units[ub + (long long)rank] = make_uint2(kx[k], ex[k]);
+        } else {
+          long long ub2, ucap;
+          region(sd.bucket_begin + bk[k], ub2, ucap);
+          put_wide(k, ub, ucap, (bb >> 32) + rk[k]);
+        }
       }
     }
   } else {
@@ -375,10 +397,17 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
       if (bk[k] >= 0) {
         const long long gb = sd.bucket_begin + bk[k];
         const unsigned long long old = atomicAdd(&p.cursor[gb], nr[k] ? 1ull : (1ull << 32));
-        atomicMax(&gmax[gb * 3 + cd.slot], (unsigned long long)ev[k]);
+        const long long ev = cd.e[base + threadIdx.x + (long long)k * THREADS];
+        atomicMax(&gmax[gb * 3 + cd.slot], (unsigned long long)ev);
         if (scap && (old & 0xFFFFFFFFull) + (old >> 32) == (unsigned long long)scap)
           atomicAdd(&p.oversized[1], 1ull);
-        place(k, gb, nr[k] ? (old & 0xFFFFFFFFull) : (old >> 32));
+        long long ub, ucap;
+        region(gb, ub, ucap);
+        if (nr[k]) {
+          if ((long long)(old & 0xFFFFFFFFull) < ucap) units[ub + (long long)(old & 0xFFFFFFFFull)] = make_uint2(kx[k], ex[k]);
+        } else {
+          put_wide(k, ub, ucap, old >> 32);
+        }
       }
     }
   }
