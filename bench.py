@@ -35,9 +35,9 @@ METRIC = "trace events/sec reduced to full metric tree"
 ALGO_BYTES = {
     "stats": 8,          # read start
     "hist": 16,          # read start + end (exact-count fallback only)
-    "scatter": 32,       # read start + end, write one 16 B bucketed record
-    "merge_wave": None,  # read 16 B per record, write 8 B per merged interval and level
-                         # (16 B on resources whose buckets are wider than 2^30 ns)
+    "scatter": None,     # read start + end, write the 8 B bucketed form (16 B form: +8)
+    "merge_wave": None,  # read the 8 B bucketed form (16 B: +8), write 8 B per merged
+                         # interval and level (16 B on resources with buckets wider than 2^30 ns)
 }
 
 
@@ -145,7 +145,9 @@ def bench_single(hp, trace, steps, warmup, workload, tune_cache=None):
     stage_ms = {k: v / steps for k, v in stage_tot.items()}
     dom = max((k for k in stage_ms if k in ALGO_BYTES), key=lambda k: stage_ms[k])
     if dom == "merge_wave":
-        algo = 16 * n_events + 8 * info.n_components + 8 * info.n_wide_components
+        algo = 8 * n_events + 8 * info.n_wide_records + 8 * info.n_components + 8 * info.n_wide_components
+    elif dom == "scatter":
+        algo = 24 * n_events + 8 * info.n_wide_records
     else:
         algo = ALGO_BYTES[dom] * n_events
     achieved = algo / (stage_ms[dom] * 1e-3) / 1e9
@@ -157,6 +159,7 @@ def bench_single(hp, trace, steps, warmup, workload, tune_cache=None):
     return {"tuning": tuning, "ms_per_step": dt * 1e3, "ms_per_step_graph": dt_graph * 1e3, "events": n_events,
             "value": n_events / dt, "value_graph": n_events / dt_graph, "stage_ms": stage_ms, "roofline": roof,
             "components": int(info.n_components), "wide_components": int(info.n_wide_components),
+            "wide_records": int(info.n_wide_records),
             "buckets": int(info.n_buckets),
             "oversized_buckets": int(info.n_oversized), "trees": trees}
 
@@ -459,7 +462,8 @@ def main():
            "roofline": r["roofline"],
            "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
            "graph_replay": {"ms_per_step": round(r["ms_per_step_graph"], 4), "events_per_s": r["value_graph"]},
-           "components": r["components"], "wide_components": r["wide_components"], "buckets": r["buckets"],
+           "components": r["components"], "wide_components": r["wide_components"],
+           "wide_records": r["wide_records"], "buckets": r["buckets"],
            "oversized_buckets": r["oversized_buckets"],
            "tuning": r["tuning"]}
     if not args.no_cpu_baseline:

@@ -126,6 +126,9 @@ typedef struct {
     int32_t graph_replays;  /* builds served by replaying a captured HIP graph */
     int64_t n_wide_components; /* of n_components, those stored in the 16 B form (resources
                                   whose time buckets are wider than 2^30 ns); the rest take 8 B */
+    int64_t n_wide_records; /* records of the last build regrouped in the 16 B form (wide
+                               buckets, or an end 2^32 - 1 ns or more past the bucket start);
+                               the rest take 8 B */
 } hpop_session_info;
 
 /* One batch of records of one kind on one resource (hpop_add_events_multi,

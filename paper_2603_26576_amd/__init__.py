@@ -73,7 +73,8 @@ class hpop_tuning(ctypes.Structure):
 class hpop_session_info(ctypes.Structure):
     _fields_ = [("n_events", ctypes.c_int64), ("n_chunks", ctypes.c_int64), ("n_buckets", ctypes.c_int64),
                 ("n_oversized", ctypes.c_int64), ("n_components", ctypes.c_int64), ("n_regions", ctypes.c_int32),
-                ("graph_replays", ctypes.c_int32), ("n_wide_components", ctypes.c_int64)]
+                ("graph_replays", ctypes.c_int32), ("n_wide_components", ctypes.c_int64),
+                ("n_wide_records", ctypes.c_int64)]
 
 
 class hpop_server_config(ctypes.Structure):

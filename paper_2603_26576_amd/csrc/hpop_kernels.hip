@@ -620,7 +620,7 @@ __device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (
 // component stores are conditional.
 template <int IPL, int NLEV>
 __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, long long gb, long long off, int ni,
-                                             long long lo) {
+                                             long long lo, const long long (&carry)[3]) {
   const int lane = threadIdx.x & 63;
   const int q0 = lane * IPL;
   const int cnt = min(max(ni - q0, 0), IPL);
@@ -644,7 +644,7 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, l
     for (int j = 0; j < IPL; ++j) tmax = max(tmax, e_in(j, l));
     unsigned int tot;
     const unsigned int ex = wave_excl_scan_u32<OpMaxU>(tmax, 0u, tot);
-    const long long c = p.carry[gb * 3 + l];
+    const long long c = carry[l];
     const unsigned int cr = c < lo ? 0u : (c - lo >= 0xFFFFFFFFll ? 0xFFFFFFFFu : (unsigned int)(c - lo + 1));
     M[l] = max(ex, cr);
   }
@@ -704,7 +704,7 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, l
 // Returns false (nothing written) when the bucket must take the block path.
 template <int IPL>
 __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
-                                            long long lo, const uint2* rec, int nlev) {
+                                            const uint2* rec, const long long (&carry)[3]) {
   const int lane = threadIdx.x & 63;
   unsigned int kr[IPL], er[IPL], rk[IPL];
   unsigned int kor = 0;
@@ -720,6 +720,10 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
       kor |= x.x;
     }
   }
+  // the segment's geometry only now, while the records are in flight
+  const SegDesc sd = p.segs[p.bucket_seg[gb]];
+  const long long lo = bucket_lo(seg_geom(p.stats[p.bucket_seg[gb]], sd), gb - sd.bucket_begin);
+  const int nlev = sd.n_levels;
   kor >>= 2;
   kor = (unsigned int)wave_reduce_i32<OpOrI>((int)kor, 0);
   // sub-bins: about two per record, 128 .. 1024; a lane owns bpl of them (two per LDS word)
@@ -800,8 +804,8 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   }
   if (__ballot(crowded)) return false;
   wave_sync();
-  if (nlev == 2) wave_flatten<IPL, 2>(p, W, gb, off, ni, lo);
-  else wave_flatten<IPL, 3>(p, W, gb, off, ni, lo);
+  if (nlev == 2) wave_flatten<IPL, 2>(p, W, gb, off, ni, lo, carry);
+  else wave_flatten<IPL, 3>(p, W, gb, off, ni, lo, carry);
   return true;
 }
 
@@ -812,12 +816,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   const long long gb = (long long)blockIdx.x * 4 + wave;
   if (gb >= p.n_buckets) return;
   WaveSmem& W = wsm[wave];
-  const int seg = p.bucket_seg[gb];
-  const SegDesc sd = p.segs[seg];
-  const Geom g = seg_geom(p.stats[seg], sd);
   const BucketRecs br = bucket_recs(p, gb);
   const long long n = (long long)br.n8 + br.n16;
   const long long off = (long long)p.offsets[gb];
+  const long long carry[3] = {p.carry[gb * 3], p.carry[gb * 3 + 1], p.carry[gb * 3 + 2]};
   if (n == 0 || br.overflow) {
     // empty, or a slot overflow that makes the host redo the build
     if (lane < 3) {
@@ -830,13 +832,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   if (br.n16 == 0 && n <= kWaveCap) {
     // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
     const int ni = (int)n;
-    const long long lo = bucket_lo(g, gb - sd.bucket_begin);
     const uint2* rec = br.narrow;
-    const int nlev = sd.n_levels;
-    if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, lo, rec, nlev);
-    else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, lo, rec, nlev);
-    else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, lo, rec, nlev);
-    else done = wave_bucket<8>(p, W, gb, off, ni, lo, rec, nlev);
+    if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry);
+    else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry);
+    else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, rec, carry);
+    else done = wave_bucket<8>(p, W, gb, off, ni, rec, carry);
   }
   if (!done && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
 }

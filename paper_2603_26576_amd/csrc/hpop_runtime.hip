@@ -926,6 +926,7 @@ hpop_status hpop_session_get_info(const hpop_session* s, hpop_session_info* out)
   out->n_oversized = s->engine.last_oversized;
   out->n_components = 0;
   out->n_wide_components = 0;
+  out->n_wide_records = 0;
   const Engine& En = s->engine;
   if (En.built && En.ws.plan.n_buckets > 0) {
     // read back the per-bucket component counts and the segment ranges
@@ -934,7 +935,9 @@ hpop_status hpop_session_get_info(const hpop_session* s, hpop_session_info* out)
     const size_t ns = En.h_segs.size();
     std::vector<unsigned int> nc((size_t)(3 * nb));
     std::vector<SegStats> st(ns);
+    std::vector<unsigned long long> cur((size_t)nb);
     if (hipStreamSynchronize(s->stream) == hipSuccess &&
+        hipMemcpy(cur.data(), En.ws.plan.cursor, cur.size() * 8, hipMemcpyDeviceToHost) == hipSuccess &&
         hipMemcpy(nc.data(), En.ws.plan.ncomp, nc.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
         (ns == 0 || hipMemcpy(st.data(), En.ws.plan.stats, ns * sizeof(SegStats), hipMemcpyDeviceToHost) == hipSuccess)) {
       long long t = 0, w = 0;
@@ -950,6 +953,7 @@ hpop_status hpop_session_get_info(const hpop_session* s, hpop_session_info* out)
       }
       out->n_components = t;
       out->n_wide_components = w;
+      for (unsigned long long c : cur) out->n_wide_records += (long long)(c >> 32);
     }
   }
   out->n_regions = (int32_t)s->regions.size();

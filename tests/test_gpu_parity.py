@@ -148,7 +148,8 @@ def test_long_intervals_and_wide_buckets():
     regions = [(0, 1 << 46), (1 << 20, 1 << 33), (5 << 30, 7 << 30)]
     check(tg.Trace(0, 2, chunks, regions))
     check(tg.Trace(1, 0, host, regions))
-    # the sparse resource keeps 16 B components, the dense one 8 B ones
+    # the sparse resource keeps 16 B components and records, the dense one
+    # mostly 8 B ones
     s_ = hp.hpop_session_create(0, 2)
     try:
         hp.add_chunks(s_, [(c.resource, c.kind, c.start, c.end) for c in chunks])
@@ -156,6 +157,7 @@ def test_long_intervals_and_wide_buckets():
         hp.hpop_metrics_compute_all(s_)
         info = hp.hpop_session_get_info(s_)
         assert 0 < info.n_wide_components < info.n_components
+        assert 0 < info.n_wide_records < tg.Trace(0, 2, chunks, regions).n_events
     finally:
         hp.hpop_session_destroy(s_)
 
