@@ -580,7 +580,7 @@ __global__ __launch_bounds__(THREADS) void k_merge_block(Plan p) {
 // result does not depend on it). Other buckets (more records, any record in
 // the 16 B form, a crowded sub-bin) go to the block path's queue.
 struct alignas(16) WaveSmem {
-  unsigned int key[kWaveCap];        // sorted keys
+  unsigned int key[kWaveCap];        // sorted keys (then, with end[], the components of one level)
   unsigned int end[kWaveCap];        // ends of the sorted records
   unsigned int bins[kWaveBins / 2];  // two 16-bit counters (then sub-bin starts) per word
 };
@@ -619,7 +619,7 @@ __device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (
 // no maximum, measure or break, so the phases need no branches; only the
 // component stores are conditional.
 template <int IPL, int NLEV>
-__device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, long long gb, long long off, int ni,
+__device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
                                              long long lo, const long long (&carry)[3]) {
   const int lane = threadIdx.x & 63;
   const int q0 = lane * IPL;
@@ -669,26 +669,30 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, const WaveSmem& W, l
   for (int l = 0; l < NLEV; ++l) P[l] = wave_excl_scan_u32<OpSumU>(acc[l], 0u, totp[l]);
   unsigned int totr;
   const unsigned int Rp = wave_excl_scan_u32<OpSumU>(nbrk, 0u, totr);
+  // components of one level at a time are staged in LDS (the sorted keys and
+  // ends are in registers by now) and then written out in full 64-lane rows
+  uint2* stage = (uint2*)W.key;  // key[] and end[]: kWaveCap entries of 8 B
+  wave_sync();
 #pragma unroll
   for (int l = 0; l < NLEV; ++l) {
-    // byte offsets below 2^32 from a wave-uniform base
-    char* out = (char*)(p.compn[l] + off);
-    unsigned int rb = ((Rp >> (10 * l)) & 0x3FFu) << 3;
+    unsigned int r = (Rp >> (10 * l)) & 0x3FFu;
     unsigned int Ml = M[l], Pl = P[l];
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
       const unsigned int s = s_in(j, l), e = e_in(j, l);
       if (s > Ml) {
-        CompN c;
-        c.cs = s - 1;
-        c.pl = Pl;
-        *(CompN*)(out + rb) = c;
-        rb += 8;
+        stage[r] = make_uint2(s - 1, Pl);  // CompN {start - lo, measure before}
+        ++r;
       }
       const unsigned int b = max(s, Ml);
       Pl += max(e, b) - b;
       Ml = max(Ml, e);
     }
+    wave_sync();
+    const int nl = (int)((totr >> (10 * l)) & 0x3FFu);
+    uint2* out = (uint2*)(p.compn[l] + off);
+    for (int i = lane; i < nl; i += 64) out[i] = stage[i];
+    wave_sync();
   }
   if (lane < 3) {
     unsigned int bs = 0;
