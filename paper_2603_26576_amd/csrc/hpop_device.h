@@ -100,11 +100,17 @@ __device__ __forceinline__ BucketRecs bucket_recs(const Plan& p, long long gb) {
   return r;
 }
 
-// the 16 B form of an 8 B record of the bucket starting at lo
-__device__ __forceinline__ Elem widen(uint2 x, long long lo) {
+// The 16 B form of an 8 B record of the bucket starting at lo. A clamped end
+// (field 0xFFFFFFFF) becomes the largest end of the bucket's records of the
+// same rank (maxend: per rank): every clamped record of a rank reaches past
+// lo + 2^32 - 2 and starts before lo + 2^30, so they all overlap, and giving
+// each the largest of their ends leaves the union of every level unchanged.
+__device__ __forceinline__ Elem widen(uint2 x, long long lo, const unsigned long long* maxend) {
   Elem el;
+  const unsigned int slot = x.x & 3u;
   el.s = lo + (long long)(x.x >> 2);
-  el.e_slot = (long long)((unsigned long long)(lo + (long long)x.y - 1) | ((unsigned long long)(x.x & 3u) << kSlotShift));
+  const long long e = x.y == 0xFFFFFFFFu ? (long long)maxend[slot] : lo + (long long)x.y - 1;
+  el.e_slot = (long long)((unsigned long long)e | ((unsigned long long)slot << kSlotShift));
   return el;
 }
 

@@ -100,12 +100,13 @@ struct Elem {  // one record regrouped by bucket (the 16 B form)
 
 // Records regrouped by bucket. A bucket owns a region of 2 x capacity 8 B
 // units (capacity = slot_cap with fixed slots, else its record count) at
-// unit 2 x (gb x slot_cap, or offsets[gb]). A record of a narrow segment whose
-// end lies less than 2^32 - 1 ns after the bucket's first time `lo` takes one
-// unit from the front, in the 8 B form
-//   x = (start - lo) << 2 | slot,  y = end - lo + 1;
-// any other record takes two units from the back in the 16 B form. cursor[gb]
-// counts both: 8 B records in the low 32 bits, 16 B records in the high 32.
+// unit 2 x (gb x slot_cap, or offsets[gb]). A record of a narrow segment
+// takes one unit from the front, in the 8 B form
+//   x = (start - lo) << 2 | slot,  y = min(end - lo + 1, 0xFFFFFFFF)
+// where lo is the bucket's first time (a clamped end stands for the largest
+// end of the bucket's records of that slot, maxend); a record of a wide
+// segment takes two units from the back in the 16 B form. cursor[gb] counts
+// both: 8 B records in the low 32 bits, 16 B records in the high 32.
 // Device pointers of one build plan.
 struct Plan {
   const ChunkDesc* chunks;

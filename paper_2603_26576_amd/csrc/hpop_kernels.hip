@@ -281,9 +281,9 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
       } else if (sv < ev) {
         bk[k] = bucket_of(sv, g);
         const long long lo = bucket_lo(g, bk[k]);
-        nr[k] = seg_n && ev - lo < 0xFFFFFFFFll;
+        nr[k] = seg_n;
         kx[k] = ((unsigned int)(sv - lo) << 2) | (unsigned int)cd.slot;
-        ex[k] = (unsigned int)(ev - lo + 1);
+        ex[k] = ev - lo < 0xFFFFFFFFll ? (unsigned int)(ev - lo + 1) : 0xFFFFFFFFu;  // far ends clamped
         bmin = min(bmin, bk[k]);
         bmax = max(bmax, bk[k]);
       }
@@ -336,13 +336,14 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
         const unsigned long long m = __ballot(in);
         const unsigned long long mn = __ballot(in && nr[k]);
         long long emax;
-        if (mn == m) {
-          // all 8 B records: the largest end in 32 bits, relative to the bucket
-          const unsigned int e32 = (unsigned int)wave_reduce_i32<OpMaxU32>((int)(in ? ex[k] : 0u), 0);
+        unsigned int e32 = 0;
+        if (mn == m) e32 = (unsigned int)wave_reduce_i32<OpMaxU32>((int)(in ? ex[k] : 0u), 0);
+        if (mn == m && e32 != 0xFFFFFFFFu) {
+          // all 8 B records, none clamped: the largest end in 32 bits, relative to the bucket
           emax = bucket_lo(g, lb) + (long long)e32 - 1;
         } else {
           long long ev = 0;
-          if (in) ev = nr[k] ? bucket_lo(g, lb) + (long long)ex[k] - 1 : cd.e[base + threadIdx.x + (long long)k * THREADS];
+          if (in) ev = cd.e[base + threadIdx.x + (long long)k * THREADS];
           emax = wave_reduce_i64<OpMax>(ev, 0ll);
         }
         unsigned long long b = 0;
@@ -511,7 +512,8 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
     const long long lo = g.min_s + (bl << g.shift);
     if (n <= CAP) {
       const int ni = (int)n;
-      for (int i = threadIdx.x; i < br.n8; i += THREADS) sm.E[i] = widen(br.narrow[i], lo);
+      const unsigned long long* mx = p.maxend + gb * 3;
+      for (int i = threadIdx.x; i < br.n8; i += THREADS) sm.E[i] = widen(br.narrow[i], lo, mx);
       for (int i = threadIdx.x; i < br.n16; i += THREADS) sm.E[br.n8 + i] = br.wide[i];
       __syncthreads();
       const unsigned short* ord = sort_lds<THREADS, CAP>(sm, ni, lo);
@@ -522,7 +524,8 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
       // own region (16 B per record), then flatten CAP records at a time,
       // carrying the running state across tiles
       Elem* a = p.elems2 + off;
-      for (long long i = threadIdx.x; i < br.n8; i += THREADS) a[i] = widen(br.narrow[i], lo);
+      const unsigned long long* mx = p.maxend + gb * 3;
+      for (long long i = threadIdx.x; i < br.n8; i += THREADS) a[i] = widen(br.narrow[i], lo, mx);
       for (long long i = threadIdx.x; i < br.n16; i += THREADS) a[br.n8 + i] = br.wide[i];
       __threadfence_block();
       __syncthreads();
@@ -620,7 +623,8 @@ __device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (
 // component stores are conditional.
 template <int IPL, int NLEV>
 __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
-                                             long long lo, const long long (&carry)[3]) {
+                                             long long lo, const long long (&carry)[3],
+                                             const long long (&maxe)[3]) {
   const int lane = threadIdx.x & 63;
   const int q0 = lane * IPL;
   const int cnt = min(max(ni - q0, 0), IPL);
@@ -695,11 +699,18 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
     wave_sync();
   }
   if (lane < 3) {
-    unsigned int bs = 0;
+    long long bs = 0;
 #pragma unroll
-    for (int l = 0; l < NLEV; ++l)
-      if (lane == l) bs = totp[l];
-    p.bsum[gb * 3 + lane] = (long long)bs;
+    for (int l = 0; l < NLEV; ++l) {
+      if (lane == l) {
+        bs = (long long)totp[l];
+        // ends clamped to lo + 2^32 - 2: the level's union also covers up to
+        // its largest true end, beyond what earlier buckets already covered
+        const long long from = max(carry[l], lo + 0xFFFFFFFEll);
+        if (maxe[l] > from) bs += maxe[l] - from;
+      }
+    }
+    p.bsum[gb * 3 + lane] = bs;
     p.ncomp[gb * 3 + lane] = (totr >> (10 * lane)) & 0x3FFu;
   }
 }
@@ -708,7 +719,8 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
 // Returns false (nothing written) when the bucket must take the block path.
 template <int IPL>
 __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
-                                            const uint2* rec, const long long (&carry)[3]) {
+                                            const uint2* rec, const long long (&carry)[3],
+                                            const long long (&maxe)[3]) {
   const int lane = threadIdx.x & 63;
   unsigned int kr[IPL], er[IPL], rk[IPL];
   unsigned int kor = 0;
@@ -808,8 +820,8 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   }
   if (__ballot(crowded)) return false;
   wave_sync();
-  if (nlev == 2) wave_flatten<IPL, 2>(p, W, gb, off, ni, lo, carry);
-  else wave_flatten<IPL, 3>(p, W, gb, off, ni, lo, carry);
+  if (nlev == 2) wave_flatten<IPL, 2>(p, W, gb, off, ni, lo, carry, maxe);
+  else wave_flatten<IPL, 3>(p, W, gb, off, ni, lo, carry, maxe);
   return true;
 }
 
@@ -824,6 +836,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
   const long long n = (long long)br.n8 + br.n16;
   const long long off = (long long)p.offsets[gb];
   const long long carry[3] = {p.carry[gb * 3], p.carry[gb * 3 + 1], p.carry[gb * 3 + 2]};
+  // largest end per level of the bucket's own records (0: none)
+  long long maxe[3];
+  maxe[0] = (long long)p.maxend[gb * 3];
+  maxe[1] = max(maxe[0], (long long)p.maxend[gb * 3 + 1]);
+  maxe[2] = max(maxe[1], (long long)p.maxend[gb * 3 + 2]);
   if (n == 0 || br.overflow) {
     // empty, or a slot overflow that makes the host redo the build
     if (lane < 3) {
@@ -837,10 +854,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
     // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
     const int ni = (int)n;
     const uint2* rec = br.narrow;
-    if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry);
-    else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry);
-    else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, rec, carry);
-    else done = wave_bucket<8>(p, W, gb, off, ni, rec, carry);
+    if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry, maxe);
+    else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry, maxe);
+    else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, rec, carry, maxe);
+    else done = wave_bucket<8>(p, W, gb, off, ni, rec, carry, maxe);
   }
   if (!done && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
 }

@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
       const long long blo = bucket_lo(gs, b);
       const long long n = (long long)br.n8 + br.n16;
       for (long long i = threadIdx.x; i < n; i += kServThreads) {
-        const Elem el = i < br.n8 ? widen(br.narrow[i], blo) : br.wide[i - br.n8];
+        const Elem el = i < br.n8 ? widen(br.narrow[i], blo, p.maxend + gb * 3) : br.wide[i - br.n8];
         const int slot = (int)((unsigned long long)el.e_slot >> kSlotShift);
         if (slot <= l) {
           const unsigned int q = atomicAdd(&s_fill, 1u);
