@@ -169,6 +169,100 @@ struct OpSum {
   __device__ static long long apply(long long a, long long b) { return a + b; }
 };
 
+// ----------------------------------------------------------------------------
+// wave-level scans with DPP lane shifts (no LDS round trips)
+// ----------------------------------------------------------------------------
+
+// DPP controls of the gfx9 family: row_shr:n, row_bcast:15 / :31, wave_shr:1
+constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+// v from the lane selected by CTRL, or `old` where that lane is outside the
+// row/bank masks or has no source lane
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ long long dpp64(long long old, long long v) {
+  const int lo = __builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(old >> 32), (int)(v >> 32), CTRL, ROW_MASK, BANK_MASK, false);
+  return (long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned long long)(unsigned int)lo);
+}
+
+__device__ __forceinline__ long long readlane64(long long v, int lane) {
+  const int lo = __builtin_amdgcn_readlane((int)v, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
+  return (long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned long long)(unsigned int)lo);
+}
+
+// Exclusive scan over the 64 lanes (lane order) with identity `id`, and the total.
+template <class Op>
+__device__ __forceinline__ long long wave_excl_scan_dpp(long long x, long long id, long long& total) {
+  x = Op::apply(x, dpp64<kDppRowShr1, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowShr2, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowShr4, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowShr8, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowBcast15, 0xa, 0xf>(id, x));
+  x = Op::apply(x, dpp64<kDppRowBcast31, 0xc, 0xf>(id, x));
+  total = readlane64(x, 63);
+  return dpp64<kDppWaveShr1, 0xf, 0xf>(id, x);
+}
+
+struct OpMaxU {
+  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a > b ? a : b; }
+};
+struct OpSumU {
+  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a + b; }
+};
+
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ unsigned int dpp32(unsigned int old, unsigned int v) {
+  return (unsigned int)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
+}
+
+// Exclusive scan over the 64 lanes (lane order) with identity `id`, and the total.
+template <class Op>
+__device__ __forceinline__ unsigned int wave_excl_scan_u32(unsigned int x, unsigned int id, unsigned int& total) {
+  x = Op::apply(x, dpp32<kDppRowShr1, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr2, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr4, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowShr8, 0xf, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowBcast15, 0xa, 0xf>(id, x));
+  x = Op::apply(x, dpp32<kDppRowBcast31, 0xc, 0xf>(id, x));
+  total = (unsigned int)__builtin_amdgcn_readlane((int)x, 63);
+  return dpp32<kDppWaveShr1, 0xf, 0xf>(id, x);
+}
+
+struct OpMinI {
+  __device__ static int apply(int a, int b) { return a < b ? a : b; }
+};
+struct OpMaxI {
+  __device__ static int apply(int a, int b) { return a > b ? a : b; }
+};
+struct OpMaxU32 {  // unsigned maximum on int lanes
+  __device__ static int apply(int a, int b) { return (unsigned int)a > (unsigned int)b ? a : b; }
+};
+struct OpOrI {
+  __device__ static int apply(int a, int b) { return a | b; }
+};
+
+// Reduction over the 64 lanes with DPP row shifts (no LDS round trips); every
+// lane receives the result.
+template <class Op>
+__device__ __forceinline__ int wave_reduce_i32(int x, int id) {
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr1, 0xf, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr2, 0xf, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr4, 0xf, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr8, 0xf, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowBcast15, 0xa, 0xf, false));
+  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowBcast31, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
+template <class Op>
+__device__ __forceinline__ long long wave_reduce_i64(long long x, long long id) {
+  long long total;
+  (void)wave_excl_scan_dpp<Op>(x, id, total);
+  return total;
+}
+
 // Block-wide exclusive scan of K int64 lanes per thread (thread order), with totals.
 // `lds` holds NW*K int64. Contains barriers: call from uniform control flow.
 template <int THREADS, int K, class Op>
@@ -176,20 +270,12 @@ __device__ __forceinline__ void block_excl_scan(const long long (&v)[K], long lo
                                                 long long (&total)[K], long long ident, long long* lds) {
   constexpr int NW = THREADS / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  long long inc[K];
+  long long ex[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    long long x = v[k];
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      long long y = __shfl_up(x, d, 64);
-      if (lane >= d) x = Op::apply(x, y);
-    }
-    inc[k] = x;
-  }
-  if (lane == 63) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) lds[wave * K + k] = inc[k];
+    long long tot;
+    ex[k] = wave_excl_scan_dpp<Op>(v[k], ident, tot);
+    if (lane == 0) lds[wave * K + k] = tot;
   }
   __syncthreads();
 #pragma unroll
@@ -200,9 +286,7 @@ __device__ __forceinline__ void block_excl_scan(const long long (&v)[K], long lo
       if (w < wave) pre = Op::apply(pre, t);
       tot = Op::apply(tot, t);
     }
-    long long ex = __shfl_up(inc[k], 1, 64);
-    if (lane == 0) ex = ident;
-    excl[k] = Op::apply(pre, ex);
+    excl[k] = Op::apply(pre, ex[k]);
     total[k] = tot;
   }
   __syncthreads();
@@ -565,100 +649,6 @@ __device__ __forceinline__ void block_tree(long long (&v)[9], long long* lds) {
     }
   }
   __syncthreads();
-}
-
-// ----------------------------------------------------------------------------
-// wave-level scans with DPP lane shifts (no LDS round trips)
-// ----------------------------------------------------------------------------
-
-// DPP controls of the gfx9 family: row_shr:n, row_bcast:15 / :31, wave_shr:1
-constexpr int kDppRowShr1 = 0x111, kDppRowShr2 = 0x112, kDppRowShr4 = 0x114, kDppRowShr8 = 0x118;
-constexpr int kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
-
-// v from the lane selected by CTRL, or `old` where that lane is outside the
-// row/bank masks or has no source lane
-template <int CTRL, int ROW_MASK, int BANK_MASK>
-__device__ __forceinline__ long long dpp64(long long old, long long v) {
-  const int lo = __builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(old >> 32), (int)(v >> 32), CTRL, ROW_MASK, BANK_MASK, false);
-  return (long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned long long)(unsigned int)lo);
-}
-
-__device__ __forceinline__ long long readlane64(long long v, int lane) {
-  const int lo = __builtin_amdgcn_readlane((int)v, lane);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), lane);
-  return (long long)(((unsigned long long)(unsigned int)hi << 32) | (unsigned long long)(unsigned int)lo);
-}
-
-// Exclusive scan over the 64 lanes (lane order) with identity `id`, and the total.
-template <class Op>
-__device__ __forceinline__ long long wave_excl_scan_dpp(long long x, long long id, long long& total) {
-  x = Op::apply(x, dpp64<kDppRowShr1, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp64<kDppRowShr2, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp64<kDppRowShr4, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp64<kDppRowShr8, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp64<kDppRowBcast15, 0xa, 0xf>(id, x));
-  x = Op::apply(x, dpp64<kDppRowBcast31, 0xc, 0xf>(id, x));
-  total = readlane64(x, 63);
-  return dpp64<kDppWaveShr1, 0xf, 0xf>(id, x);
-}
-
-struct OpMaxU {
-  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a > b ? a : b; }
-};
-struct OpSumU {
-  __device__ static unsigned int apply(unsigned int a, unsigned int b) { return a + b; }
-};
-
-template <int CTRL, int ROW_MASK, int BANK_MASK>
-__device__ __forceinline__ unsigned int dpp32(unsigned int old, unsigned int v) {
-  return (unsigned int)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, BANK_MASK, false);
-}
-
-// Exclusive scan over the 64 lanes (lane order) with identity `id`, and the total.
-template <class Op>
-__device__ __forceinline__ unsigned int wave_excl_scan_u32(unsigned int x, unsigned int id, unsigned int& total) {
-  x = Op::apply(x, dpp32<kDppRowShr1, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowShr2, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowShr4, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowShr8, 0xf, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowBcast15, 0xa, 0xf>(id, x));
-  x = Op::apply(x, dpp32<kDppRowBcast31, 0xc, 0xf>(id, x));
-  total = (unsigned int)__builtin_amdgcn_readlane((int)x, 63);
-  return dpp32<kDppWaveShr1, 0xf, 0xf>(id, x);
-}
-
-struct OpMinI {
-  __device__ static int apply(int a, int b) { return a < b ? a : b; }
-};
-struct OpMaxI {
-  __device__ static int apply(int a, int b) { return a > b ? a : b; }
-};
-struct OpMaxU32 {  // unsigned maximum on int lanes
-  __device__ static int apply(int a, int b) { return (unsigned int)a > (unsigned int)b ? a : b; }
-};
-struct OpOrI {
-  __device__ static int apply(int a, int b) { return a | b; }
-};
-
-// Reduction over the 64 lanes with DPP row shifts (no LDS round trips); every
-// lane receives the result.
-template <class Op>
-__device__ __forceinline__ int wave_reduce_i32(int x, int id) {
-  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr1, 0xf, 0xf, false));
-  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr2, 0xf, 0xf, false));
-  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr4, 0xf, 0xf, false));
-  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowShr8, 0xf, 0xf, false));
-  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowBcast15, 0xa, 0xf, false));
-  x = Op::apply(x, __builtin_amdgcn_update_dpp(id, x, kDppRowBcast31, 0xc, 0xf, false));
-  return __builtin_amdgcn_readlane(x, 63);
-}
-
-template <class Op>
-__device__ __forceinline__ long long wave_reduce_i64(long long x, long long id) {
-  long long total;
-  (void)wave_excl_scan_dpp<Op>(x, id, total);
-  return total;
 }
 
 }  // namespace hpop

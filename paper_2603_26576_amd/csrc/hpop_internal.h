@@ -142,6 +142,8 @@ struct Plan {
   unsigned int* queue;               // [n_buckets] buckets handed to the block path
   unsigned long long* oversized;     // [0] buckets above the on-chip capacity, [1] buckets above slot_cap
   unsigned int* owner_err;           // [n_owners] set when an owner has an invalid record
+  unsigned long long* racc;          // [n_racc][9] per-region partial sums and maxima, zero between launches
+  int64_t n_racc;
   int32_t n_owners;
   int32_t pad2;
 };

@@ -43,6 +43,7 @@ __global__ void k_reset(Plan p) {
   }
   if (tid < 4) p.ticket[tid] = 0;
   for (long long i = tid; i < p.n_owners; i += stride) p.owner_err[i] = 0;
+  for (long long i = tid; i < 9 * p.n_racc; i += stride) p.racc[i] = 0;
   // tile -> chunk map of the streaming passes, so that their workgroups start
   // with one load instead of a dependent binary search
   for (long long t = tid; t < p.n_tiles; t += stride) p.tile_chunk[t] = upper_index_chunk(p.chunks, p.n_chunks, t);
@@ -415,8 +416,12 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
 }
 
 // ----------------------------------------------------------------------------
-// carry / base: per-segment scans over buckets, one wave per segment
+// carry / base: per-segment scans over buckets, one wave per segment; a lane
+// takes kSegIPL consecutive buckets per round (serial within the lane, DPP
+// across lanes), so a segment of 2048 buckets needs 4 rounds
 // ----------------------------------------------------------------------------
+
+constexpr int kSegIPL = 8;
 
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
@@ -429,25 +434,37 @@ __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
   // the running max end before any record: just below the first start
   const long long init = st.min_s > st.max_s ? -1 : (long long)st.min_s - 1;
   long long run[3] = {init, init, init};
-  for (long long b0 = 0; b0 < nb; b0 += 64) {
-    const long long b = b0 + lane;
-    const bool ok = b < nb;
-    long long v[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
-    if (ok) {
-      p.bucket_seg[sd.bucket_begin + b] = (int32_t)seg;
-      const unsigned long long* m = p.maxend + (sd.bucket_begin + b) * 3;
-      const long long m0 = m[0] ? (long long)m[0] : LLONG_MIN;
-      const long long m1 = m[1] ? (long long)m[1] : LLONG_MIN;
-      const long long m2 = m[2] ? (long long)m[2] : LLONG_MIN;
-      v[0] = m0;
-      v[1] = m1 > m0 ? m1 : m0;
-      v[2] = m2 > v[1] ? m2 : v[1];
+  for (long long c0 = 0; c0 < nb; c0 += 64 * kSegIPL) {
+    const long long b0 = c0 + (long long)lane * kSegIPL;
+    long long v[kSegIPL][3];
+    long long tl[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
+#pragma unroll
+    for (int j = 0; j < kSegIPL; ++j) {
+      const long long b = b0 + j;
+      v[j][0] = v[j][1] = v[j][2] = LLONG_MIN;
+      if (b < nb) {
+        p.bucket_seg[sd.bucket_begin + b] = (int32_t)seg;
+        const unsigned long long* m = p.maxend + (sd.bucket_begin + b) * 3;
+        const long long m0 = m[0] ? (long long)m[0] : LLONG_MIN;
+        const long long m1 = m[1] ? (long long)m[1] : LLONG_MIN;
+        const long long m2 = m[2] ? (long long)m[2] : LLONG_MIN;
+        v[j][0] = m0;
+        v[j][1] = m1 > m0 ? m1 : m0;
+        v[j][2] = m2 > v[j][1] ? m2 : v[j][1];
+      }
+#pragma unroll
+      for (int l = 0; l < 3; ++l) tl[l] = v[j][l] > tl[l] ? v[j][l] : tl[l];
     }
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       long long all;
-      const long long ex = wave_excl_scan_dpp<OpMax>(v[l], LLONG_MIN, all);
-      if (ok) p.carry[(sd.bucket_begin + b) * 3 + l] = ex > run[l] ? ex : run[l];
+      const long long ex = wave_excl_scan_dpp<OpMax>(tl[l], LLONG_MIN, all);
+      long long cur = ex > run[l] ? ex : run[l];
+#pragma unroll
+      for (int j = 0; j < kSegIPL; ++j) {
+        if (b0 + j < nb) p.carry[(sd.bucket_begin + b0 + j) * 3 + l] = cur;
+        cur = v[j][l] > cur ? v[j][l] : cur;
+      }
       run[l] = all > run[l] ? all : run[l];
     }
   }
@@ -463,14 +480,27 @@ __global__ __launch_bounds__(THREADS) void k_base(Plan p) {
   const SegDesc sd = p.segs[seg];
   const long long nb = 1ll << sd.log_nb;
   long long run[3] = {0, 0, 0};
-  for (long long b0 = 0; b0 < nb; b0 += 64) {
-    const long long b = b0 + lane;
-    const bool ok = b < nb;
+  for (long long c0 = 0; c0 < nb; c0 += 64 * kSegIPL) {
+    const long long b0 = c0 + (long long)lane * kSegIPL;
+    long long v[kSegIPL][3];
+    long long tl[3] = {0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kSegIPL; ++j) {
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        v[j][l] = b0 + j < nb ? p.bsum[(sd.bucket_begin + b0 + j) * 3 + l] : 0;
+        tl[l] += v[j][l];
+      }
+    }
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
       long long all;
-      const long long ex = wave_excl_scan_dpp<OpSum>(ok ? p.bsum[(sd.bucket_begin + b) * 3 + l] : 0, 0, all);
-      if (ok) p.base[(sd.bucket_begin + b) * 3 + l] = run[l] + ex;
+      long long cur = run[l] + wave_excl_scan_dpp<OpSum>(tl[l], 0, all);
+#pragma unroll
+      for (int j = 0; j < kSegIPL; ++j) {
+        if (b0 + j < nb) p.base[(sd.bucket_begin + b0 + j) * 3 + l] = cur;
+        cur += v[j][l];
+      }
       run[l] += all;
     }
   }
@@ -900,39 +930,72 @@ __device__ long long measure_before(const Plan& p, int seg, int l, long long t) 
   return base + pl + (ce < t ? ce : t) - cs;
 }
 
+// Region, part 1: one thread per (resource, level, end of the region) clips by
+// binary search; a slice of kRegionSlice resources of one region per
+// workgroup writes their state times and adds its sums and maxima to the
+// region's accumulator (exact integer atomics: the order does not matter).
+constexpr int kRegionSlice = 32;
+
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_region(Plan p, const RegionDesc* regions, Tree* trees,
-                                                    long long* times) {
+__global__ __launch_bounds__(THREADS) void k_region_part(Plan p, const RegionDesc* regions, long long* times) {
+  static_assert(THREADS == 8 * kRegionSlice, "8 threads per resource");
+  __shared__ long long sM[kRegionSlice][4][2];
   __shared__ long long lds[THREADS / 64 * 10];
   const RegionDesc rd = regions[blockIdx.x];
-  const long long E = rd.t1 - rd.t0;
   const int R = rd.n_hosts + rd.n_devices;
-  // sums: U, W, MPI, Other, UW, K, M ; maxes: UW, K, KM
-  long long sU = 0, sW = 0, sMPI = 0, sO = 0, sK = 0, sM = 0;
-  long long mUW = 0, mK = 0, mKM = 0;
-  for (int r = threadIdx.x; r < R; r += THREADS) {
-    const int seg = rd.seg_begin + r;
-    const bool host = r < rd.n_hosts;
-    const int nl = host ? 3 : 2;
+  const int r0 = blockIdx.y * kRegionSlice;
+  if (r0 >= R) return;  // uniform: this slice lies past the region's resources
+  const int rl = threadIdx.x >> 3, l = (threadIdx.x >> 1) & 3, ep = threadIdx.x & 1;
+  const int r = r0 + rl;
+  const bool host = r < rd.n_hosts;
+  if (r < R && l < (host ? 3 : 2)) sM[rl][l][ep] = measure_before(p, rd.seg_begin + r, l, ep ? rd.t1 : rd.t0);
+  __syncthreads();
+  const long long E = rd.t1 - rd.t0;
+  // sums: U, W, MPI, Other, K, M ; maxes: U+W, K, K+M
+  long long v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if ((threadIdx.x & 7) == 0 && r < R) {
     long long D[3] = {0, 0, 0};
-    for (int l = 0; l < nl; ++l) D[l] = measure_before(p, seg, l, rd.t1) - measure_before(p, seg, l, rd.t0);
+    for (int k = 0; k < (host ? 3 : 2); ++k) D[k] = sM[rl][k][1] - sM[rl][k][0];
     long long* out = times + (rd.times_off + r) * 4;
     if (host) {
       const long long u = D[0], w = D[1] - D[0], mpi = D[2] - D[1], o = E - D[2];
       out[0] = u; out[1] = w; out[2] = mpi; out[3] = o;
-      sU += u; sW += w; sMPI += mpi; sO += o;
-      mUW = u + w > mUW ? u + w : mUW;
+      v[0] = u; v[1] = w; v[2] = mpi; v[3] = o;
+      v[6] = u + w;
     } else {
       const long long k = D[0], mm = D[1] - D[0], idle = E - D[1];
       out[0] = k; out[1] = mm; out[2] = idle; out[3] = 0;
-      sK += k; sM += mm;
-      mK = k > mK ? k : mK;
-      mKM = k + mm > mKM ? k + mm : mKM;
+      v[4] = k; v[5] = mm;
+      v[7] = k;
+      v[8] = k + mm;
     }
   }
-  long long v[9] = {sU, sW, sMPI, sO, sK, sM, mUW, mK, mKM};
   block_tree<THREADS>(v, lds);
-  if (threadIdx.x == 0) trees[blockIdx.x] = make_tree(E, rd.n_hosts, rd.n_devices, v);
+  if (threadIdx.x == 0) {
+    unsigned long long* acc = p.racc + (long long)blockIdx.x * 9;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+      if (v[i]) atomicAdd(acc + i, (unsigned long long)v[i]);
+#pragma unroll
+    for (int i = 6; i < 9; ++i)
+      if (v[i]) atomicMax(acc + i, (unsigned long long)v[i]);
+  }
+}
+
+// Region, part 2: one thread per region turns the accumulator into the tree
+// (FP64 ratios) and clears it for the next launch.
+__global__ __launch_bounds__(64) void k_region_final(Plan p, const RegionDesc* regions, int n_regions, Tree* trees) {
+  const int g = blockIdx.x * 64 + threadIdx.x;
+  if (g >= n_regions) return;
+  const RegionDesc rd = regions[g];
+  unsigned long long* acc = p.racc + (long long)g * 9;
+  long long v[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    v[i] = (long long)acc[i];
+    acc[i] = 0;
+  }
+  trees[g] = make_tree(rd.t1 - rd.t0, rd.n_hosts, rd.n_devices, v);
 }
 
 // ----------------------------------------------------------------------------
@@ -1008,10 +1071,14 @@ hipError_t launch_base(const Plan& p, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_region(const Plan& p, const RegionDesc* regions, int n_regions, Tree* trees, long long* times,
-                         hipStream_t st) {
+hipError_t launch_region(const Plan& p, const RegionDesc* regions, int n_regions, int max_res, Tree* trees,
+                         long long* times, hipStream_t st) {
   if (n_regions == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_region<256>, dim3((unsigned)n_regions), dim3(256), 0, st, p, regions, trees, times);
+  const unsigned slices = (unsigned)std::max(1, (max_res + kRegionSlice - 1) / kRegionSlice);
+  hipLaunchKernelGGL(k_region_part<8 * kRegionSlice>, dim3((unsigned)n_regions, slices), dim3(8 * kRegionSlice), 0, st,
+                     p, regions, times);
+  hipLaunchKernelGGL(k_region_final, dim3((unsigned)((n_regions + 63) / 64)), dim3(64), 0, st, p, regions, n_regions,
+                     trees);
   return hipGetLastError();
 }
 

@@ -189,6 +189,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   small += carve_bytes(n_buckets, sizeof(unsigned int));
   small += carve_bytes(n_owners, sizeof(unsigned int));
   small += carve_bytes(n_regions, sizeof(RegionDesc)) + carve_bytes(n_regions, sizeof(Tree));
+  small += carve_bytes(9 * n_regions, sizeof(unsigned long long));
   small += carve_bytes(4 * n_times, sizeof(long long));
   if (!meta.reserve(a, small, false)) {
     err = "device allocation of " + std::to_string(small) + " bytes (build metadata) failed";
@@ -231,6 +232,8 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   p.pad2 = 0;
   d_regions = carve<RegionDesc>(cur, n_regions);
   d_trees = carve<Tree>(cur, n_regions);
+  p.racc = carve<unsigned long long>(cur, 9 * n_regions);
+  p.n_racc = n_regions;
   d_times = carve<long long>(cur, 4 * n_times);
   p.elems = (Elem*)elems.ptr;
   p.elems2 = (Elem*)elems2.ptr;
@@ -448,7 +451,9 @@ hpop_status Engine::enqueue(bool build, bool with_timing, std::string& err) {
     HPOP_HIP(launch_base(p, st), "k_base");
     HPOP_HIP(mark("base"), "hipEventRecord");
   }
-  HPOP_HIP(launch_region(p, ws.d_regions, nreg, ws.d_trees, ws.d_times, st), "k_region");
+  int max_res = 0;
+  for (const RegionDesc& rd : h_regions) max_res = std::max(max_res, rd.n_hosts + rd.n_devices);
+  HPOP_HIP(launch_region(p, ws.d_regions, nreg, max_res, ws.d_trees, ws.d_times, st), "k_region");
   HPOP_HIP(mark("region"), "hipEventRecord");
   n_marks = ev;
   // results: trees, first bad record, oversized buckets, slot overflow
