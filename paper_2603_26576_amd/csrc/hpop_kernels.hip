@@ -416,12 +416,13 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
 }
 
 // ----------------------------------------------------------------------------
-// carry / base: per-segment scans over buckets, one wave per segment; a lane
-// takes kSegIPL consecutive buckets per round (serial within the lane, DPP
-// across lanes), so a segment of 2048 buckets needs 4 rounds
+// carry / base: per-segment scans over buckets, one wave per segment. A round
+// covers kSegRows x 64 buckets: all of its loads are issued first (row j,
+// lane i: bucket c0 + 64 j + i, coalesced), then one DPP scan per row in
+// bucket order, then the stores; so a round costs one memory round trip
 // ----------------------------------------------------------------------------
 
-constexpr int kSegIPL = 8;
+constexpr int kSegRows = 8;
 
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
@@ -434,38 +435,36 @@ __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
   // the running max end before any record: just below the first start
   const long long init = st.min_s > st.max_s ? -1 : (long long)st.min_s - 1;
   long long run[3] = {init, init, init};
-  for (long long c0 = 0; c0 < nb; c0 += 64 * kSegIPL) {
-    const long long b0 = c0 + (long long)lane * kSegIPL;
-    long long v[kSegIPL][3];
-    long long tl[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
+  for (long long c0 = 0; c0 < nb; c0 += 64 * kSegRows) {
+    unsigned long long m[kSegRows][3];
 #pragma unroll
-    for (int j = 0; j < kSegIPL; ++j) {
-      const long long b = b0 + j;
-      v[j][0] = v[j][1] = v[j][2] = LLONG_MIN;
+    for (int j = 0; j < kSegRows; ++j) {
+      const long long b = c0 + 64 * j + lane;
+      m[j][0] = m[j][1] = m[j][2] = 0;
       if (b < nb) {
         p.bucket_seg[sd.bucket_begin + b] = (int32_t)seg;
-        const unsigned long long* m = p.maxend + (sd.bucket_begin + b) * 3;
-        const long long m0 = m[0] ? (long long)m[0] : LLONG_MIN;
-        const long long m1 = m[1] ? (long long)m[1] : LLONG_MIN;
-        const long long m2 = m[2] ? (long long)m[2] : LLONG_MIN;
-        v[j][0] = m0;
-        v[j][1] = m1 > m0 ? m1 : m0;
-        v[j][2] = m2 > v[j][1] ? m2 : v[j][1];
+        const unsigned long long* q = p.maxend + (sd.bucket_begin + b) * 3;
+        m[j][0] = q[0];
+        m[j][1] = q[1];
+        m[j][2] = q[2];
       }
-#pragma unroll
-      for (int l = 0; l < 3; ++l) tl[l] = v[j][l] > tl[l] ? v[j][l] : tl[l];
     }
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      long long all;
-      const long long ex = wave_excl_scan_dpp<OpMax>(tl[l], LLONG_MIN, all);
-      long long cur = ex > run[l] ? ex : run[l];
+    for (int j = 0; j < kSegRows; ++j) {
+      const long long b = c0 + 64 * j + lane;
+      long long v[3];
+      v[0] = m[j][0] ? (long long)m[j][0] : LLONG_MIN;
+      const long long m1 = m[j][1] ? (long long)m[j][1] : LLONG_MIN;
+      const long long m2 = m[j][2] ? (long long)m[j][2] : LLONG_MIN;
+      v[1] = m1 > v[0] ? m1 : v[0];
+      v[2] = m2 > v[1] ? m2 : v[1];
 #pragma unroll
-      for (int j = 0; j < kSegIPL; ++j) {
-        if (b0 + j < nb) p.carry[(sd.bucket_begin + b0 + j) * 3 + l] = cur;
-        cur = v[j][l] > cur ? v[j][l] : cur;
+      for (int l = 0; l < 3; ++l) {
+        long long all;
+        const long long ex = wave_excl_scan_dpp<OpMax>(v[l], LLONG_MIN, all);
+        if (b < nb) p.carry[(sd.bucket_begin + b) * 3 + l] = ex > run[l] ? ex : run[l];
+        run[l] = all > run[l] ? all : run[l];
       }
-      run[l] = all > run[l] ? all : run[l];
     }
   }
   // largest end of the segment (level 2 holds every kind); no record: the min start
@@ -480,28 +479,24 @@ __global__ __launch_bounds__(THREADS) void k_base(Plan p) {
   const SegDesc sd = p.segs[seg];
   const long long nb = 1ll << sd.log_nb;
   long long run[3] = {0, 0, 0};
-  for (long long c0 = 0; c0 < nb; c0 += 64 * kSegIPL) {
-    const long long b0 = c0 + (long long)lane * kSegIPL;
-    long long v[kSegIPL][3];
-    long long tl[3] = {0, 0, 0};
+  for (long long c0 = 0; c0 < nb; c0 += 64 * kSegRows) {
+    long long v[kSegRows][3];
 #pragma unroll
-    for (int j = 0; j < kSegIPL; ++j) {
+    for (int j = 0; j < kSegRows; ++j) {
+      const long long b = c0 + 64 * j + lane;
 #pragma unroll
-      for (int l = 0; l < 3; ++l) {
-        v[j][l] = b0 + j < nb ? p.bsum[(sd.bucket_begin + b0 + j) * 3 + l] : 0;
-        tl[l] += v[j][l];
-      }
+      for (int l = 0; l < 3; ++l) v[j][l] = b < nb ? p.bsum[(sd.bucket_begin + b) * 3 + l] : 0;
     }
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-      long long all;
-      long long cur = run[l] + wave_excl_scan_dpp<OpSum>(tl[l], 0, all);
+    for (int j = 0; j < kSegRows; ++j) {
+      const long long b = c0 + 64 * j + lane;
 #pragma unroll
-      for (int j = 0; j < kSegIPL; ++j) {
-        if (b0 + j < nb) p.base[(sd.bucket_begin + b0 + j) * 3 + l] = cur;
-        cur += v[j][l];
+      for (int l = 0; l < 3; ++l) {
+        long long all;
+        const long long ex = wave_excl_scan_dpp<OpSum>(v[j][l], 0, all);
+        if (b < nb) p.base[(sd.bucket_begin + b) * 3 + l] = run[l] + ex;
+        run[l] += all;
       }
-      run[l] += all;
     }
   }
   if (lane == 0) {
@@ -1044,7 +1039,7 @@ hipError_t launch_scatter(const Plan& p, hipStream_t st) {
 
 hipError_t launch_carry(const Plan& p, hipStream_t st) {
   if (p.n_segs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_carry<256>, dim3((unsigned)((p.n_segs + 3) / 4)), dim3(256), 0, st, p);
+  hipLaunchKernelGGL(k_carry<64>, dim3((unsigned)p.n_segs), dim3(64), 0, st, p);  // a wave per segment, spread over the CUs
   return hipGetLastError();
 }
 
@@ -1067,7 +1062,7 @@ hipError_t launch_merge_block(const Plan& p, int cap, hipStream_t st) {
 
 hipError_t launch_base(const Plan& p, hipStream_t st) {
   if (p.n_segs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_base<256>, dim3((unsigned)((p.n_segs + 3) / 4)), dim3(256), 0, st, p);
+  hipLaunchKernelGGL(k_base<64>, dim3((unsigned)p.n_segs), dim3(64), 0, st, p);  // a wave per segment, spread over the CUs
   return hipGetLastError();
 }
 
