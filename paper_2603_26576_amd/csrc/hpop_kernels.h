@@ -9,7 +9,7 @@ namespace hpop {
 constexpr int kScanTile = 4096;  // bucket counts per workgroup of the offset scan
 constexpr int kHistWin = 512;    // LDS bucket window of one streaming tile
 constexpr int kWaveCap = 512;    // records one wave sorts and flattens on its own
-constexpr int kWaveBins = 1024;  // sub-bins of the wave path's counting sort
+constexpr int kWaveBins = 512;   // sub-bins of the wave path's counting sort (at most)
 
 hipError_t launch_reset(const Plan& p, hipStream_t st);
 hipError_t launch_stats(const Plan& p, hipStream_t st);

@@ -41,7 +41,7 @@ __global__ void k_reset(Plan p) {
     p.oversized[0] = 0;
     p.oversized[1] = 0;
   }
-  if (tid < 4) p.ticket[tid] = 0;
+  if (tid < 6) p.ticket[tid] = 0;
   for (long long i = tid; i < p.n_owners; i += stride) p.owner_err[i] = 0;
   for (long long i = tid; i < 9 * p.n_racc; i += stride) p.racc[i] = 0;
   // tile -> chunk map of the streaming passes, so that their workgroups start
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(THREADS) void k_merge_block(Plan p) {
 // Comparisons, maxima and measure differences are unchanged by the common
 // shift, and the union measure of one bucket's records stays below 2^32, so
 // every quantity of the flatten fits 32 bits. The sort is a counting sort on
-// the top bits of the start into 128-1024 sub-bins, writing keys and ends to
+// the top bits of the start into 128-512 sub-bins (about one per record), writing keys and ends to
 // their sorted places in LDS, then an insertion sort inside each sub-bin that
 // received two or more records (equal starts may end in any order: the merged
 // result does not depend on it). Other buckets (more records, any record in
@@ -656,14 +656,20 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
   unsigned int kv[IPL], ev[IPL];
   lds_load<IPL>(W.key + q0, kv);
   lds_load<IPL>(W.end + q0, ev);
-  unsigned int sv[IPL], sl[IPL];
+  unsigned int sv[IPL];
 #pragma unroll
   for (int j = 0; j < IPL; ++j) {
-    sv[j] = (kv[j] >> 2) + 1;             // start - lo + 1, the same shift as the ends
-    sl[j] = j < cnt ? (kv[j] & 3u) : 3u;  // positions past the bucket belong to no level
+    sv[j] = (kv[j] >> 2) + 1;  // start - lo + 1, the same shift as the ends
+    if (j >= cnt) {
+      // positions past the bucket belong to no level: rank 3, empty pair
+      kv[j] = 0xFFFFFFFFu;
+      sv[j] = 0;
+      ev[j] = 0;
+    }
   }
-  auto s_in = [&](int j, int l) { return sl[j] <= (unsigned int)l ? sv[j] : 0u; };
-  auto e_in = [&](int j, int l) { return sl[j] <= (unsigned int)l ? ev[j] : 0u; };
+  // the top level holds every record; the ones below only ranks <= l
+  auto s_in = [&](int j, int l) { return l == NLEV - 1 || (kv[j] & 3u) <= (unsigned int)l ? sv[j] : 0u; };
+  auto e_in = [&](int j, int l) { return l == NLEV - 1 || (kv[j] & 3u) <= (unsigned int)l ? ev[j] : 0u; };
   // the largest end before each lane: earlier lanes, else the earlier buckets
   unsigned int M[NLEV];
 #pragma unroll
@@ -767,9 +773,9 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   const int nlev = sd.n_levels;
   kor >>= 2;
   kor = (unsigned int)wave_reduce_i32<OpOrI>((int)kor, 0);
-  // sub-bins: about two per record, 128 .. 1024; a lane owns bpl of them (two per LDS word)
+  // sub-bins: about one per record, 128 .. 512; a lane owns bpl of them (two per LDS word)
   int dbits = 7;
-  while ((1 << dbits) < 2 * ni && dbits < 10) ++dbits;
+  while ((1 << dbits) < ni && dbits < 9) ++dbits;
   const int nbins = 1 << dbits, wpl = nbins >> 7;
   for (int j = 0; j < wpl; ++j) W.bins[lane * wpl + j] = 0;
   wave_sync();
@@ -850,13 +856,12 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   return true;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_merge_wave(Plan p) {
-  __shared__ WaveSmem wsm[4];
+// One bucket by one wave. Returns 0 when done, 1 when it holds more than
+// 64 x MAXIPL (at most kWaveCap) records of the 8 B form (the large-bucket
+// wave kernel takes it), 2 when it needs the block path.
+template <int MAXIPL>
+__device__ __forceinline__ int merge_wave_bucket(const Plan& p, WaveSmem& W, long long gb) {
   const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // everything per bucket is wave-uniform
-  const long long gb = (long long)blockIdx.x * 4 + wave;
-  if (gb >= p.n_buckets) return;
-  WaveSmem& W = wsm[wave];
   const BucketRecs br = bucket_recs(p, gb);
   const long long n = (long long)br.n8 + br.n16;
   const long long off = (long long)p.offsets[gb];
@@ -872,19 +877,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) voi
       p.bsum[gb * 3 + lane] = 0;
       p.ncomp[gb * 3 + lane] = 0;
     }
-    return;
+    return 0;
   }
-  bool done = false;
-  if (br.n16 == 0 && n <= kWaveCap) {
-    // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
-    const int ni = (int)n;
-    const uint2* rec = br.narrow;
-    if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry, maxe);
-    else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry, maxe);
-    else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, rec, carry, maxe);
-    else done = wave_bucket<8>(p, W, gb, off, ni, rec, carry, maxe);
+  if (br.n16 != 0 || n > kWaveCap) return 2;
+  // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
+  const int ni = (int)n;
+  if (ni > 64 * MAXIPL) return 1;
+  const uint2* rec = br.narrow;
+  bool done;
+  if (MAXIPL == 8) done = wave_bucket<8>(p, W, gb, off, ni, rec, carry, maxe);
+  else if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry, maxe);
+  else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry, maxe);
+  else done = wave_bucket<4>(p, W, gb, off, ni, rec, carry, maxe);
+  return done ? 0 : 2;
+}
+
+// A wave per bucket of up to 256 records (46 VGPRs, 5 KB of LDS: 8 waves per
+// SIMD); larger buckets of the 8 B form go to queue_big.
+__global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
+  __shared__ WaveSmem wsm[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // everything per bucket is wave-uniform
+  const long long gb = (long long)blockIdx.x * 4 + wave;
+  if (gb >= p.n_buckets) return;
+  const int r = merge_wave_bucket<4>(p, wsm[wave], gb);
+  if (r == 1 && lane == 0) p.queue_big[atomicAdd(&p.ticket[3], 1u)] = (unsigned int)gb;
+  if (r == 2 && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
+}
+
+// Buckets of 257-512 records: persistent waves take them from queue_big
+// (ticket[3] of them, final once k_merge_wave has finished) with a shared
+// counter (ticket[4]); every wave exits once the counter passes the length.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_merge_wave_big(Plan p) {
+  __shared__ WaveSmem wsm[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const unsigned int qlen = __hip_atomic_load(&p.ticket[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (true) {
+    unsigned int idx = 0;
+    if (lane == 0) idx = atomicAdd(&p.ticket[4], 1u);
+    idx = (unsigned int)__builtin_amdgcn_readfirstlane((int)idx);
+    if (idx >= qlen) break;
+    const long long gb = (long long)p.queue_big[idx];
+    if (merge_wave_bucket<8>(p, wsm[wave], gb) != 0 && lane == 0)
+      p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
   }
-  if (!done && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
 }
 
 // ----------------------------------------------------------------------------
@@ -1046,6 +1083,9 @@ hipError_t launch_carry(const Plan& p, hipStream_t st) {
 hipError_t launch_merge_wave(const Plan& p, hipStream_t st) {
   if (p.n_buckets == 0) return hipSuccess;
   hipLaunchKernelGGL(k_merge_wave, dim3((unsigned)((p.n_buckets + 3) / 4)), dim3(256), 0, st, p);
+  // persistent waves for the large buckets: 24 per CU on 256 CUs at most
+  const unsigned big = (unsigned)std::min<long long>((p.n_buckets + 3) / 4, 256 * 6);
+  hipLaunchKernelGGL(k_merge_wave_big, dim3(big), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
