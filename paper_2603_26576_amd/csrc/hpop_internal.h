@@ -138,10 +138,8 @@ struct Plan {
   int64_t n_elems;
   unsigned long long* err;           // [0] first bad record: chunk << 40 | index
   unsigned long long* scan_state;    // decoupled look-back words of the bucket scan
-  unsigned int* ticket;              // [6]: scan ticket, block-path take counter, block-path queue length,
-                                     //      large-bucket queue length, large-bucket take counter, unused
+  unsigned int* ticket;              // [4]: scan ticket, block-path take counter, block-path queue length
   unsigned int* queue;               // [n_buckets] buckets handed to the block path
-  unsigned int* queue_big;           // [n_buckets] buckets of 257-512 records for the 8-per-lane wave kernel
   unsigned long long* oversized;     // [0] buckets above the on-chip capacity, [1] buckets above slot_cap
   unsigned int* owner_err;           // [n_owners] set when an owner has an invalid record
   unsigned long long* racc;          // [n_racc][9] per-region partial sums and maxima, zero between launches

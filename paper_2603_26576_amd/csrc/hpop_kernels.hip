@@ -41,7 +41,7 @@ __global__ void k_reset(Plan p) {
     p.oversized[0] = 0;
     p.oversized[1] = 0;
   }
-  if (tid < 6) p.ticket[tid] = 0;
+  if (tid < 4) p.ticket[tid] = 0;
   for (long long i = tid; i < p.n_owners; i += stride) p.owner_err[i] = 0;
   for (long long i = tid; i < 9 * p.n_racc; i += stride) p.racc[i] = 0;
   // tile -> chunk map of the streaming passes, so that their workgroups start
@@ -856,12 +856,15 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   return true;
 }
 
-// One bucket by one wave. Returns 0 when done, 1 when it holds more than
-// 64 x MAXIPL (at most kWaveCap) records of the 8 B form (the large-bucket
-// wave kernel takes it), 2 when it needs the block path.
-template <int MAXIPL>
-__device__ __forceinline__ int merge_wave_bucket(const Plan& p, WaveSmem& W, long long gb) {
+// One wave per bucket (at most 80 VGPRs: 6 waves per SIMD). Buckets that need
+// the block path go to its queue.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_merge_wave(Plan p) {
+  __shared__ WaveSmem wsm[4];
   const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // everything per bucket is wave-uniform
+  const long long gb = (long long)blockIdx.x * 4 + wave;
+  if (gb >= p.n_buckets) return;
+  WaveSmem& W = wsm[wave];
   const BucketRecs br = bucket_recs(p, gb);
   const long long n = (long long)br.n8 + br.n16;
   const long long off = (long long)p.offsets[gb];
@@ -877,51 +880,19 @@ __device__ __forceinline__ int merge_wave_bucket(const Plan& p, WaveSmem& W, lon
       p.bsum[gb * 3 + lane] = 0;
       p.ncomp[gb * 3 + lane] = 0;
     }
-    return 0;
+    return;
   }
-  if (br.n16 != 0 || n > kWaveCap) return 2;
-  // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
-  const int ni = (int)n;
-  if (ni > 64 * MAXIPL) return 1;
-  const uint2* rec = br.narrow;
-  bool done;
-  if (MAXIPL == 8) done = wave_bucket<8>(p, W, gb, off, ni, rec, carry, maxe);
-  else if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry, maxe);
-  else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry, maxe);
-  else done = wave_bucket<4>(p, W, gb, off, ni, rec, carry, maxe);
-  return done ? 0 : 2;
-}
-
-// A wave per bucket of up to 256 records (46 VGPRs, 5 KB of LDS: 8 waves per
-// SIMD); larger buckets of the 8 B form go to queue_big.
-__global__ __launch_bounds__(256) void k_merge_wave(Plan p) {
-  __shared__ WaveSmem wsm[4];
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // everything per bucket is wave-uniform
-  const long long gb = (long long)blockIdx.x * 4 + wave;
-  if (gb >= p.n_buckets) return;
-  const int r = merge_wave_bucket<4>(p, wsm[wave], gb);
-  if (r == 1 && lane == 0) p.queue_big[atomicAdd(&p.ticket[3], 1u)] = (unsigned int)gb;
-  if (r == 2 && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
-}
-
-// Buckets of 257-512 records: persistent waves take them from queue_big
-// (ticket[3] of them, final once k_merge_wave has finished) with a shared
-// counter (ticket[4]); every wave exits once the counter passes the length.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_merge_wave_big(Plan p) {
-  __shared__ WaveSmem wsm[4];
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const unsigned int qlen = __hip_atomic_load(&p.ticket[3], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  while (true) {
-    unsigned int idx = 0;
-    if (lane == 0) idx = atomicAdd(&p.ticket[4], 1u);
-    idx = (unsigned int)__builtin_amdgcn_readfirstlane((int)idx);
-    if (idx >= qlen) break;
-    const long long gb = (long long)p.queue_big[idx];
-    if (merge_wave_bucket<8>(p, wsm[wave], gb) != 0 && lane == 0)
-      p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
+  bool done = false;
+  if (br.n16 == 0 && n <= kWaveCap) {
+    // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
+    const int ni = (int)n;
+    const uint2* rec = br.narrow;
+    if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry, maxe);
+    else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry, maxe);
+    else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, rec, carry, maxe);
+    else done = wave_bucket<8>(p, W, gb, off, ni, rec, carry, maxe);
   }
+  if (!done && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
 }
 
 // ----------------------------------------------------------------------------
@@ -1083,9 +1054,6 @@ hipError_t launch_carry(const Plan& p, hipStream_t st) {
 hipError_t launch_merge_wave(const Plan& p, hipStream_t st) {
   if (p.n_buckets == 0) return hipSuccess;
   hipLaunchKernelGGL(k_merge_wave, dim3((unsigned)((p.n_buckets + 3) / 4)), dim3(256), 0, st, p);
-  // persistent waves for the large buckets: 24 per CU on 256 CUs at most
-  const unsigned big = (unsigned)std::min<long long>((p.n_buckets + 3) / 4, 256 * 6);
-  hipLaunchKernelGGL(k_merge_wave_big, dim3(big), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 

@@ -185,8 +185,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   small += carve_bytes(3 * n_buckets, sizeof(long long)) * 3;
   small += carve_bytes(3 * n_buckets, sizeof(unsigned int));
   small += carve_bytes(3 * n_segs, sizeof(long long));
-  small += carve_bytes(1, 8) + carve_bytes(nscan, 8) + carve_bytes(6, 4) + carve_bytes(2, 8);
-  small += carve_bytes(n_buckets, sizeof(unsigned int));
+  small += carve_bytes(1, 8) + carve_bytes(nscan, 8) + carve_bytes(4, 4) + carve_bytes(2, 8);
   small += carve_bytes(n_buckets, sizeof(unsigned int));
   small += carve_bytes(n_owners, sizeof(unsigned int));
   small += carve_bytes(n_regions, sizeof(RegionDesc)) + carve_bytes(n_regions, sizeof(Tree));
@@ -225,10 +224,9 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   p.seg_total = carve<long long>(cur, 3 * n_segs);
   p.err = carve<unsigned long long>(cur, 1);
   p.scan_state = carve<unsigned long long>(cur, nscan);
-  p.ticket = carve<unsigned int>(cur, 6);
+  p.ticket = carve<unsigned int>(cur, 4);
   p.oversized = carve<unsigned long long>(cur, 2);
   p.queue = carve<unsigned int>(cur, n_buckets);
-  p.queue_big = carve<unsigned int>(cur, n_buckets);
   p.owner_err = carve<unsigned int>(cur, n_owners);
   p.n_owners = (int32_t)n_owners;
   p.pad2 = 0;
