@@ -164,6 +164,53 @@ def test_long_intervals_and_wide_buckets():
         hp.hpop_session_destroy(s_)
 
 
+def long_interval_traces(seed):
+    """A dense device resource with far-ending records next to a sparse one
+    (buckets wider than 2^30 ns), and a host with long MPI states."""
+    rng = np.random.default_rng(seed)
+    s = np.sort(rng.integers(0, 1 << 34, size=20000)).astype(np.int64)
+    e = s + rng.integers(0, 2000, size=s.size)
+    far = rng.random(s.size) < 0.003
+    e[far] = s[far] + rng.integers(1 << 32, 1 << 35, size=int(far.sum()))
+    k = rng.random(s.size) < 0.35
+    s2 = np.sort(rng.integers(0, 1 << 45, size=1500)).astype(np.int64)
+    e2 = s2 + rng.integers(0, 1 << 40, size=s2.size)
+    dev = [tg.Chunk(0, tg.DEV_KERNEL, s[~k], e[~k]), tg.Chunk(0, tg.DEV_MEMOP, s[k], e[k]),
+           tg.Chunk(1, tg.DEV_KERNEL, s2, e2)]
+    s3 = np.sort(rng.integers(0, 1 << 36, size=8000)).astype(np.int64)
+    kinds = rng.integers(0, 3, size=s3.size)
+    e3 = s3 + np.where(kinds == 2, rng.integers(1 << 31, 1 << 33, size=s3.size), rng.integers(0, 5000, size=s3.size))
+    host = [tg.Chunk(0, kd, s3[kinds == kd], e3[kinds == kd]) for kd in (tg.HOST_USEFUL, tg.HOST_OFFLOAD, tg.HOST_MPI)]
+    regions = [(0, 1 << 46), (1 << 20, 1 << 33), (5 << 30, 7 << 30)]
+    return tg.Trace(0, 2, dev, regions), tg.Trace(1, 0, host, regions)
+
+
+def test_batched_mixed_record_forms():
+    """One batched build over traces whose resources take the 8 B form (with
+    clamped far ends), the 16 B form, or are tiny."""
+    rng = np.random.default_rng(91)
+    traces = list(long_interval_traces(92)) + [tg.random_tiny(rng, max_span=3000, max_events=200, t0=int(rng.integers(0, 1 << 60)),
+                                                             n_regions=3) for _ in range(4)]
+    sessions = []
+    try:
+        for tr in traces:
+            s, _ = new_session(tr)
+            sessions.append(s)
+        for flags in (0, hp.HPOP_FORCE_REBUILD):
+            trees = hp.hpop_batch_compute(sessions, flags)
+            k = 0
+            for tr in traces:
+                want = oracle.compute(tr)
+                for g in range(len(tr.regions)):
+                    np.testing.assert_array_equal(hp.tree_sums(trees[k]), want["sums"][g])
+                    np.testing.assert_array_equal(hp.tree_ratios(trees[k]).view(np.int64),
+                                                  want["ratios"][g].view(np.int64))
+                    k += 1
+    finally:
+        for s in sessions:
+            hp.hpop_session_destroy(s)
+
+
 def test_identical_starts_and_degenerate_intervals():
     n = 5000
     s = np.full(n, 7_000_000, np.int64)

@@ -209,3 +209,42 @@ def test_replay_equals_oracle():
         want = expected(ranks, origin, qs, q)
         check_tree(r, want, 0, "replay session %d query %d region" % (s, q))
         check_tree(g, want, 1, "replay session %d query %d global" % (s, q))
+
+
+def test_long_records_across_queries():
+    """Records lasting 2^32-2^35 ns (ends far past their time bucket) in
+    consecutive queries of one session: the serving splice must see their true
+    ends, also when a later query's records fall under them."""
+    rng = np.random.default_rng(57)
+    ranks = 2
+    origin = 1 << 40
+    qs = []
+    t = origin
+    for q in range(4):
+        chunks = []
+        for r in range(2 * ranks):
+            kinds = (tg.HOST_USEFUL, tg.HOST_OFFLOAD, tg.HOST_MPI) if r < ranks else (tg.DEV_KERNEL, tg.DEV_MEMOP)
+            for kd in kinds:
+                n = int(rng.integers(200, 2000))
+                s = np.sort(t + rng.integers(-(1 << 30), 1 << 36, size=n)).astype(np.int64)
+                s = np.maximum(s, origin)
+                d = rng.integers(1, 50_000, size=n)
+                far = rng.random(n) < 0.01
+                d[far] = rng.integers(1 << 32, 1 << 35, size=int(far.sum()))
+                chunks.append(tg.Chunk(r, kd, s, s + d))
+        hi = max(int(c.end.max()) for c in chunks)
+        qs.append((chunks, t, max(hi, t + 1)))
+        t = max(hi, t + 1)
+    srv = hp.hpop_server_create(max_sessions=2, max_inflight=4)
+    try:
+        sid = hp.hpop_server_open_session(srv, ranks, ranks, origin)
+        for q, (chunks, t0, t1) in enumerate(qs):
+            payload = as_payload(chunks, q % 2 == 1)  # kept alive until the query is done
+            tk = hp.hpop_server_submit(srv, sid, payload, hp.HPOP_MEM_DEVICE if q % 2 else hp.HPOP_MEM_HOST, t0, t1)
+            reg, glob = hp.hpop_server_wait(srv, tk)
+            del payload
+            want = expected(ranks, origin, qs, q)
+            check_tree(reg, want, 0, "long records query %d region" % q)
+            check_tree(glob, want, 1, "long records query %d global" % q)
+    finally:
+        hp.hpop_server_destroy(srv)
