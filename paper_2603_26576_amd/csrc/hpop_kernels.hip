@@ -856,9 +856,10 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   return true;
 }
 
-// One wave per bucket (at most 80 VGPRs: 6 waves per SIMD). Buckets that need
+// One wave per bucket, 8 waves per SIMD (64 VGPRs: the 8-record-per-lane path spills a few
+// values, which costs less than the lost occupancy). Buckets that need
 // the block path go to its queue.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_merge_wave(Plan p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge_wave(Plan p) {
   __shared__ WaveSmem wsm[4];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // everything per bucket is wave-uniform
