@@ -190,15 +190,18 @@ def bench_batched(hp, traces, steps, warmup, tune_cache=None):
             "tuning": {"bucket_target": tun.bucket_target, "bucket_cap": tun.bucket_cap, "tile_elems": tun.tile_elems}}
 
 
-def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, streams=4, warm=1_000_000):
+def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, streams=4, warm=1_000_000,
+                host_lambdas=()):
     """Poisson region-close queries against device-resident sessions.
 
     Each session's record stream is generated once and uploaded to the GPU;
     its first `warm` records are applied untimed, then every query takes the
     next slice of its session's stream (log-uniform 10^4-10^6 records, spread
     over all resources in proportion) and closes the region
-    [previous close, new frontier). Payloads are device-resident, so latency
-    and throughput measure the serving runtime and kernels, not PCIe.
+    [previous close, new frontier). With device-resident payloads latency and
+    throughput measure the serving runtime and kernels; the runs at
+    `host_lambdas` hand the same slices over from host memory (copied at
+    submission, staged through pinned memory), so they include PCIe.
     """
     import ctypes
     import threading
@@ -218,22 +221,24 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
         chunks = []
         for c in tr.chunks:
             chunks.append((c.resource, c.kind, torch.from_numpy(c.start).cuda(), torch.from_numpy(c.end).cuda(),
-                           np.maximum.accumulate(c.end)))
+                           np.maximum.accumulate(c.end), c.start, c.end))
         sess.append({"origin": tr.info["t0"], "chunks": chunks, "total": tr.n_events})
     torch.cuda.synchronize()
 
-    def slices(sidx, n_rec, cursor):
+    def slices(sidx, n_rec, cursor, host=False):
         """hpop_event_chunk array for the next n_rec records of a session, and the new frontier."""
         S = sess[sidx]
         arr = (hp.hpop_event_chunk * len(S["chunks"]))()
         frontier = S["origin"]
         k = 0
-        for j, (r, kind, st, en, pmax) in enumerate(S["chunks"]):
+        for j, (r, kind, st, en, pmax, hst, hen) in enumerate(S["chunks"]):
             ln = st.numel()
             a = cursor[j]
             b = min(ln, a + max(1, int(round(n_rec * ln / S["total"]))))
             if b > a:
-                arr[k] = hp.hpop_event_chunk(r, kind, st.data_ptr() + 8 * a, en.data_ptr() + 8 * a, b - a)
+                ps = hst.ctypes.data if host else st.data_ptr()
+                pe = hen.ctypes.data if host else en.data_ptr()
+                arr[k] = hp.hpop_event_chunk(r, kind, ps + 8 * a, pe + 8 * a, b - a)
                 k += 1
                 frontier = max(frontier, int(pmax[b - 1]))
             cursor[j] = b
@@ -241,7 +246,7 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
 
     lib = hp.lib()
     results = []
-    for lam in lambdas:
+    for lam, host in [(l, False) for l in lambdas] + [(l, True) for l in host_lambdas]:
         srv = hp.hpop_server_create(max_sessions=n_sessions, max_inflight=n_sessions, queue_capacity=1 << 16,
                                     mem_budget_bytes=64 << 30)
         try:
@@ -263,14 +268,15 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
             plan = []
             for q in range(n_queries):
                 i = int(owner[q])
-                arr, k, fr = slices(i, int(sizes[q]), cursors[i])
+                arr, k, fr = slices(i, int(sizes[q]), cursors[i], host)
                 t1 = max(fr, closes[i] + 1)
                 plan.append((sids[i], arr, k, closes[i], t1, int(sizes[q])))
                 closes[i] = t1
             arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_queries))
             queries = [(sid, (arr, k), a, b, int(arrivals[q] * 1e9))
                        for q, (sid, arr, k, a, b, n_rec) in enumerate(plan)]
-            _, _, lat_ns, wall_ns, busy = hp.hpop_server_replay(srv, queries, hp.HPOP_MEM_DEVICE)
+            _, _, lat_ns, wall_ns, busy = hp.hpop_server_replay(srv, queries,
+                                                                hp.HPOP_MEM_HOST if host else hp.HPOP_MEM_DEVICE)
             st = hp.hpop_server_get_stats(srv)
         finally:
             hp.hpop_server_destroy(srv)
@@ -278,7 +284,8 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
         ev = int(sizes.sum())
         lat_us = np.sort(lat_ns) * 1e-3
         steps_run = max(1, st.device_steps - base.device_steps)
-        results.append({"lambda_req_s": lam, "queries": n_queries, "events": ev,
+        results.append({"lambda_req_s": lam, "payload": "host" if host else "device", "queries": n_queries,
+                        "events": ev,
                         "offered_events_per_s": ev / float(arrivals[-1]),
                         "events_per_s": ev / wall,
                         "achieved_req_s": n_queries / wall,
@@ -288,9 +295,10 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
                         "mean_batch": round((st.mean_batch * st.device_steps - base.mean_batch * base.device_steps)
                                             / steps_run, 2),
                         "busy_retries": busy})
-        log("serving lambda=%d: %s" % (lam, results[-1]))
+        log("serving lambda=%d %s: %s" % (lam, "host" if host else "device", results[-1]))
     return {"sessions": n_sessions, "ranks": ranks, "devices": ranks, "streams": streams,
-            "warm_events_per_session": warm, "payload": "device-resident",
+            "warm_events_per_session": warm,
+            "payload": "device-resident, or host memory (copied at submission) where a run says so",
             "latency": "scheduled arrival to trees on the host",
             "runs": results}
 
@@ -405,6 +413,7 @@ def main():
     ap.add_argument("--serving-only", action="store_true", help="profiling aid: run only the serving leg")
     ap.add_argument("--serving-queries", type=int, default=400)
     ap.add_argument("--serving-lambdas", default="2000,10000")
+    ap.add_argument("--serving-host-lambdas", default="2000", help="runs with payloads in host memory")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON)")
     ap.add_argument("--trace-cache", default=None, help="npz file to reuse the generated workload")
@@ -430,7 +439,8 @@ def main():
 
     if args.serving_only:
         lams = [int(x) for x in args.serving_lambdas.split(",") if x]
-        print(json.dumps({"serving": serving_leg(hp, lams, args.serving_queries)}), flush=True)
+        host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x]
+        print(json.dumps({"serving": serving_leg(hp, lams, args.serving_queries, host_lambdas=host_lams)}), flush=True)
         return
     log("generating workload %s (scale %g)" % (args.workload, args.scale))
     t = time.time()
@@ -480,8 +490,9 @@ def main():
         log("batched: %s" % out["batched"])
     if not args.no_serving and args.serving_queries > 0:
         lams = [int(x) for x in args.serving_lambdas.split(",") if x]
+        host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x]
         log("serving leg: lambdas %s, %d queries each" % (lams, args.serving_queries))
-        out["serving"] = serving_leg(hp, lams, args.serving_queries)
+        out["serving"] = serving_leg(hp, lams, args.serving_queries, host_lambdas=host_lams)
     line = json.dumps(out)
     print(line, flush=True)
     if args.json_out:

@@ -141,6 +141,19 @@ typedef struct {
     int64_t count;
 } hpop_event_chunk;
 
+/* Renderings of a metric tree (host code, no device work): the two trees of
+ * the paper's metric tables (Sec. 4.1; host PE -> {MPI PE -> {LB, CE},
+ * Device Offload Eff.}, device PE -> {LB, CE, Orchestration Eff.}) as
+ * indented text, or as one JSON object with the ratios, the integer times and
+ * the list of 0/0 ratios. Writes at most cap bytes including the terminating
+ * NUL (cap = 0: nothing written); *needed (optional) receives the full size
+ * including the NUL. HPOP_E_ARG for a null tree, an unknown format, or a
+ * null buffer with cap > 0. */
+#define HPOP_FORMAT_TEXT 0
+#define HPOP_FORMAT_JSON 1
+hpop_status hpop_tree_format(const hpop_metric_tree* tree, int32_t format, char* buf, int64_t cap,
+                             int64_t* needed);
+
 /* Status text; never NULL. */
 const char* hpop_status_string(hpop_status status);
 /* Last error message of a session (owned by the session, valid until its next call);

@@ -140,6 +140,7 @@ _SIGS = {
                                 ctypes.POINTER(hpop_metric_tree)]),
     "hpop_server_get_stats": (_I32, [_P, ctypes.POINTER(hpop_server_stats)]),
     "hpop_server_last_error": (ctypes.c_char_p, [_P]),
+    "hpop_tree_format": (_I32, [ctypes.POINTER(hpop_metric_tree), _I32, ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
     "hpop_server_replay": (_I32, [_P, ctypes.POINTER(hpop_replay_query), _I32, _I32,
                                   ctypes.POINTER(hpop_metric_tree), ctypes.POINTER(hpop_metric_tree),
                                   ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -388,6 +389,19 @@ def hpop_server_replay(srv, queries, mem_space):
 # ---------------------------------------------------------------------------
 # conveniences over the calls above
 # ---------------------------------------------------------------------------
+
+HPOP_FORMAT_TEXT = 0
+HPOP_FORMAT_JSON = 1
+
+
+def hpop_tree_format(t, fmt=HPOP_FORMAT_TEXT):
+    """The tree as indented text or as a JSON object (a str)."""
+    need = _I64()
+    _check(lib().hpop_tree_format(ctypes.byref(t), fmt, None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(int(need.value))
+    _check(lib().hpop_tree_format(ctypes.byref(t), fmt, buf, need.value, None))
+    return buf.value.decode()
+
 
 def tree_ratios(t):
     return np.array([getattr(t, f) for f in RATIO_FIELDS], np.float64)
