@@ -265,9 +265,13 @@ hpop_status hpop_server_destroy(hpop_server* srv);
  * global region. */
 hpop_status hpop_server_open_session(hpop_server* srv, int32_t n_hosts, int32_t n_devices,
                                      int64_t t_origin, int32_t* out_sid);
-/* Non-blocking. Records in `chunks` are HPOP_MEM_HOST (copied before return)
- * or HPOP_MEM_DEVICE (read by the server's stream; keep them unchanged until
- * the ticket completes). Returns HPOP_E_BUSY when the queue is full. */
+/* Non-blocking. Records in `chunks` are HPOP_MEM_HOST (copied into the
+ * server's page-locked memory before return) or HPOP_MEM_DEVICE (read by the
+ * server's stream; keep them unchanged until the ticket completes). Records
+ * are validated on the device in both cases: a query holding an invalid one
+ * (start < 0, start > end or end >= 2^62) is not applied and its
+ * hpop_server_wait returns HPOP_E_BAD_INTERVAL. Returns HPOP_E_BUSY when the
+ * queue or the memory budget is full (nothing is copied then). */
 hpop_status hpop_server_submit(hpop_server* srv, int32_t sid, const hpop_event_chunk* chunks,
                                int32_t n_chunks, int32_t mem_space, int64_t t0, int64_t t1,
                                uint64_t* out_ticket);

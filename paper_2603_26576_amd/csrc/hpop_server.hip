@@ -345,13 +345,52 @@ using namespace hpop;
 
 namespace {
 
+// Page-locked host blocks reused across queries (best fit by size), so a
+// host payload is copied once, at submission, and DMA-ed from there.
+struct PinnedPool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_blocks;
+  std::vector<std::pair<void*, size_t>> all;
+  void* get(size_t bytes, size_t& got) {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = free_blocks.lower_bound(bytes);
+    if (it != free_blocks.end()) {
+      got = it->first;
+      void* p = it->second;
+      free_blocks.erase(it);
+      return p;
+    }
+    size_t b = 4096;
+    while (b < bytes) b <<= 1;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    all.push_back({p, b});
+    got = b;
+    return p;
+  }
+  void put(void* p, size_t bytes) {
+    if (!p) return;
+    std::lock_guard<std::mutex> g(mu);
+    free_blocks.insert({bytes, p});
+  }
+  void release() {
+    for (auto& b : all) (void)hipHostFree(b.first);
+    all.clear();
+    free_blocks.clear();
+  }
+};
+
 struct Query {
   uint64_t ticket = 0;
   int32_t sid = 0;
   int32_t mem_space = HPOP_MEM_HOST;
   int64_t t0 = 0, t1 = 0;
   std::vector<hpop_event_chunk> chunks;  // device pointers, or pointers into `host`
-  std::vector<int64_t> host;             // copied host records (start arrays then end arrays)
+  int64_t* host = nullptr;               // copied host records (pinned): start arrays then end arrays
+  size_t host_words = 0, host_block = 0;
   long long n_records = 0;
   std::chrono::steady_clock::time_point submitted, finished;
   bool done = false;
@@ -399,7 +438,8 @@ struct hpop_server {
   DevBuf d_lists, d_items, d_reqs, d_pool, d_frontier, d_ctl, d_trees, d_stage, d_moves;
   DevBuf heap;  // every session list, Comp entries; bump-allocated, compacted when full
   long long heap_cap = 0, heap_used = 0;
-  PinnedBuf h_stage, h_out;
+  PinnedBuf h_out;
+  PinnedPool pinned;  // host payloads of queued queries
   long long pool_cap = 0;
   // statistics
   std::vector<double> lat_us;
@@ -427,16 +467,14 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   Engine& En = S->engine;
   const int nq = (int)batch.size();
   hipStream_t st = S->stream;
-  // ---- stage host records (one copy), then describe every chunk to the build
+  // ---- host payloads go to the device straight from their pinned copies;
+  // then every chunk is described to the build
   size_t host_bytes = 0;
   for (int q = 0; q < nq; ++q)
-    if (batch[q]->mem_space == HPOP_MEM_HOST) host_bytes += batch[q]->host.size() * 8;
-  if (host_bytes) {
-    if (!S->h_stage.reserve(host_bytes) || !ensure(S->d_stage, A, host_bytes)) {
-      err = "staging allocation failed";
-      return HPOP_E_OOM;
-    }
-    // the previous step's copy out of the pinned buffer has completed (each step ends synchronised)
+    if (batch[q]->mem_space == HPOP_MEM_HOST) host_bytes += batch[q]->host_words * 8;
+  if (host_bytes && !ensure(S->d_stage, A, host_bytes)) {
+    err = "staging allocation failed";
+    return HPOP_E_OOM;
   }
   En.h_chunks.clear();
   En.h_regions.clear();
@@ -459,10 +497,12 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     r.list_begin = ss.list_begin;
     const int R = ss.n_hosts + ss.n_devices;
     const int64_t* dev_base = nullptr;
-    if (Q->mem_space == HPOP_MEM_HOST && !Q->host.empty()) {
-      memcpy((char*)S->h_stage.ptr + hoff, Q->host.data(), Q->host.size() * 8);
+    if (Q->mem_space == HPOP_MEM_HOST && Q->host_words) {
       dev_base = (const int64_t*)((char*)S->d_stage.ptr + hoff);
-      hoff += Q->host.size() * 8;
+      const hipError_t e = hipMemcpyAsync((char*)S->d_stage.ptr + hoff, Q->host, Q->host_words * 8,
+                                          hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return err = std::string("host payload copy: ") + hipGetErrorString(e), HPOP_E_HIP;
+      hoff += Q->host_words * 8;
     }
     std::vector<int> seg_of_res(R, -1);
     for (const hpop_event_chunk& ch : Q->chunks) {
@@ -482,8 +522,8 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
       }
       ChunkDesc d;
       if (Q->mem_space == HPOP_MEM_HOST) {
-        d.s = dev_base + (ch.start - Q->host.data());
-        d.e = dev_base + (ch.end - Q->host.data());
+        d.s = dev_base + (ch.start - Q->host);
+        d.e = dev_base + (ch.end - Q->host);
       } else {
         d.s = ch.start;
         d.e = ch.end;
@@ -617,10 +657,6 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     S->pool_cap = (long long)(S->d_pool.bytes / sizeof(Elem));
   }
   // ---- the build of the step's records (no regions: the trees come from the lists)
-  if (host_bytes) {
-    hipError_t e = hipMemcpyAsync(S->d_stage.ptr, S->h_stage.ptr, host_bytes, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return err = hipGetErrorString(e), HPOP_E_HIP;
-  }
   if (!En.ws.pinned.reserve(64)) {
     err = "pinned host allocation failed";
     return HPOP_E_OOM;
@@ -735,6 +771,11 @@ void worker_loop(hpop_server* S) {
       std::lock_guard<std::mutex> sg(S->state_mu);
       st = run_step(S, batch, err);
     }
+    // every step ends synchronised: the host payloads have been copied
+    for (Query* Q : batch) {
+      S->pinned.put(Q->host, Q->host_block);
+      Q->host = nullptr;
+    }
     const auto now = std::chrono::steady_clock::now();
     lk.lock();
     ++S->steps;
@@ -829,7 +870,7 @@ hpop_status hpop_server_destroy(hpop_server* S) {
   for (DevBuf* b : {&S->d_lists, &S->d_items, &S->d_reqs, &S->d_pool, &S->d_frontier, &S->d_ctl, &S->d_trees,
                     &S->d_stage, &S->d_moves})
     b->release(S->alloc);
-  S->h_stage.release();
+  S->pinned.release();
   S->h_out.release();
   (void)hipStreamSynchronize(S->stream);
   (void)hipStreamDestroy(S->stream);
@@ -920,21 +961,38 @@ hpop_status hpop_server_submit(hpop_server* S, int32_t sid, const hpop_event_chu
       }
       total += c.count;
     }
+    auto busy = [&] {
+      return (int)S->queue.size() >= S->cfg.queue_capacity ||
+             (S->inflight_bytes + total * 16 > S->cfg.mem_budget_bytes && S->inflight_bytes > 0);
+    };
     if (mem_space == HPOP_MEM_HOST) {
-      Q->host.resize((size_t)2 * total);
+      {
+        std::lock_guard<std::mutex> g(S->mu);  // no copy for a query that would be refused anyway
+        if (busy()) {
+          S->last_error = "queue full";
+          delete Q;
+          return HPOP_E_BUSY;
+        }
+      }
+      // one copy into pinned memory; the records are validated on the device
+      // like device payloads (an invalid one fails the query at hpop_server_wait)
+      if (total > 0) {
+        Q->host = (int64_t*)S->pinned.get((size_t)total * 16, Q->host_block);
+        if (!Q->host) {
+          delete Q;
+          return srv_fail(S, HPOP_E_OOM, "pinned host allocation failed");
+        }
+      }
+      Q->host_words = (size_t)2 * total;
       long long o = 0;
       for (int32_t i = 0; i < n_chunks; ++i) {
         const hpop_event_chunk& c = chunks[i];
-        for (int64_t j = 0; j < c.count; ++j)
-          if (c.start[j] < 0 || c.start[j] > c.end[j] || c.end[j] >= kTimeLimit) {
-            delete Q;
-            return srv_fail(S, HPOP_E_BAD_INTERVAL, "chunk " + std::to_string(i) + " record " + std::to_string(j));
-          }
-        memcpy(Q->host.data() + o, c.start, c.count * 8);
-        memcpy(Q->host.data() + o + c.count, c.end, c.count * 8);
+        if (c.count == 0) continue;
+        memcpy(Q->host + o, c.start, c.count * 8);
+        memcpy(Q->host + o + c.count, c.end, c.count * 8);
         hpop_event_chunk cc = c;
-        cc.start = Q->host.data() + o;
-        cc.end = Q->host.data() + o + c.count;
+        cc.start = Q->host + o;
+        cc.end = Q->host + o + c.count;
         Q->chunks.push_back(cc);
         o += 2 * c.count;
       }
@@ -945,9 +1003,9 @@ hpop_status hpop_server_submit(hpop_server* S, int32_t sid, const hpop_event_chu
     Q->submitted = std::chrono::steady_clock::now();
     {
       std::lock_guard<std::mutex> g(S->mu);
-      if ((int)S->queue.size() >= S->cfg.queue_capacity ||
-          (S->inflight_bytes + total * 16 > S->cfg.mem_budget_bytes && S->inflight_bytes > 0)) {
+      if (busy()) {
         S->last_error = "queue full";
+        S->pinned.put(Q->host, Q->host_block);
         delete Q;
         return HPOP_E_BUSY;
       }

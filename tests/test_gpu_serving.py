@@ -133,7 +133,8 @@ def test_large_batches_take_the_global_sort_path():
         hp.hpop_server_destroy(srv)
 
 
-def test_bad_device_record_rejected_and_state_unchanged():
+@pytest.mark.parametrize("device", [True, False])
+def test_bad_record_rejected_and_state_unchanged(device):
     import torch
     ranks = 2
     plan = make_queries(31, 1, ranks, 2)
@@ -144,11 +145,13 @@ def test_bad_device_record_rejected_and_state_unchanged():
         chunks, t0, t1 = qs[0]
         t = hp.hpop_server_submit(srv, sid, as_payload(chunks, False), hp.HPOP_MEM_HOST, t0, t1)
         hp.hpop_server_wait(srv, t)
-        bad_s = torch.tensor([origin + 5, origin + 9], dtype=torch.int64, device="cuda")
-        bad_e = torch.tensor([origin + 6, origin + 1], dtype=torch.int64, device="cuda")
-        torch.cuda.synchronize()
-        t = hp.hpop_server_submit(srv, sid, [(ranks, hp.HPOP_DEV_KERNEL, bad_s, bad_e)], hp.HPOP_MEM_DEVICE,
-                                  t0, t1)
+        bad_s = np.array([origin + 5, origin + 9], np.int64)
+        bad_e = np.array([origin + 6, origin + 1], np.int64)
+        if device:
+            bad_s, bad_e = torch.from_numpy(bad_s).cuda(), torch.from_numpy(bad_e).cuda()
+            torch.cuda.synchronize()
+        t = hp.hpop_server_submit(srv, sid, [(ranks, hp.HPOP_DEV_KERNEL, bad_s, bad_e)],
+                                  hp.HPOP_MEM_DEVICE if device else hp.HPOP_MEM_HOST, t0, t1)
         with pytest.raises(hp.HpopError) as ei:
             hp.hpop_server_wait(srv, t)
         assert ei.value.status == hp.HPOP_E_BAD_INTERVAL
