@@ -104,3 +104,69 @@ def compute(trace, threads=1, regions=None, lib=None):
     res, kind, s, e = trace.flat()
     return compute_arrays(trace.n_hosts, trace.n_devices, res, kind, s, e,
                           trace.regions if regions is None else regions, threads, lib)
+
+
+HOST_LEVELS = [(0,), (0, 1), (0, 1, 2)]   # {U}, {U, W}, {U, W, MPI} by kind
+DEVICE_LEVELS = [(3,), (3, 4)]            # {K}, {K, M}
+
+
+def _ratio(num, den, bit, mask):
+    """One IEEE division of two exact integers; 0/0 := 1, flagged (as the C oracle)."""
+    if den == 0:
+        mask[0] |= 1 << bit
+        return 1.0
+    return float(num) / float(den)
+
+
+def compute_multi(trace, regions):
+    """Regions entered repeatedly, each resource on its own clock: regions[g] is
+    a list of (resource, a, b) with disjoint [a, b) per resource.
+
+    Plain definition: for resource r and nested level l, D_l(r) is the sum over
+    r's intervals of the union measure of the level's records inside it (the
+    C union_measure); E_r is r's own time in the region. Host: U = D_0,
+    W = D_1 - D_0, MPI = D_2 - D_1, Other = E_r - D_2; device: K = D_0,
+    M = D_1 - D_0, Idle = E_r - D_1. E follows eq. 1 literally: the largest
+    E_r over host processes (over devices when no host process is in the
+    region). Aggregates and ratios as eqs. 4-12, each ratio one IEEE division.
+    """
+    n, m = trace.n_hosts, trace.n_devices
+    R = n + m
+    res, kind, s, e = trace.flat()
+    nreg = len(regions)
+    times = np.zeros((nreg, R, 4), np.int64)
+    sums = np.zeros((nreg, 10), np.int64)
+    ratios = np.zeros((nreg, 9), np.float64)
+    masks = np.zeros(nreg, np.uint32)
+    Es = np.zeros(nreg, np.int64)
+    for g, ivls in enumerate(regions):
+        per = [[] for _ in range(R)]
+        for r, a, b in ivls:
+            per[r].append((int(a), int(b)))
+        Er = np.array([sum(b - a for a, b in per[r]) for r in range(R)], np.int64)
+        E = int(Er[:n].max()) if n and Er[:n].max() > 0 else (int(Er[n:].max()) if m else 0)
+        Es[g] = E
+        for r in range(R):
+            levels = HOST_LEVELS if r < n else DEVICE_LEVELS
+            D = []
+            for kinds in levels:
+                sel = (res == r) & np.isin(kind, kinds)
+                D.append(int(union_measure(s[sel], e[sel], per[r]).sum()) if per[r] else 0)
+            if r < n:
+                times[g, r] = [D[0], D[1] - D[0], D[2] - D[1], Er[r] - D[2]]
+            else:
+                times[g, r] = [D[0], D[1] - D[0], Er[r] - D[1], 0]
+        h, d = times[g, :n], times[g, n:]
+        sU, sW, sMPI, sO = (int(h[:, i].sum()) for i in range(4))
+        sUW = sU + sW
+        mUW = int((h[:, 0] + h[:, 1]).max()) if n else 0
+        sK, sM = int(d[:, 0].sum()), int(d[:, 1].sum())
+        mK = int(d[:, 0].max()) if m else 0
+        mKM = int((d[:, 0] + d[:, 1]).max()) if m else 0
+        sums[g] = [sU, sW, sMPI, sO, sUW, mUW, sK, sM, mK, mKM]
+        mk = [0]
+        ratios[g] = [_ratio(sU, n * E, 0, mk), _ratio(sUW, n * E, 1, mk), _ratio(sUW, n * mUW, 2, mk),
+                     _ratio(mUW, E, 3, mk), _ratio(sU, sUW, 4, mk), _ratio(sK, m * E, 5, mk),
+                     _ratio(sK, m * mK, 6, mk), _ratio(mK, mKM, 7, mk), _ratio(mKM, E, 8, mk)]
+        masks[g] = mk[0]
+    return {"times": times, "sums": sums, "ratios": ratios, "mask": masks, "E": Es}

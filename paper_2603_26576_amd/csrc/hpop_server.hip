@@ -545,7 +545,7 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   if (rc != HPOP_OK) return rc;
   // ---- list capacity: a list grows by at most its level's new records. A list
   // that outgrows its place moves to the end of the heap (at least doubling);
-  // when the heap is full, every list moves into a new heap twice the live
+  // when the heap is full, every list moves into a new heap four times the live
   // size. All moves of a step are one kernel; the host tables change only
   // once it is enqueued.
   const size_t nl = S->lists.size();
@@ -577,7 +577,7 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     } else {
       long long live = 0;
       for (size_t i = 0; i < nl; ++i) live += n_cap[i];
-      new_heap_cap = std::max(2 * live, 1ll << 16);
+      new_heap_cap = std::max(4 * live, 1ll << 16);  // 4x: few compactions while sessions grow
       if (!new_heap.reserve(A, (size_t)new_heap_cap * sizeof(Comp), false)) {
         err = "device allocation for the session lists failed";
         return HPOP_E_OOM;
