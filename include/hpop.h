@@ -191,6 +191,18 @@ hpop_status hpop_clear_events(hpop_session* s);
  * user). Returns its id (0, 1, ...). */
 hpop_status hpop_region_define(hpop_session* s, int64_t t0, int64_t t1, int32_t* out_region);
 hpop_status hpop_num_regions(const hpop_session* s, int32_t* out);
+/* A region entered repeatedly, each resource on its own clock (regions that
+ * processes enter and leave through TALP's user-level API, Sec. 3.2):
+ * `count` intervals [t0[i], t1[i]) of resource[i] (0 .. n+m-1; intervals of one
+ * resource must not overlap; resources without intervals are outside the
+ * region). A resource's state times are measured over its own intervals and
+ * its remainder (Other / Idle) completes its own time in the region. E is
+ * eq. 1 read literally: the largest in-region time of a host process (of a
+ * device when no host process has an interval). Errors: HPOP_E_ARG (null
+ * pointer, count < 1), HPOP_E_RESOURCE, HPOP_E_REGION (t0 >= t1, overlap,
+ * bounds outside [-2^62, 2^62]), HPOP_E_OVERFLOW (E * max(n, m) >= 2^53). */
+hpop_status hpop_region_define_multi(hpop_session* s, const int32_t* resource, const int64_t* t0,
+                                     const int64_t* t1, int64_t count, int32_t* out_region);
 
 /* Metric trees of one region / of every region (out: hpop_num_regions entries).
  * Builds the merged interval lists first if records were added since the

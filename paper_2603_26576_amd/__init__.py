@@ -119,6 +119,7 @@ _SIGS = {
     "hpop_clear_events": (_I32, [_P]),
     "hpop_session_synchronize": (_I32, [_P]),
     "hpop_region_define": (_I32, [_P, _I64, _I64, ctypes.POINTER(_I32)]),
+    "hpop_region_define_multi": (_I32, [_P, _P, _P, _P, _I64, ctypes.POINTER(_I32)]),
     "hpop_num_regions": (_I32, [_P, ctypes.POINTER(_I32)]),
     "hpop_metrics_compute": (_I32, [_P, _I32, ctypes.POINTER(hpop_metric_tree)]),
     "hpop_metrics_compute_all": (_I32, [_P, _U32, ctypes.POINTER(hpop_metric_tree)]),
@@ -234,6 +235,17 @@ def hpop_clear_events(s):
 def hpop_region_define(s, t0, t1):
     out = _I32()
     _check(lib().hpop_region_define(s, int(t0), int(t1), ctypes.byref(out)), s)
+    return out.value
+
+
+def hpop_region_define_multi(s, intervals):
+    """A region entered repeatedly: intervals = [(resource, t0, t1), ...]."""
+    r = np.ascontiguousarray([int(x[0]) for x in intervals], np.int32)
+    a = np.ascontiguousarray([int(x[1]) for x in intervals], np.int64)
+    b = np.ascontiguousarray([int(x[2]) for x in intervals], np.int64)
+    out = _I32()
+    _check(lib().hpop_region_define_multi(s, r.ctypes.data, a.ctypes.data, b.ctypes.data, len(intervals),
+                                          ctypes.byref(out)), s)
     return out.value
 
 

@@ -66,8 +66,16 @@ struct RegionDesc {
   int32_t seg_begin;   // first segment of the region's session (hosts first, then devices)
   int32_t n_hosts;
   int32_t n_devices;
-  int32_t pad;
+  int32_t n_ivl;       // > 0: a region given as per-resource intervals (IvlDesc), not [t0, t1)
   int64_t times_off;   // offset (in resources) of the region's rows in the times array
+  int64_t ivl_begin;   // first IvlDesc of the region
+};
+
+// One interval of a region given per resource.
+struct IvlDesc {
+  int32_t region;
+  int32_t resource;  // within the region's session
+  int64_t a, b;
 };
 
 struct Tree {  // identical layout to hpop_metric_tree

@@ -21,6 +21,6 @@ hipError_t launch_merge_wave(const Plan& p, hipStream_t st);
 hipError_t launch_merge_block(const Plan& p, int cap, hipStream_t st);
 hipError_t launch_base(const Plan& p, hipStream_t st);
 hipError_t launch_region(const Plan& p, const RegionDesc* regions, int n_regions, int max_res, Tree* trees,
-                         long long* times, hipStream_t st);
+                         long long* times, const IvlDesc* ivls, long long n_ivls, long long* macc, hipStream_t st);
 
 }  // namespace hpop

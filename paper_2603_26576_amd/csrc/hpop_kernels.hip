@@ -948,7 +948,7 @@ __global__ __launch_bounds__(THREADS) void k_region_part(Plan p, const RegionDes
   const RegionDesc rd = regions[blockIdx.x];
   const int R = rd.n_hosts + rd.n_devices;
   const int r0 = blockIdx.y * kRegionSlice;
-  if (r0 >= R) return;  // uniform: this slice lies past the region's resources
+  if (r0 >= R || rd.n_ivl) return;  // uniform: past the region's resources, or a per-resource region
   const int rl = threadIdx.x >> 3, l = (threadIdx.x >> 1) & 3, ep = threadIdx.x & 1;
   const int r = r0 + rl;
   const bool host = r < rd.n_hosts;
@@ -992,6 +992,7 @@ __global__ __launch_bounds__(64) void k_region_final(Plan p, const RegionDesc* r
   const int g = blockIdx.x * 64 + threadIdx.x;
   if (g >= n_regions) return;
   const RegionDesc rd = regions[g];
+  if (rd.n_ivl) return;  // a per-resource region: k_region_multi
   unsigned long long* acc = p.racc + (long long)g * 9;
   long long v[9];
 #pragma unroll
@@ -1000,6 +1001,85 @@ __global__ __launch_bounds__(64) void k_region_final(Plan p, const RegionDesc* r
     acc[i] = 0;
   }
   trees[g] = make_tree(rd.t1 - rd.t0, rd.n_hosts, rd.n_devices, v);
+}
+
+// Regions given as per-resource interval lists (a region entered repeatedly,
+// each resource on its own clock). Part 1 clears the accumulators of their
+// resources; part 2 adds, per (interval, level, end of the interval), the
+// level's measure before that end (the start with a minus sign) and each
+// interval's length; part 3 turns them into state times (the remainder
+// completes the resource's own time in the region) and the tree, with E the
+// largest host in-region time (eq. 1), or the largest device one when no host
+// process is in the region.
+__global__ __launch_bounds__(256) void k_ivl_zero(const RegionDesc* regions, long long* macc) {
+  const RegionDesc rd = regions[blockIdx.x];
+  if (rd.n_ivl == 0) return;
+  const int R = rd.n_hosts + rd.n_devices;
+  for (int i = threadIdx.x; i < 4 * R; i += 256) macc[rd.times_off * 4 + i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_ivl_acc(Plan p, const RegionDesc* regions, const IvlDesc* ivls,
+                                                 long long n_ivls, long long* macc) {
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long i = t >> 3;
+  if (i >= n_ivls) return;
+  const int l = (int)((t >> 1) & 3), ep = (int)(t & 1);
+  const IvlDesc iv = ivls[i];
+  const RegionDesc rd = regions[iv.region];
+  unsigned long long* acc = (unsigned long long*)(macc + (rd.times_off + iv.resource) * 4);
+  if (l == 3) {
+    if (ep) atomicAdd(acc + 3, (unsigned long long)(iv.b - iv.a));
+    return;
+  }
+  if (l >= (iv.resource < rd.n_hosts ? 3 : 2)) return;
+  const long long v = measure_before(p, rd.seg_begin + iv.resource, l, ep ? iv.b : iv.a);
+  atomicAdd(acc + l, (unsigned long long)(ep ? v : -v));  // two's complement: the sum is exact
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_region_multi(const RegionDesc* regions, const long long* macc, Tree* trees,
+                                                          long long* times) {
+  __shared__ long long lds[THREADS / 64 * 10];
+  __shared__ long long semax[2][THREADS / 64];
+  const RegionDesc rd = regions[blockIdx.x];
+  if (rd.n_ivl == 0) return;
+  const int R = rd.n_hosts + rd.n_devices;
+  // sums: U, W, MPI, Other, K, M ; maxes: U+W, K, K+M
+  long long v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  long long eh = 0, ed = 0;
+  for (int r = threadIdx.x; r < R; r += THREADS) {
+    const long long* a = macc + (rd.times_off + r) * 4;
+    const long long D0 = a[0], D1 = a[1], D2 = a[2], Er = a[3];
+    long long* out = times + (rd.times_off + r) * 4;
+    if (r < rd.n_hosts) {
+      const long long u = D0, w = D1 - D0, mpi = D2 - D1, o = Er - D2;
+      out[0] = u; out[1] = w; out[2] = mpi; out[3] = o;
+      v[0] += u; v[1] += w; v[2] += mpi; v[3] += o;
+      v[6] = u + w > v[6] ? u + w : v[6];
+      eh = Er > eh ? Er : eh;
+    } else {
+      const long long k = D0, mm = D1 - D0, idle = Er - D1;
+      out[0] = k; out[1] = mm; out[2] = idle; out[3] = 0;
+      v[4] += k; v[5] += mm;
+      v[7] = k > v[7] ? k : v[7];
+      v[8] = k + mm > v[8] ? k + mm : v[8];
+      ed = Er > ed ? Er : ed;
+    }
+  }
+  eh = wave_reduce_i64<OpMax>(eh, 0);
+  ed = wave_reduce_i64<OpMax>(ed, 0);
+  if ((threadIdx.x & 63) == 0) {
+    semax[0][threadIdx.x >> 6] = eh;
+    semax[1][threadIdx.x >> 6] = ed;
+  }
+  block_tree<THREADS>(v, lds);  // its barriers also publish semax
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < THREADS / 64; ++w) {
+      eh = semax[0][w] > eh ? semax[0][w] : eh;
+      ed = semax[1][w] > ed ? semax[1][w] : ed;
+    }
+    trees[blockIdx.x] = make_tree(eh ? eh : ed, rd.n_hosts, rd.n_devices, v);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -1076,13 +1156,20 @@ hipError_t launch_base(const Plan& p, hipStream_t st) {
 }
 
 hipError_t launch_region(const Plan& p, const RegionDesc* regions, int n_regions, int max_res, Tree* trees,
-                         long long* times, hipStream_t st) {
+                         long long* times, const IvlDesc* ivls, long long n_ivls, long long* macc, hipStream_t st) {
   if (n_regions == 0) return hipSuccess;
   const unsigned slices = (unsigned)std::max(1, (max_res + kRegionSlice - 1) / kRegionSlice);
   hipLaunchKernelGGL(k_region_part<8 * kRegionSlice>, dim3((unsigned)n_regions, slices), dim3(8 * kRegionSlice), 0, st,
                      p, regions, times);
   hipLaunchKernelGGL(k_region_final, dim3((unsigned)((n_regions + 63) / 64)), dim3(64), 0, st, p, regions, n_regions,
                      trees);
+  if (n_ivls > 0) {
+    hipLaunchKernelGGL(k_ivl_zero, dim3((unsigned)n_regions), dim3(256), 0, st, regions, macc);
+    hipLaunchKernelGGL(k_ivl_acc, dim3((unsigned)((8 * n_ivls + 255) / 256)), dim3(256), 0, st, p, regions, ivls,
+                       n_ivls, macc);
+    hipLaunchKernelGGL(k_region_multi<256>, dim3((unsigned)n_regions), dim3(256), 0, st, regions,
+                       (const long long*)macc, trees, times);
+  }
   return hipGetLastError();
 }
 

@@ -63,12 +63,14 @@ struct Workspace {
   RegionDesc* d_regions = nullptr;
   Tree* d_trees = nullptr;
   long long* d_times = nullptr;
+  IvlDesc* d_ivls = nullptr;     // intervals of regions given per resource
+  long long* d_macc = nullptr;   // [n_times][4] their per-resource accumulators
   hipGraphExec_t graph_exec = nullptr;
   long long layout_gen = 0;
   hpop_status prepare(Alloc& a, long long n_chunks, long long n_tiles, long long n_segs, long long n_buckets,
                       long long n_elems,
                       long long n_slots, long long n_regions, long long n_times, long long n_owners,
-                      std::string& err);
+                      long long n_ivls, std::string& err);
   void release(Alloc& a);
 };
 
@@ -79,6 +81,7 @@ struct Engine {
   std::vector<ChunkDesc> h_chunks;
   std::vector<SegDesc> h_segs;
   std::vector<RegionDesc> h_regions;
+  std::vector<IvlDesc> h_ivls;
   std::vector<std::pair<int, int>> chunk_owner;  // (session index, chunk index) per chunk desc
   std::vector<int> seg_of_session, reg_of_session;
   long long n_times = 0;
@@ -125,7 +128,8 @@ struct hpop_session {
   size_t arena_used = 0;
   int64_t n_events = 0;
   int64_t n_calls = 0;
-  std::vector<std::pair<int64_t, int64_t>> regions;
+  std::vector<std::pair<int64_t, int64_t>> regions;  // [t0, t1), or the span of a per-resource region
+  std::vector<std::vector<hpop::IvlDesc>> region_ivls;  // per region: its intervals (empty: [t0, t1))
   unsigned long long version = 0;
   hpop::PinnedBuf staging;
   hpop_tuning tuning{};

@@ -170,8 +170,8 @@ static T* carve(char*& cur, size_t n) {
 static size_t carve_bytes(size_t n, size_t sz) { return (n * sz + 255) & ~size_t(255); }
 
 hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, long long n_segs,
-                               long long n_buckets, long long n_elems, long long n_slots, long long n_regions, long long n_times,
-                               long long n_owners, std::string& err) {
+                               long long n_buckets, long long n_elems, long long n_slots, long long n_regions,
+                               long long n_times, long long n_owners, long long n_ivls, std::string& err) {
   const size_t nscan = (size_t)((n_buckets + kScanTile - 1) / kScanTile + 1);
   size_t small = 0;
   small += carve_bytes(n_chunks, sizeof(ChunkDesc));
@@ -190,6 +190,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   small += carve_bytes(n_owners, sizeof(unsigned int));
   small += carve_bytes(n_regions, sizeof(RegionDesc)) + carve_bytes(n_regions, sizeof(Tree));
   small += carve_bytes(9 * n_regions, sizeof(unsigned long long));
+  small += carve_bytes(n_ivls, sizeof(IvlDesc)) + carve_bytes(n_ivls ? 4 * n_times : 0, sizeof(long long));
   small += carve_bytes(4 * n_times, sizeof(long long));
   if (!meta.reserve(a, small, false)) {
     err = "device allocation of " + std::to_string(small) + " bytes (build metadata) failed";
@@ -235,6 +236,8 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   p.racc = carve<unsigned long long>(cur, 9 * n_regions);
   p.n_racc = n_regions;
   d_times = carve<long long>(cur, 4 * n_times);
+  d_ivls = carve<IvlDesc>(cur, n_ivls);
+  d_macc = carve<long long>(cur, n_ivls ? 4 * n_times : 0);
   p.elems = (Elem*)elems.ptr;
   p.elems2 = (Elem*)elems2.ptr;
   for (int l = 0; l < 3; ++l) {
@@ -296,6 +299,7 @@ static void tuned(const hpop_tuning& t, int& target, int& cap, int& tile, int& s
 hpop_status Engine::assemble(hpop_session* const* ss, int k, std::string& err) {
   h_chunks.clear();
   h_regions.clear();
+  h_ivls.clear();
   chunk_owner.clear();
   seg_of_session.assign(k, 0);
   reg_of_session.assign(k, 0);
@@ -335,8 +339,13 @@ hpop_status Engine::assemble(hpop_session* const* ss, int k, std::string& err) {
       rd.seg_begin = seg_base;
       rd.n_hosts = s->n_hosts;
       rd.n_devices = s->n_devices;
-      rd.pad = 0;
       rd.times_off = times;
+      rd.n_ivl = (int32_t)s->region_ivls[g].size();
+      rd.ivl_begin = (int64_t)h_ivls.size();
+      for (IvlDesc iv : s->region_ivls[g]) {
+        iv.region = (int32_t)h_regions.size();
+        h_ivls.push_back(iv);
+      }
       times += R;
       h_regions.push_back(rd);
     }
@@ -375,7 +384,7 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
   }
   hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), tiles, n_segs, buckets, elems,
                               slots > 0 ? buckets * (long long)slots : 0, (long long)h_regions.size(), times,
-                              std::max(1, n_owners), err);
+                              std::max(1, n_owners), (long long)h_ivls.size(), err);
   if (st != HPOP_OK) return st;
   ws.plan.n_tiles = tiles;
   ws.plan.tile_elems = tile;
@@ -389,8 +398,8 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
 hpop_status Engine::upload(std::string& err) {
   // descriptors go through pinned memory so the copies are stream-ordered
   const size_t bc = h_chunks.size() * sizeof(ChunkDesc), bs = h_segs.size() * sizeof(SegDesc),
-               br = h_regions.size() * sizeof(RegionDesc);
-  if (!ws.pinned_desc.reserve(bc + bs + br + 64)) {
+               br = h_regions.size() * sizeof(RegionDesc), bi = h_ivls.size() * sizeof(IvlDesc);
+  if (!ws.pinned_desc.reserve(bc + bs + br + bi + 64)) {
     err = "pinned host allocation failed";
     return HPOP_E_OOM;
   }
@@ -400,10 +409,14 @@ hpop_status Engine::upload(std::string& err) {
   if (bc) memcpy(h, h_chunks.data(), bc);
   if (bs) memcpy(h + bc, h_segs.data(), bs);
   if (br) memcpy(h + bc + bs, h_regions.data(), br);
+  if (bi) memcpy(h + bc + bs + br, h_ivls.data(), bi);
   if (bc) HPOP_HIP(hipMemcpyAsync(ws.d_chunks, h, bc, hipMemcpyHostToDevice, alloc.stream), "upload chunks");
   if (bs) HPOP_HIP(hipMemcpyAsync(ws.d_segs, h + bc, bs, hipMemcpyHostToDevice, alloc.stream), "upload segments");
   if (br)
     HPOP_HIP(hipMemcpyAsync(ws.d_regions, h + bc + bs, br, hipMemcpyHostToDevice, alloc.stream), "upload regions");
+  if (bi)
+    HPOP_HIP(hipMemcpyAsync(ws.d_ivls, h + bc + bs + br, bi, hipMemcpyHostToDevice, alloc.stream),
+             "upload region intervals");
   return HPOP_OK;
 }
 
@@ -453,7 +466,9 @@ hpop_status Engine::enqueue(bool build, bool with_timing, std::string& err) {
   }
   int max_res = 0;
   for (const RegionDesc& rd : h_regions) max_res = std::max(max_res, rd.n_hosts + rd.n_devices);
-  HPOP_HIP(launch_region(p, ws.d_regions, nreg, max_res, ws.d_trees, ws.d_times, st), "k_region");
+  HPOP_HIP(launch_region(p, ws.d_regions, nreg, max_res, ws.d_trees, ws.d_times, ws.d_ivls, (long long)h_ivls.size(),
+                         ws.d_macc, st),
+           "k_region");
   HPOP_HIP(mark("region"), "hipEventRecord");
   n_marks = ev;
   // results: trees, first bad record, oversized buckets, slot overflow
@@ -847,6 +862,53 @@ hpop_status hpop_region_define(hpop_session* s, int64_t t0, int64_t t1, int32_t*
   if (E >= (1ull << 53) || E * w >= (1ull << 53))
     return fail(s, HPOP_E_OVERFLOW, "(t1 - t0) * max(n, m) must be below 2^53 for exact FP64 ratios");
   s->regions.push_back(std::make_pair(t0, t1));
+  s->region_ivls.emplace_back();
+  *out_region = (int32_t)s->regions.size() - 1;
+  return HPOP_OK;
+  HPOP_GUARD_END(s)
+}
+
+hpop_status hpop_region_define_multi(hpop_session* s, const int32_t* resource, const int64_t* t0,
+                                     const int64_t* t1, int64_t count, int32_t* out_region) {
+  HPOP_GUARD_BEGIN
+  if (!s || !resource || !t0 || !t1 || !out_region || count < 1) return fail(s, HPOP_E_ARG, "bad arguments");
+  const int R = s->n_hosts + s->n_devices;
+  std::vector<IvlDesc> iv((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    if (resource[i] < 0 || resource[i] >= R) return fail(s, HPOP_E_RESOURCE, "interval " + std::to_string(i));
+    if (!(t0[i] < t1[i]) || t0[i] < -kTimeLimit || t1[i] > kTimeLimit)
+      return fail(s, HPOP_E_REGION, "interval " + std::to_string(i) + " needs t0 < t1 within [-2^62, 2^62]");
+    iv[i].region = 0;
+    iv[i].resource = resource[i];
+    iv[i].a = t0[i];
+    iv[i].b = t1[i];
+  }
+  std::sort(iv.begin(), iv.end(), [](const IvlDesc& x, const IvlDesc& y) {
+    return x.resource != y.resource ? x.resource < y.resource : x.a < y.a;
+  });
+  // no overlap within a resource; E as eq. 1: the largest host total (device total without hosts)
+  std::vector<unsigned long long> tot((size_t)R, 0);
+  for (size_t i = 0; i < iv.size(); ++i) {
+    if (i > 0 && iv[i].resource == iv[i - 1].resource && iv[i].a < iv[i - 1].b)
+      return fail(s, HPOP_E_REGION, "overlapping intervals on resource " + std::to_string(iv[i].resource));
+    tot[iv[i].resource] += (unsigned long long)(iv[i].b - iv[i].a);
+  }
+  unsigned long long eh = 0, ed = 0;
+  for (int r = 0; r < R; ++r) (r < s->n_hosts ? eh : ed) = std::max(r < s->n_hosts ? eh : ed, tot[r]);
+  const unsigned long long E = eh ? eh : ed;
+  unsigned long long maxdur = 0;
+  for (unsigned long long t : tot) maxdur = std::max(maxdur, t);
+  const unsigned long long w = (unsigned long long)std::max(1, std::max(s->n_hosts, s->n_devices));
+  (void)E;
+  if (maxdur >= (1ull << 53) / w)
+    return fail(s, HPOP_E_OVERFLOW, "E * max(n, m) must be below 2^53 for exact FP64 ratios");
+  int64_t lo = iv[0].a, hi = iv[0].b;
+  for (const IvlDesc& x : iv) {
+    lo = std::min(lo, x.a);
+    hi = std::max(hi, x.b);
+  }
+  s->regions.push_back(std::make_pair(lo, hi));
+  s->region_ivls.push_back(std::move(iv));
   *out_region = (int32_t)s->regions.size() - 1;
   return HPOP_OK;
   HPOP_GUARD_END(s)

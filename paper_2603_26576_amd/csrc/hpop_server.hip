@@ -478,6 +478,7 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   }
   En.h_chunks.clear();
   En.h_regions.clear();
+  En.h_ivls.clear();
   std::vector<long long> seg_count;
   std::vector<char> seg_host;
   std::vector<ServItem> items;

@@ -310,3 +310,65 @@ def test_batched_equals_single():
     finally:
         for s in sessions:
             hp.hpop_session_destroy(s)
+
+
+def multi_session(trace, multi):
+    s, keep = new_session(trace)
+    for ivls in multi:
+        hp.hpop_region_define_multi(s, ivls)
+    return s, keep
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_regions_entered_repeatedly(seed):
+    """Per-resource interval lists against the oracle's definition, next to
+    ordinary regions of the same session (those stay as before)."""
+    rng = np.random.default_rng(6000 + seed)
+    tr = tg.make_trace(seed, int(rng.integers(1, 5)), int(rng.integers(1, 5)), 3, int(rng.integers(50, 3000)),
+                       int(rng.integers(20, 800)), regions="tiles", n_regions=3)
+    R = tr.n_hosts + tr.n_devices
+    lo, hi = tr.info["t0"], tr.info["t_end"]
+    multi = []
+    for _ in range(3):
+        ivls = []
+        for r in range(R):
+            k = int(rng.integers(0, 5))
+            cuts = np.sort(rng.choice(np.arange(lo - 1000, hi + 1000, max(1, (hi - lo) // 5000)), size=2 * k,
+                                      replace=False)) if k else []
+            ivls += [(r, int(cuts[2 * i]), int(cuts[2 * i + 1])) for i in range(k) if cuts[2 * i] < cuts[2 * i + 1]]
+        if not ivls:
+            ivls = [(0, lo, hi)]
+        multi.append(ivls)
+    want = oracle.compute_multi(tr, multi)
+    want_plain = oracle.compute(tr)
+    s, keep = multi_session(tr, multi)
+    try:
+        for flags in (0, hp.HPOP_FORCE_REBUILD):
+            trees = hp.hpop_metrics_compute_all(s, flags)
+            G = len(tr.regions)
+            for g in range(G):
+                np.testing.assert_array_equal(hp.tree_sums(trees[g]), want_plain["sums"][g])
+            for j in range(len(multi)):
+                t = trees[G + j]
+                assert t.E == want["E"][j]
+                np.testing.assert_array_equal(hp.tree_sums(t), want["sums"][j], err_msg="multi %d" % j)
+                np.testing.assert_array_equal(hp.tree_ratios(t).view(np.int64), want["ratios"][j].view(np.int64))
+                assert t.undefined_mask == want["mask"][j]
+                for r in range(R):
+                    np.testing.assert_array_equal(hp.hpop_resource_times(s, G + j, r), want["times"][j][r])
+    finally:
+        hp.hpop_session_destroy(s)
+
+
+def test_region_define_multi_errors():
+    s = hp.hpop_session_create(2, 1)
+    try:
+        for bad, code in [([(3, 0, 10)], hp.HPOP_E_RESOURCE), ([(0, 5, 5)], hp.HPOP_E_REGION),
+                          ([(0, 0, 10), (0, 5, 20)], hp.HPOP_E_REGION), ([(0, 0, 1 << 52)], hp.HPOP_E_OVERFLOW)]:
+            with pytest.raises(hp.HpopError) as ei:
+                hp.hpop_region_define_multi(s, bad)
+            assert ei.value.status == code
+        assert hp.hpop_num_regions(s) == 0
+        assert hp.hpop_region_define_multi(s, [(0, 0, 10), (0, 10, 20), (2, 3, 4)]) == 0
+    finally:
+        hp.hpop_session_destroy(s)
