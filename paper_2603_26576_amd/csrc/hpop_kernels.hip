@@ -645,7 +645,10 @@ __device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (
 // (running max of ends, measures and break counts, component writes). A
 // record outside level l takes part as the empty pair (0, 0), which changes
 // no maximum, measure or break, so the phases need no branches; only the
-// component stores are conditional.
+// component stores are conditional. A position past the bucket holds the key
+// 3 (rank 3, start lo) with end 0: outside every lower level, and in the top
+// level the pair (1, 0), which also changes nothing there, because position 0
+// holds a record whose end is at least 1 and comes first in the sweep.
 template <int IPL, int NLEV>
 __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
                                              long long lo, const long long (&carry)[3],
@@ -656,19 +659,18 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
   unsigned int kv[IPL], ev[IPL];
   lds_load<IPL>(W.key + q0, kv);
   lds_load<IPL>(W.end + q0, ev);
-  unsigned int sv[IPL];
 #pragma unroll
   for (int j = 0; j < IPL; ++j) {
-    sv[j] = (kv[j] >> 2) + 1;  // start - lo + 1, the same shift as the ends
     if (j >= cnt) {
-      // positions past the bucket belong to no level: rank 3, empty pair
-      kv[j] = 0xFFFFFFFFu;
-      sv[j] = 0;
+      kv[j] = 3u;
       ev[j] = 0;
     }
   }
+  // start - lo + 1, the same shift as the ends (recomputed at each use: fewer
+  // live registers than keeping it)
+  auto sv = [&](int j) { return (kv[j] >> 2) + 1u; };
   // the top level holds every record; the ones below only ranks <= l
-  auto s_in = [&](int j, int l) { return l == NLEV - 1 || (kv[j] & 3u) <= (unsigned int)l ? sv[j] : 0u; };
+  auto s_in = [&](int j, int l) { return l == NLEV - 1 || (kv[j] & 3u) <= (unsigned int)l ? sv(j) : 0u; };
   auto e_in = [&](int j, int l) { return l == NLEV - 1 || (kv[j] & 3u) <= (unsigned int)l ? ev[j] : 0u; };
   // the largest end before each lane: earlier lanes, else the earlier buckets
   unsigned int M[NLEV];
@@ -699,6 +701,12 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
     }
     acc[l] = a;
   }
+  if constexpr (IPL == 8) {
+    // opaque to the compiler: it recomputes the per-level selections of each
+    // phase instead of keeping them all live (which spills at 64 VGPRs)
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) asm volatile("" : "+v"(kv[j]), "+v"(ev[j]));
+  }
   unsigned int P[NLEV], totp[NLEV];
 #pragma unroll
   for (int l = 0; l < NLEV; ++l) P[l] = wave_excl_scan_u32<OpSumU>(acc[l], 0u, totp[l]);
@@ -706,6 +714,12 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
   const unsigned int Rp = wave_excl_scan_u32<OpSumU>(nbrk, 0u, totr);
   // components of one level at a time are staged in LDS (the sorted keys and
   // ends are in registers by now) and then written out in full 64-lane rows
+  if constexpr (IPL == 8) {
+    // opaque to the compiler: it recomputes the per-level selections of each
+    // phase instead of keeping them all live (which spills at 64 VGPRs)
+#pragma unroll
+    for (int j = 0; j < IPL; ++j) asm volatile("" : "+v"(kv[j]), "+v"(ev[j]));
+  }
   uint2* stage = (uint2*)W.key;  // key[] and end[]: kWaveCap entries of 8 B
   wave_sync();
 #pragma unroll
@@ -856,9 +870,8 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   return true;
 }
 
-// One wave per bucket, 8 waves per SIMD (64 VGPRs: the 8-record-per-lane path spills a few
-// values, which costs less than the lost occupancy). Buckets that need
-// the block path go to its queue.
+// One wave per bucket, 8 waves per SIMD (64 VGPRs). Buckets that need the
+// block path go to its queue.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge_wave(Plan p) {
   __shared__ WaveSmem wsm[4];
   const int lane = threadIdx.x & 63;

@@ -122,6 +122,29 @@ def test_crowded_sub_bins_fall_back_to_block_path():
     check(tr2)
 
 
+@pytest.mark.parametrize("n", [2, 60, 200, 300, 512])
+def test_largest_narrow_key(n):
+    """One bucket 2^30 ns wide (the widest the 8 B form holds) whose records
+    include starts at its first time and 2^30 - 1 ns after it: the largest
+    key the wave path sorts. One bucket per resource (target 512), so every
+    wave size of the path is taken, for a device (2 levels) and a host (3)."""
+    rng = np.random.default_rng(7000 + n)
+    t0 = 1 << 40
+    chunks = []
+    for res, kinds in ((0, (tg.HOST_USEFUL, tg.HOST_OFFLOAD, tg.HOST_MPI)), (1, (tg.DEV_KERNEL, tg.DEV_MEMOP))):
+        s = np.sort(rng.integers(t0, t0 + (1 << 30), size=n)).astype(np.int64)
+        s[0], s[-1] = t0, t0 + (1 << 30) - 1
+        e = s + rng.integers(0, 1 << 22, size=n)
+        e[-1] = s[-1] + int(rng.integers(0, 3))
+        k = rng.integers(0, len(kinds), size=n)
+        for i, kind in enumerate(kinds):
+            if np.any(k == i):
+                chunks.append(tg.Chunk(res, kind, s[k == i], e[k == i]))
+    tr = tg.Trace(1, 1, chunks, [(t0, t0 + (1 << 31)), (t0 + (1 << 29), t0 + (1 << 30) - 1),
+                                 (t0 + (1 << 30) - 2, t0 + (1 << 30) + 5)])
+    check(tr, tuning={"bucket_target": 512, "bucket_cap": 2048, "tile_elems": 2048})
+
+
 def test_long_intervals_and_wide_buckets():
     """Buckets the wave path's 32-bit form cannot hold: records ending 2^32 ns
     or more after their bucket's start, and sparse resources whose buckets are
