@@ -49,5 +49,44 @@ def build(verbose=False):
     return LIB
 
 
+COLLECT_SRC = os.path.join(PKG, "collect", "hpop_collect.cpp")
+COLLECT_LIB = os.path.join(PKG, "libhpop_collect.so")
+ROCM_INCLUDE = "/opt/rocm/include"
+ROCM_LIB = "/opt/rocm/lib"
+APP_SRC = os.path.join(ROOT, "tests", "apps", "collect_app.hip")
+APP_BIN = os.path.join(ROOT, "tests", "apps", "collect_app")
+
+
+def build_collect():
+    """libhpop_collect.so: the rocprofiler-sdk tool (host code only, no HIP call)."""
+    tmp = COLLECT_LIB + ".tmp%d" % os.getpid()
+    cmd = ["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE,
+           "-I", ROCM_INCLUDE, COLLECT_SRC, "-o", tmp, "-L" + ROCM_LIB, "-lrocprofiler-sdk",
+           "-Wl,-rpath," + ROCM_LIB]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("collector build failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, COLLECT_LIB)
+    return COLLECT_LIB
+
+
+def build_app():
+    """The collector's test application, linked to both libraries of the package."""
+    tmp = APP_BIN + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + [APP_SRC, "-o", tmp, "-L" + PKG, "-lhpop", "-lhpop_collect",
+                             "-Wl,-rpath," + PKG, "-Wl,-rpath,$ORIGIN/../../paper_2603_26576_amd"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("collect_app build failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, APP_BIN)
+    return APP_BIN
+
+
+def build_all(verbose=False):
+    out = [build(verbose), build_collect()]
+    out.append(build_app())
+    return out
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build_all(verbose="-v" in sys.argv))

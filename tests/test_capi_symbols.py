@@ -1,4 +1,6 @@
-"""The C-ABI library loads and exports every function include/hpop.h declares (CPU only)."""
+"""The C-ABI libraries load and export every function their headers declare
+(include/hpop.h: libhpop.so; include/hpop_collect.h: libhpop_collect.so), and
+the Python bindings cover them (CPU only)."""
 import ctypes
 import os
 import re
@@ -8,14 +10,15 @@ import paper_2603_26576_amd as hp
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    names = set()
-    for f in os.listdir(os.path.join(ROOT, "include")):
-        if f.endswith(".h"):
-            src = open(os.path.join(ROOT, "include", f)).read()
-            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-            names |= set(re.findall(r"\b(hpop_[a-z_0-9]+)\s*\(", src))
-    return sorted(names)
+def declared_functions(header="hpop.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpop_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_header_has_a_library():
+    assert sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")) == \
+        ["hpop.h", "hpop_collect.h"]
 
 
 def test_header_declares_the_boundary():
@@ -45,3 +48,15 @@ def test_status_strings_without_gpu():
 
 def test_tree_layout_matches_header():
     assert ctypes.sizeof(hp.hpop_metric_tree) == 8 + 8 + 10 * 8 + 9 * 8 + 8
+
+
+def test_collector_exports_every_declared_symbol():
+    from paper_2603_26576_amd import collect
+    names = declared_functions("hpop_collect.h")
+    assert "hpop_collect_poll" in names and "hpop_collect_copy" in names
+    lib = ctypes.CDLL(collect.COLLECT_LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert hasattr(lib, "rocprofiler_configure")
+    missing = [n for n in names if not hasattr(collect, n)]
+    assert not missing, missing
