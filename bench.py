@@ -11,20 +11,25 @@ Default workload: 256 host ranks x 256 devices x 4 streams, 10^8 device
 records plus 2.5x10^7 host records (2.0 GB of int64 start/end), host-idle
 fraction 0.1-0.4 per rank, 64 regions (the whole span and 63 tiles of it).
 
-Prints one JSON line. Extra legs (batched traces, serving) are reported as
-sub-objects of the same line; the CPU baseline times the oracle on a bounded
-sample of the same workload.
+Prints one JSON line. Extra legs (batched traces, serving, the live
+collector on its test application) are reported as sub-objects of the same
+line; the CPU baseline times the oracle on a bounded sample of the same
+workload.
 """
 import argparse
 import hashlib
 import json
 import os
+import shutil
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+COLLECT_APP = os.path.join(ROOT, "tests", "apps", "collect_app")
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
@@ -399,6 +404,44 @@ def import_traffic(kernel, workload, fetch_csv, write_csv, cal_fetch_csv, cal_wr
     print(path, rec)
 
 
+def run_collect_app(iters, live_every, prefix, with_tool):
+    from paper_2603_26576_amd import collect
+    env = collect.tool_env() if with_tool else dict(os.environ, HPOP_APP_ALLOW_INACTIVE="1")
+    if not with_tool:
+        env.pop("ROCP_TOOL_LIBRARIES", None)
+    r = subprocess.run([COLLECT_APP, str(iters), str(live_every), prefix], env=env, capture_output=True, text=True,
+                       timeout=300)
+    if r.returncode != 0:
+        raise RuntimeError("collect_app failed (%d): %s" % (r.returncode, r.stderr[-1000:]))
+    line = [l for l in r.stdout.splitlines() if l.startswith("collect_app ")][-1]
+    return {k: float(v) for k, v in (kv.split("=") for kv in line.split()[1:])}
+
+
+def collector_leg(hp, iters=400, live_every=20):
+    """The live collector on its test application (a real HIP program): the
+    tracing cost per runtime call and per iteration (with the tool against
+    without it), and the latency of each live region (poll, copy, submit to
+    an in-process hpop server, wait for its trees)."""
+    if not os.path.exists(COLLECT_APP):
+        return {"skipped": "tests/apps/collect_app is not built"}
+    tmp = tempfile.mkdtemp(prefix="hpop_collect_")
+    try:
+        base = run_collect_app(iters, 0, os.path.join(tmp, "plain"), False)
+        traced = run_collect_app(iters, 0, os.path.join(tmp, "traced"), True)
+        live = run_collect_app(iters, live_every, os.path.join(tmp, "live"), True)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+    return {"app": "tests/apps/collect_app: per iteration 150 us of host work, 2 copies of 4 MiB, a 1 MiB fill, "
+                   "2 kernels on 2 streams, a device synchronisation",
+            "iters": iters, "call_ns_without_tool": base["call_ns"], "call_ns_traced": traced["call_ns"],
+            "iter_us_without_tool": base["iter_us"], "iter_us_traced": traced["iter_us"],
+            "iter_us_live": live["iter_us"], "live_regions": int(live["regions"]),
+            "live_every_iters": live_every, "live_records_per_region": round(live["live_records"] / max(1, live["regions"]), 1),
+            "live_p50_us": live["live_p50_us"], "live_max_us": live["live_max_us"],
+            "live_poll_p50_us": live["live_poll_p50_us"],
+            "dropped": int(traced["dropped"] + live["dropped"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,6 +457,8 @@ def main():
     ap.add_argument("--serving-queries", type=int, default=400)
     ap.add_argument("--serving-lambdas", default="2000,10000")
     ap.add_argument("--serving-host-lambdas", default="2000", help="runs with payloads in host memory")
+    ap.add_argument("--no-collector", action="store_true")
+    ap.add_argument("--collector-only", action="store_true", help="run only the collector leg")
     ap.add_argument("--json-out", default=None)
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (JSON)")
     ap.add_argument("--trace-cache", default=None, help="npz file to reuse the generated workload")
@@ -437,6 +482,9 @@ def main():
         return
     hp.lib()
 
+    if args.collector_only:
+        print(json.dumps({"collector": collector_leg(None)}), flush=True)
+        return
     if args.serving_only:
         lams = [int(x) for x in args.serving_lambdas.split(",") if x]
         host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x]
@@ -493,6 +541,10 @@ def main():
         host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x]
         log("serving leg: lambdas %s, %d queries each" % (lams, args.serving_queries))
         out["serving"] = serving_leg(hp, lams, args.serving_queries, host_lambdas=host_lams)
+    if not args.no_collector:
+        log("collector leg")
+        out["collector"] = collector_leg(hp)
+        log("collector: %s" % out["collector"])
     line = json.dumps(out)
     print(line, flush=True)
     if args.json_out:

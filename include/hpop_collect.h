@@ -32,7 +32,7 @@
  * rocprofiler-sdk then calls its configuration entry when the HIP runtime
  * starts. One configuration per process; later ones are declined.
  *
- * Output. At process exit, if HPOP_COLLECT_OUT names a path (a "%p" in it is
+ * Output. At process exit (all records flushed), if HPOP_COLLECT_OUT names a path (a "%p" in it is
  * replaced by the process id), every record is written there in the format
  * below. An application can also take the records while it runs with
  * hpop_collect_poll / hpop_collect_count / hpop_collect_copy and hand them to
@@ -74,15 +74,22 @@ int32_t hpop_collect_devices(void);
 int64_t hpop_collect_now(void);
 int64_t hpop_collect_begin(void);
 
-/* Makes the records up to a frontier final and returns the frontier.
- * Device records that the runtime has completed are flushed from rocprofiler's
- * buffers; the frontier is the current time, or the start of the earliest
- * offload call still running in any thread if that is earlier. Every host
- * record that starts before the frontier is then known, so the Useful gaps up
- * to it are appended. Device records arrive in completion order, so a kernel
- * that ends before the frontier may still be delivered by a later poll.
+/* Makes the host records up to a frontier final and returns the frontier:
+ * the current time, or the start of the earliest offload call still running
+ * in any thread if that is earlier. Every host record that starts before the
+ * frontier is then known, so the Useful gaps up to it are appended. Takes
+ * microseconds: device records are not flushed here. They arrive from
+ * rocprofiler's buffers in completion order, delivered by the tool's own
+ * thread every HPOP_COLLECT_FLUSH_MS milliseconds (environment, default 10;
+ * 0 = only when a buffer fills), or at once by hpop_collect_flush; a kernel
+ * that ends before the frontier may therefore be taken by a later poll.
  * Errors: HPOP_E_STATE before configuration, HPOP_E_ARG for a null pointer. */
 hpop_status hpop_collect_poll(int64_t* out_frontier);
+
+/* Delivers every device record the runtime has completed (blocks, typically
+ * for milliseconds). Call it before a final poll to take everything.
+ * HPOP_E_STATE before configuration. */
+hpop_status hpop_collect_flush(void);
 
 /* Records of (resource, kind) made final so far (0 for an unknown pair). */
 int64_t hpop_collect_count(int32_t resource, int32_t kind);

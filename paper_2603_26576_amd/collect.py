@@ -35,6 +35,7 @@ def collect_lib():
             ("hpop_collect_now", i64, []),
             ("hpop_collect_begin", i64, []),
             ("hpop_collect_poll", i32, [p64]),
+            ("hpop_collect_flush", i32, []),
             ("hpop_collect_count", i64, [i32, i32]),
             ("hpop_collect_copy", i32, [i32, i32, i64, i64, ctypes.c_void_p, ctypes.c_void_p]),
             ("hpop_collect_write", i32, [ctypes.c_char_p]),
@@ -81,6 +82,10 @@ def hpop_collect_poll():
     f = ctypes.c_int64(0)
     _check(collect_lib().hpop_collect_poll(ctypes.byref(f)))
     return f.value
+
+
+def hpop_collect_flush():
+    _check(collect_lib().hpop_collect_flush())
 
 
 def hpop_collect_count(resource, kind):

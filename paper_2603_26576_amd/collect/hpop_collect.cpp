@@ -7,8 +7,9 @@
 // one Device Offloading record, and the Useful records are the gaps between
 // offload calls, made final up to a frontier before which no call can still
 // be missing. Device side: kernel dispatch and memory copy records delivered
-// in rocprofiler buffers, one device resource per GPU agent. The library
-// makes no HIP call.
+// in rocprofiler buffers, one device resource per GPU agent, flushed
+// periodically by a thread of the tool (a flush blocks for milliseconds, too
+// long for the application's own threads). The library makes no HIP call.
 #include <rocprofiler-sdk/registration.h>
 #include <rocprofiler-sdk/rocprofiler.h>
 
@@ -16,6 +17,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -63,6 +66,12 @@ struct Collector {
   std::mutex mu_threads;
   std::vector<ThreadSlot*> threads;
   std::atomic<int64_t> dropped{0};
+
+  // periodic delivery of device records, off the application's threads
+  std::thread flusher;
+  std::mutex mu_flush;
+  std::condition_variable cv_flush;
+  bool stop_flush = false;
 };
 
 // Created on first use and never destroyed: rocprofiler may call the tool
@@ -234,6 +243,22 @@ std::string out_path() {
   return s;
 }
 
+void flush_loop(int period_ms) {
+  std::unique_lock<std::mutex> lk(G().mu_flush);
+  while (!G().cv_flush.wait_for(lk, std::chrono::milliseconds(period_ms), [] { return G().stop_flush; })) {
+    lk.unlock();
+    rocprofiler_flush_buffer(G().buf);
+    lk.lock();
+  }
+}
+
+int flush_period_ms() {
+  const char* v = std::getenv("HPOP_COLLECT_FLUSH_MS");
+  if (!v || !*v) return 10;
+  const int ms = std::atoi(v);
+  return ms < 0 ? 0 : ms;
+}
+
 int tool_init(rocprofiler_client_finalize_t, void*) {
   if (rocprofiler_query_available_agents(ROCPROFILER_AGENT_INFO_VERSION_0, on_agents, sizeof(rocprofiler_agent_v0_t),
                                          nullptr) != ROCPROFILER_STATUS_SUCCESS)
@@ -260,11 +285,28 @@ int tool_init(rocprofiler_client_finalize_t, void*) {
   G().sealed = G().t_begin;
   if (rocprofiler_start_context(G().ctx) != ROCPROFILER_STATUS_SUCCESS) return -1;
   G().active.store(1);
+  const int period = flush_period_ms();
+  if (period > 0) {
+    try {
+      G().flusher = std::thread(flush_loop, period);
+    } catch (...) {
+      // no thread: records still arrive when a buffer fills or on hpop_collect_flush
+    }
+  }
   return 0;
 }
 
 void tool_fini(void*) {
   if (!G().active.load()) return;
+  if (G().flusher.joinable()) {
+    {
+      std::lock_guard<std::mutex> lk(G().mu_flush);
+      G().stop_flush = true;
+    }
+    G().cv_flush.notify_all();
+    G().flusher.join();
+  }
+  hpop_collect_flush();
   int64_t f = 0;
   hpop_collect_poll(&f);
   const std::string p = out_path();
@@ -305,13 +347,17 @@ int64_t hpop_collect_begin(void) { return G().active.load() ? G().t_begin : 0; }
 hpop_status hpop_collect_poll(int64_t* out_frontier) {
   if (!out_frontier) return HPOP_E_ARG;
   if (!G().active.load()) return HPOP_E_STATE;
-  // deliver what the runtime has completed; no lock held (the buffer callback takes it)
-  rocprofiler_flush_buffer(G().buf);
   const int64_t f = take_frontier();
   std::lock_guard<std::mutex> lk(G().mu);
   seal(std::max(f, G().sealed));
   *out_frontier = G().sealed;
   return HPOP_OK;
+}
+
+hpop_status hpop_collect_flush(void) {
+  if (!G().active.load()) return HPOP_E_STATE;
+  // no lock held: the buffer callback takes it
+  return rocprofiler_flush_buffer(G().buf) == ROCPROFILER_STATUS_SUCCESS ? HPOP_OK : HPOP_E_STATE;
 }
 
 int64_t hpop_collect_count(int32_t resource, int32_t kind) {

@@ -12,9 +12,16 @@
 // and with LIVE_EVERY > 0 OUT_PREFIX.live: per region, int64 t0, t1, the
 // cumulative record count of every (resource, kind) pair (resource-major,
 // 5 kinds each), then the region's and the session's hpop_metric_tree.
-// Prints one summary line; exits non-zero on any error.
+// Prints one summary line; exits non-zero on any error. The line also holds
+// what the tool costs the program: call_ns, the mean time of a cheap runtime
+// call (hipGetDevice, each one traced when the tool is active), iter_us, the
+// mean time of one iteration, and in live mode the latency of each region
+// (poll, copy, submit and wait). With HPOP_APP_ALLOW_INACTIVE=1 in the
+// environment the program also runs without the tool (LIVE_EVERY must be 0;
+// no trace is written), for the same timings without tracing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -60,10 +67,15 @@ struct Feed {
   int64_t prev = 0;            // end of the last region
   FILE* out = nullptr;
   int regions = 0;
+  std::vector<double> lat_us;   // per region: poll to answer
+  std::vector<double> poll_us;  // per region: the poll alone
+  double records = 0;           // submitted in all regions
 
   void step() {
+    const auto c0 = std::chrono::steady_clock::now();
     int64_t f = 0;
     CKH(hpop_collect_poll(&f));
+    poll_us.push_back(std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - c0).count());
     if (f <= prev) return;
     std::vector<std::vector<int64_t>> keep;
     std::vector<hpop_event_chunk> chunks;
@@ -79,11 +91,13 @@ struct Feed {
         CKH(hpop_collect_copy(r, k, taken[i], n, s, s + n));
         chunks.push_back(hpop_event_chunk{r, k, s, s + n, n});
         taken[i] = c;
+        records += (double)n;
       }
     uint64_t ticket = 0;
     CKH(hpop_server_submit(srv, sid, chunks.data(), (int32_t)chunks.size(), HPOP_MEM_HOST, prev, f, &ticket));
     hpop_metric_tree reg{}, glob{};
     CKH(hpop_server_wait(srv, ticket, -1, &reg, &glob));
+    lat_us.push_back(std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - c0).count());
     const int64_t span[2] = {prev, f};
     std::fwrite(span, sizeof span, 1, out);
     std::fwrite(taken.data(), sizeof(int64_t), taken.size(), out);
@@ -104,11 +118,20 @@ int main(int argc, char** argv) {
   const std::string prefix = argv[3];
   std::setvbuf(stdout, nullptr, _IOLBF, 0);  // a failure later on keeps what was printed
   CK(hipSetDevice(0));
-  if (!hpop_collect_active()) {
+  const char* allow = std::getenv("HPOP_APP_ALLOW_INACTIVE");
+  const bool active = hpop_collect_active() != 0;
+  if (!active && !(allow && allow[0] == '1' && live_every == 0)) {
     std::fprintf(stderr, "the hpop_collect tool is not active in this process\n");
     return 4;
   }
-  std::printf("collect_app: tool active, %d device(s)\n", hpop_collect_devices());
+  std::printf("collect_app: tool %s, %d device(s)\n", active ? "active" : "not loaded", hpop_collect_devices());
+  // a cheap runtime call, traced like any other when the tool is active
+  const int n_calls = 20000;
+  int dev = -1;
+  const auto q0 = std::chrono::steady_clock::now();
+  for (int i = 0; i < n_calls; ++i) CK(hipGetDevice(&dev));
+  const double call_ns =
+      std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - q0).count() / n_calls;
   const size_t bytes = 4u << 20;
   void *d0 = nullptr, *d1 = nullptr, *h0 = nullptr, *h1 = nullptr;
   CK(hipMalloc(&d0, bytes));
@@ -138,6 +161,7 @@ int main(int argc, char** argv) {
   }
 
   double busy_ns = 0;
+  const auto l0 = std::chrono::steady_clock::now();
   for (int it = 0; it < iters; ++it) {
     const auto b0 = std::chrono::steady_clock::now();
     while (std::chrono::steady_clock::now() - b0 < std::chrono::microseconds(150)) {
@@ -157,7 +181,10 @@ int main(int argc, char** argv) {
     CK(hipDeviceSynchronize());
     if (live_every > 0 && (it + 1) % live_every == 0) feed.step();
   }
+  const double iter_us =
+      std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - l0).count() / std::max(1, iters);
   if (live_every > 0) {
+    CKH(hpop_collect_flush());  // the last region takes every record
     feed.step();
     std::fclose(feed.out);
     CKH(hpop_server_destroy(feed.srv));
@@ -178,10 +205,22 @@ int main(int argc, char** argv) {
   CK(hipHostFree(h0));
   CK(hipHostFree(h1));
   CK(hipDeviceSynchronize());
-  int64_t f = 0;
-  CKH(hpop_collect_poll(&f));
-  CKH(hpop_collect_write((prefix + ".trace").c_str()));
-  std::printf("collect_app iters=%d kernels=%d fills=%d copies=%d busy_ns=%.0f regions=%d dropped=%lld\n", iters,
-              2 * iters, iters, 2 * iters, busy_ns, feed.regions, (long long)hpop_collect_dropped());
+  if (active) {
+    CKH(hpop_collect_flush());
+    int64_t f = 0;
+    CKH(hpop_collect_poll(&f));
+    CKH(hpop_collect_write((prefix + ".trace").c_str()));
+  }
+  std::vector<double> lat = feed.lat_us;
+  std::sort(lat.begin(), lat.end());
+  const double p50 = lat.empty() ? 0.0 : lat[lat.size() / 2], mx = lat.empty() ? 0.0 : lat.back();
+  std::vector<double> pl = feed.poll_us;
+  std::sort(pl.begin(), pl.end());
+  const double poll_p50 = pl.empty() ? 0.0 : pl[pl.size() / 2];
+  std::printf(
+      "collect_app iters=%d kernels=%d fills=%d copies=%d busy_ns=%.0f regions=%d dropped=%lld call_ns=%.1f "
+      "iter_us=%.1f live_p50_us=%.1f live_max_us=%.1f live_poll_p50_us=%.1f live_records=%.0f\n",
+      iters, 2 * iters, iters, 2 * iters, busy_ns, feed.regions, (long long)hpop_collect_dropped(), call_ns, iter_us,
+      p50, mx, poll_p50, feed.records);
   return 0;
 }
