@@ -170,3 +170,55 @@ def compute_multi(trace, regions):
                      _ratio(sK, m * mK, 6, mk), _ratio(mK, mKM, 7, mk), _ratio(mKM, E, 8, mk)]
         masks[g] = mk[0]
     return {"times": times, "sums": sums, "ratios": ratios, "mask": masks, "E": Es}
+
+
+def compute_streams(n_streams, chunks, regions):
+    """Stream concurrency of the devices (the stream-level row; the paper
+    leaves streams to its future Device Computational Efficiency branch,
+    Sec. 4.1, so the definition is this engine's reading).
+
+    n_streams[g]: streams declared on device g (all count, busy or not).
+    chunks: (device g, stream s, start, end) kernel records, s < n_streams[g].
+    regions: [(t0, t1)].
+
+    Plain definition, per region and device g: U_gs = union measure of the
+    records of stream s inside the region (the C union_measure); B_g = union
+    measure of all records of g; ST_g = sum_s U_gs (the stream time: the
+    integral of the number of active streams). Aggregates over devices:
+    busy = sum_g B_g, stream_time = sum_g ST_g, capacity = sum_g S_g B_g;
+    efficiency = stream_time / capacity (bit 0 when 0/0), mean_active =
+    stream_time / busy (bit 1). Each ratio one IEEE division; 0/0 := 1.
+    Returns per_device [region][g] = (B_g, ST_g, S_g), sums [region] =
+    (busy, stream_time, capacity), ratios, mask.
+    """
+    m = len(n_streams)
+    nreg = len(regions)
+    per = np.zeros((nreg, m, 3), np.int64)
+    sums = np.zeros((nreg, 3), np.int64)
+    ratios = np.zeros((nreg, 2), np.float64)
+    masks = np.zeros(nreg, np.uint32)
+    for g in range(m):
+        sel = [c for c in chunks if c[0] == g]
+        s_all = np.concatenate([np.asarray(c[2], np.int64) for c in sel]) if sel else np.zeros(0, np.int64)
+        e_all = np.concatenate([np.asarray(c[3], np.int64) for c in sel]) if sel else np.zeros(0, np.int64)
+        B = union_measure(s_all, e_all, regions) if nreg else np.zeros(0, np.int64)
+        ST = np.zeros(nreg, np.int64)
+        for st in range(int(n_streams[g])):
+            cs = [c for c in sel if c[1] == st]
+            if not cs:
+                continue
+            ss = np.concatenate([np.asarray(c[2], np.int64) for c in cs])
+            ee = np.concatenate([np.asarray(c[3], np.int64) for c in cs])
+            ST += union_measure(ss, ee, regions)
+        per[:, g, 0] = B
+        per[:, g, 1] = ST
+        per[:, g, 2] = int(n_streams[g])
+    for r in range(nreg):
+        busy = int(per[r, :, 0].sum())
+        stream_time = int(per[r, :, 1].sum())
+        capacity = int((per[r, :, 0] * per[r, :, 2]).sum())
+        sums[r] = [busy, stream_time, capacity]
+        mk = [0]
+        ratios[r] = [_ratio(stream_time, capacity, 0, mk), _ratio(stream_time, busy, 1, mk)]
+        masks[r] = mk[0]
+    return {"per_device": per, "sums": sums, "ratios": ratios, "mask": masks}
