@@ -50,12 +50,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# the sources that define the build kernels (their code, launch shapes and data layout)
+KERNEL_SOURCES = ("hpop_kernels.hip", "hpop_kernels.h", "hpop_device.h", "hpop_internal.h")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_26576_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

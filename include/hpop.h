@@ -242,6 +242,58 @@ hpop_status hpop_autotune(hpop_session* const* sessions, int32_t k, const char* 
                           hpop_tuning* out);
 
 /* ----------------------------------------------------------------------------
+ * Stream concurrency. The paper counts each device as one resource and leaves
+ * its streams to a future Device Computational Efficiency branch (Sec. 4.1),
+ * so this measure is the library's own definition. For device g with S_g
+ * declared streams and a region [t0, t1):
+ *   B_g  = time during which at least one of its streams runs a kernel
+ *   ST_g = sum over its streams of the time that stream runs a kernel
+ *          (the integral of the number of active streams)
+ * and over the devices:
+ *   stream_eff  = sum ST_g / sum S_g B_g   (1: every declared stream runs
+ *                 whenever its device runs a kernel; 1/S: one at a time)
+ *   mean_active = sum ST_g / sum B_g        (mean active streams while busy)
+ * Each ratio is one IEEE division of exact integers; 0/0 is 1 with its bit
+ * (0, 1) set. Records of one stream that overlap count once.
+ * -------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t busy;          /* sum over devices of B_g */
+    int64_t stream_time;   /* sum over devices of ST_g */
+    int64_t capacity;      /* sum over devices of S_g * B_g */
+    int32_t m;             /* devices */
+    int32_t n_streams;     /* sum over devices of S_g */
+    double stream_eff;     /* bit 0 */
+    double mean_active;    /* bit 1 */
+    uint32_t undefined_mask;
+    uint32_t reserved;
+} hpop_stream_tree;
+
+/* Declares S_g = n_streams[g] >= 0 streams on each of the session's devices
+ * (array of n_devices; stream ids 0 .. S_g - 1; sum of S_g + 1 at most 2^24).
+ * May be called again only while no stream record was added (HPOP_E_STATE).
+ * Errors: HPOP_E_ARG (null, negative or too many streams). */
+hpop_status hpop_session_set_streams(hpop_session* s, const int32_t* n_streams);
+
+/* Kernel records of one stream of one device: like hpop_add_events with kind
+ * HPOP_DEV_KERNEL (they count in the device tree too), and kept by stream for
+ * hpop_stream_metrics. Same memory rules and validation as hpop_add_events.
+ * Errors: HPOP_E_STATE (no hpop_session_set_streams), HPOP_E_RESOURCE (not a
+ * device, or stream outside 0 .. S_g - 1), HPOP_E_ARG, HPOP_E_BAD_INTERVAL;
+ * a failed call adds nothing. */
+hpop_status hpop_add_stream_events(hpop_session* s, int32_t resource, int32_t stream, const int64_t* start,
+                                   const int64_t* end, int64_t count, int32_t mem_space);
+
+/* Stream concurrency of every region (out[n_regions]) and, if per_device is
+ * not NULL, per region and device the triple (B_g, ST_g, S_g)
+ * (int64[n_regions][n_devices][3]). flags as hpop_metrics_compute_all.
+ * Errors: HPOP_E_STATE (no hpop_session_set_streams), HPOP_E_REGION (a region
+ * of hpop_region_define_multi: stream measures need one span per region),
+ * HPOP_E_OVERFLOW ((t1 - t0) * sum S_g >= 2^53), HPOP_E_BAD_INTERVAL (an
+ * invalid device-memory record), HPOP_E_OOM, HPOP_E_HIP. */
+hpop_status hpop_stream_metrics(hpop_session* s, uint32_t flags, hpop_stream_tree* out, int64_t* per_device);
+
+/* ----------------------------------------------------------------------------
  * Serving runtime (online analysis: Section 3.2 describes TALP's run-time
  * queries; Section 4.2 its batched, asynchronously delivered device records).
  *

@@ -142,6 +142,9 @@ _SIGS = {
     "hpop_server_get_stats": (_I32, [_P, ctypes.POINTER(hpop_server_stats)]),
     "hpop_server_last_error": (ctypes.c_char_p, [_P]),
     "hpop_tree_format": (_I32, [ctypes.POINTER(hpop_metric_tree), _I32, ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
+    "hpop_session_set_streams": (_I32, [_P, _P]),
+    "hpop_add_stream_events": (_I32, [_P, _I32, _I32, _P, _P, _I64, _I32]),
+    "hpop_stream_metrics": (_I32, [_P, _U32, ctypes.c_void_p, _P]),
     "hpop_server_replay": (_I32, [_P, ctypes.POINTER(hpop_replay_query), _I32, _I32,
                                   ctypes.POINTER(hpop_metric_tree), ctypes.POINTER(hpop_metric_tree),
                                   ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
@@ -247,6 +250,38 @@ def hpop_region_define_multi(s, intervals):
     _check(lib().hpop_region_define_multi(s, r.ctypes.data, a.ctypes.data, b.ctypes.data, len(intervals),
                                           ctypes.byref(out)), s)
     return out.value
+
+
+class hpop_stream_tree(ctypes.Structure):
+    _fields_ = [("busy", ctypes.c_int64), ("stream_time", ctypes.c_int64), ("capacity", ctypes.c_int64),
+                ("m", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("stream_eff", ctypes.c_double),
+                ("mean_active", ctypes.c_double), ("undefined_mask", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+def hpop_session_set_streams(s, n_streams):
+    """Declare the streams of every device: n_streams[g] for device g."""
+    arr = np.ascontiguousarray(n_streams, np.int32)
+    _check(lib().hpop_session_set_streams(s, arr.ctypes.data if arr.size else None), s)
+
+
+def hpop_add_stream_events(s, resource, stream, start, end):
+    ps, ms = _ptr(start)
+    pe, me = _ptr(end)
+    if ms != me or len(start) != len(end):
+        raise ValueError("start and end must have the same length and memory space")
+    _check(lib().hpop_add_stream_events(s, resource, stream, ps, pe, len(start), ms), s)
+
+
+def hpop_stream_metrics(s, flags=0, n_devices=None):
+    """Stream trees of every region; given the session's n_devices, also the
+    int64 array [region][device][3] of (busy, stream time, streams)."""
+    n = hpop_num_regions(s)
+    out = (hpop_stream_tree * max(1, n))()
+    per = np.zeros((max(1, n), max(1, n_devices), 3), np.int64) if n_devices is not None else None
+    _check(lib().hpop_stream_metrics(s, flags, ctypes.cast(out, ctypes.c_void_p),
+                                     per.ctypes.data if per is not None else None), s)
+    trees = list(out[:n])
+    return (trees, per[:n, :n_devices]) if per is not None else trees
 
 
 def hpop_num_regions(s):

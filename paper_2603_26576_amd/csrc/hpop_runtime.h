@@ -138,4 +138,10 @@ struct hpop_session {
   hpop::Engine engine;
   hpop::Engine batch_engine;
   std::string last_error;
+  // stream concurrency (hpop_session_set_streams): an inner session whose
+  // resources are, per device g, one holding all its stream records followed
+  // by one per stream (resource stream_off[g] + 1 + stream)
+  hpop_session* streams = nullptr;
+  std::vector<int32_t> stream_n, stream_off;
+  hpop::DevBuf stream_buf;
 };

@@ -708,6 +708,8 @@ hpop_status hpop_session_destroy(hpop_session* s) {
   HPOP_GUARD_BEGIN
   if (!s) return fail(nullptr, HPOP_E_ARG, "null session");
   (void)hipStreamSynchronize(s->stream);
+  if (s->streams) hpop_session_destroy(s->streams);
+  s->stream_buf.release(s->alloc);
   s->engine.release();
   s->batch_engine.release();
   s->arena.release(s->alloc);
@@ -843,6 +845,7 @@ hpop_status hpop_session_synchronize(hpop_session* s) {
 hpop_status hpop_clear_events(hpop_session* s) {
   HPOP_GUARD_BEGIN
   if (!s) return fail(nullptr, HPOP_E_ARG, "null session");
+  if (s->streams) hpop_clear_events(s->streams);
   s->chunks.clear();
   s->arena_used = 0;
   s->arena.used = 0;

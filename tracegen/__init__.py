@@ -110,18 +110,22 @@ def _gaps(rng, n):
 
 
 def device_timeline(rng, n_events: int, streams: int, w: float, t0: int,
-                    p_memop: float = P_MEMOP, p_overlap: float = P_OVERLAP):
-    """One device's activity: returns (start, end, kind, realised overlap fraction).
+                    p_memop: float = P_MEMOP, p_overlap: float = P_OVERLAP, return_streams: bool = False):
+    """One device's activity: returns (start, end, kind, realised overlap fraction),
+    and with return_streams also the stream of every event.
 
     Events form launch groups. The first event of a group starts a gap after
     the previous group's last end; each further event of the group starts
     inside its predecessor (at a uniform fraction of the predecessor's
-    duration), as a launch on another stream would.
+    duration), as a launch on another stream would. A group holds at most
+    `streams` events, on distinct streams (rotating from group to group), so
+    no stream runs two events at once.
     """
     n = int(n_events)
     if n == 0:
         z = np.zeros(0, np.int64)
-        return z, z, np.zeros(0, np.int32), 0.0
+        out = (z, z, np.zeros(0, np.int32), 0.0)
+        return out + (np.zeros(0, np.int32),) if return_streams else out
     is_mem = rng.random(n) < p_memop
     kdur = _durations(rng, n, w)
     size = np.exp(rng.uniform(np.log(MEMOP_MIN_BYTES), np.log(MEMOP_MAX_BYTES), size=n))
@@ -160,7 +164,10 @@ def device_timeline(rng, n_events: int, streams: int, w: float, t0: int,
     gstart = t0 + np.cumsum(gap + prev_extent)
     s = gstart[gid] + off
     e = s + d
-    return s.astype(np.int64), e.astype(np.int64), kind, float(ov.mean())
+    out = (s.astype(np.int64), e.astype(np.int64), kind, float(ov.mean()))
+    if return_streams:
+        return out + (((gid + pos) % max(streams, 1)).astype(np.int32),)
+    return out
 
 
 def host_timeline(rng, n_events: int, w: float, t0: int, idle_frac: Optional[float] = None):
@@ -282,6 +289,23 @@ def make_trace(seed: int, n_ranks: int, n_devices: int, streams: int,
 # ----------------------------------------------------------------------------
 # the workload configurations
 # ----------------------------------------------------------------------------
+
+def stream_kernels(seed: int, n_devices: int, streams: int, events_per_device: int, t0: int = T0,
+                   w_range=(0.5, 1.5), p_overlap: float = 0.5):
+    """Kernel records per (device, stream) with the launch-group shape of
+    device_timeline: returns (streams per device, [(device, stream, start, end)])."""
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(w_range[0], w_range[1], size=n_devices)
+    chunks = []
+    for g in range(n_devices):
+        s, e, _, _, st = device_timeline(rng, events_per_device, streams, float(w[g]), t0, p_memop=0.0,
+                                         p_overlap=p_overlap, return_streams=True)
+        for k in range(streams):
+            sel = st == k
+            if sel.any():
+                chunks.append((g, k, s[sel], e[sel]))
+    return [streams] * n_devices, chunks
+
 
 def small(seed: int = 1001) -> Trace:
     """4 ranks, one device each, 2 streams, 10^4 events per resource, 1 region."""
