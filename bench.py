@@ -11,8 +11,8 @@ Default workload: 256 host ranks x 256 devices x 4 streams, 10^8 device
 records plus 2.5x10^7 host records (2.0 GB of int64 start/end), host-idle
 fraction 0.1-0.4 per rank, 64 regions (the whole span and 63 tiles of it).
 
-Prints one JSON line. Extra legs (batched traces, serving, the live
-collector on its test application) are reported as sub-objects of the same
+Prints one JSON line. Extra legs (batched traces, serving, stream
+concurrency, the live collector on its test application) are reported as sub-objects of the same
 line; the CPU baseline times the oracle on a bounded sample of the same
 workload.
 """
@@ -196,6 +196,46 @@ def bench_batched(hp, traces, steps, warmup, tune_cache=None):
     return {"traces": len(traces), "events": n_events, "segments": segs, "ms_per_step": round(dt * 1e3, 3),
             "events_per_s": n_events / dt,
             "tuning": {"bucket_target": tun.bucket_target, "bucket_cap": tun.bucket_cap, "tile_elems": tun.tile_elems}}
+
+
+def streams_leg(hp, steps, warmup, n_devices=256, streams=4, per_device=100_000, n_regions=16, seed=1006):
+    """Stream concurrency of every device (hpop_stream_metrics): kernel records
+    tagged by stream, in the launch-group shape of the main workload's
+    devices, resident in HBM; each step rebuilds the per-stream and per-device
+    merged lists and reduces all regions (the whole span and tiles of it)."""
+    import torch
+    import tracegen as tg
+    n_streams, chunks = tg.stream_kernels(seed, n_devices, streams, per_device)
+    n_rec = sum(int(c[2].size) for c in chunks)
+    lo = min(int(c[2].min()) for c in chunks)
+    hi = max(int(c[3].max()) for c in chunks)
+    cuts = np.linspace(lo, hi, n_regions).astype(np.int64)
+    regions = [(lo, hi)] + [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])]
+    s = hp.hpop_session_create(0, n_devices)
+    try:
+        hp.hpop_session_set_tuning(s, 256, 2048, 2048)
+        hp.hpop_session_set_streams(s, n_streams)
+        dev = [(g, k, torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()) for g, k, a, b in chunks]
+        torch.cuda.synchronize()
+        for g, k, a, b in dev:
+            hp.hpop_add_stream_events(s, g, k, a, b)
+        hp.hpop_session_synchronize(s)
+        del dev
+        for t0, t1 in regions:
+            hp.hpop_region_define(s, t0, t1)
+        for _ in range(max(1, warmup)):
+            trees = hp.hpop_stream_metrics(s, hp.HPOP_FORCE_REBUILD)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            trees = hp.hpop_stream_metrics(s, hp.HPOP_FORCE_REBUILD)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+    finally:
+        hp.hpop_session_destroy(s)
+    return {"devices": n_devices, "streams_per_device": streams, "records": n_rec, "regions": len(regions),
+            "ms_per_step": round(dt * 1e3, 3), "records_per_s": n_rec / dt,
+            "stream_eff": trees[0].stream_eff, "mean_active": trees[0].mean_active}
 
 
 def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, streams=4, warm=1_000_000,
@@ -460,6 +500,8 @@ def main():
     ap.add_argument("--serving-queries", type=int, default=400)
     ap.add_argument("--serving-lambdas", default="2000,10000")
     ap.add_argument("--serving-host-lambdas", default="2000", help="runs with payloads in host memory")
+    ap.add_argument("--no-streams", action="store_true")
+    ap.add_argument("--streams-only", action="store_true", help="run only the stream concurrency leg")
     ap.add_argument("--no-collector", action="store_true")
     ap.add_argument("--collector-only", action="store_true", help="run only the collector leg")
     ap.add_argument("--json-out", default=None)
@@ -485,6 +527,9 @@ def main():
         return
     hp.lib()
 
+    if args.streams_only:
+        print(json.dumps({"streams": streams_leg(hp, args.steps, args.warmup)}), flush=True)
+        return
     if args.collector_only:
         print(json.dumps({"collector": collector_leg(None)}), flush=True)
         return
@@ -544,6 +589,10 @@ def main():
         host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x]
         log("serving leg: lambdas %s, %d queries each" % (lams, args.serving_queries))
         out["serving"] = serving_leg(hp, lams, args.serving_queries, host_lambdas=host_lams)
+    if not args.no_streams:
+        log("stream concurrency leg")
+        out["streams"] = streams_leg(hp, args.steps, args.warmup)
+        log("streams: %s" % out["streams"])
     if not args.no_collector:
         log("collector leg")
         out["collector"] = collector_leg(hp)
