@@ -768,18 +768,22 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
                                             const long long (&maxe)[3]) {
   const int lane = threadIdx.x & 63;
   unsigned int kr[IPL], er[IPL], rk[IPL];
-  unsigned int kor = 0;
+  // every lane loads every round, from a position clamped into the bucket
+  // (ni >= 1): the loads issue back to back instead of one masked block (and
+  // one wait) each
+  uint2 x[IPL];
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
     const int i = lane + 64 * r;
-    kr[r] = 0;
-    er[r] = 0;
-    if (i < ni) {
-      const uint2 x = rec[i];  // already relative to lo: (start - lo) << 2 | slot, end - lo + 1
-      kr[r] = x.x;
-      er[r] = x.y;
-      kor |= x.x;
-    }
+    x[r] = rec[i < ni ? i : ni - 1];  // already relative to lo: (start - lo) << 2 | slot, end - lo + 1
+  }
+  unsigned int kor = 0;
+#pragma unroll
+  for (int r = 0; r < IPL; ++r) {
+    const bool in = lane + 64 * r < ni;
+    kr[r] = in ? x[r].x : 0u;
+    er[r] = in ? x[r].y : 0u;
+    kor |= kr[r];
   }
   // the segment's geometry only now, while the records are in flight
   const SegDesc sd = p.segs[p.bucket_seg[gb]];
@@ -795,13 +799,16 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   wave_sync();
   const int hb = kor ? 32 - __clz((int)kor) : 0;
   const int dsh = hb > dbits ? hb - dbits : 0;  // sub-bin = (key >> 2) >> dsh
+  // the atomics of all rounds are issued with no branch, so they overlap
+  // instead of waiting one by one; a position past the bucket adds 0 to a
+  // word of its own (word `lane`: there are at least 64), so lanes past the
+  // bucket never pile onto one address
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
-    if (lane + 64 * r < ni) {
-      const unsigned int d = (kr[r] >> 2) >> dsh;
-      const unsigned int sh = 16u * (d & 1u);
-      rk[r] = (atomicAdd(&W.bins[d >> 1], 1u << sh) >> sh) & 0xFFFFu;
-    }
+    const bool in = lane + 64 * r < ni;
+    const unsigned int d = in ? (kr[r] >> 2) >> dsh : 2u * (unsigned int)lane;
+    const unsigned int sh = 16u * (d & 1u);
+    rk[r] = (atomicAdd(&W.bins[d >> 1], in ? 1u << sh : 0u) >> sh) & 0xFFFFu;
   }
   wave_sync();
   // exclusive scan of the sub-bin counters (lane order = sub-bin order)
@@ -821,14 +828,26 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   }
   wave_sync();
   unsigned int fix = 0;  // bit r: the record of round r is the second one of its sub-bin
+  constexpr int G = IPL < 4 ? IPL : 4;  // rounds placed together (bounds the live registers)
 #pragma unroll
-  for (int r = 0; r < IPL; ++r) {
-    if (lane + 64 * r < ni) {
-      const unsigned int d = (kr[r] >> 2) >> dsh;
-      const unsigned int pos = ((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu) + rk[r];
-      W.key[pos] = kr[r];
-      W.end[pos] = er[r];
-      if (rk[r] == 1) fix |= 1u << r;
+  for (int r0 = 0; r0 < IPL; r0 += G) {
+    unsigned int pos[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {  // the reads of a group first (past the bucket: word `lane`)
+      const bool in = lane + 64 * (r0 + u) < ni;
+      const unsigned int d = in ? (kr[r0 + u] >> 2) >> dsh : 2u * (unsigned int)lane;
+      pos[u] = ((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu) + rk[r0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      // a position past the bucket stores to its own index (>= ni): never
+      // read as a record, and no branch around the stores (distinct addresses)
+      const int r = r0 + u;
+      const bool in = lane + 64 * r < ni;
+      const unsigned int q = in ? pos[u] : (unsigned int)(lane + 64 * r);
+      W.key[q] = kr[r];
+      W.end[q] = er[r];
+      fix |= (in && rk[r] == 1) ? 1u << r : 0u;
     }
   }
   wave_sync();
