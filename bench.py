@@ -11,8 +11,9 @@ Default workload: 256 host ranks x 256 devices x 4 streams, 10^8 device
 records plus 2.5x10^7 host records (2.0 GB of int64 start/end), host-idle
 fraction 0.1-0.4 per rank, 64 regions (the whole span and 63 tiles of it).
 
-Prints one JSON line. Extra legs (batched traces, serving, stream
-concurrency, the live collector on its test application) are reported as sub-objects of the same
+Prints one JSON line. Extra legs (regions entered repeatedly, batched
+traces, serving, stream concurrency, the live collector on its test
+application) are reported as sub-objects of the same
 line; the CPU baseline times the oracle on a bounded sample of the same
 workload.
 """
@@ -196,6 +197,62 @@ def bench_batched(hp, traces, steps, warmup, tune_cache=None):
     return {"traces": len(traces), "events": n_events, "segments": segs, "ms_per_step": round(dt * 1e3, 3),
             "events_per_s": n_events / dt,
             "tuning": {"bucket_target": tun.bucket_target, "bucket_cap": tun.bucket_cap, "tile_elems": tun.tile_elems}}
+
+
+def entered_regions(trace, n_regions=16, entries=32, seed=1007):
+    """Regions entered repeatedly, each resource on its own clock: region q
+    gives every resource `entries` intervals, one in each of `entries` equal
+    windows of the span, at a per-resource offset and length."""
+    rng = np.random.default_rng(seed)
+    lo, hi = trace.info["t0"], trace.info["t_end"]
+    w = (hi - lo) // entries
+    R = trace.n_hosts + trace.n_devices
+    out = []
+    for q in range(n_regions):
+        off = rng.integers(0, w // 4, size=(R, 1)) + q * (w // (4 * n_regions))
+        ln = rng.integers(w // 4, w // 2, size=(R, 1))
+        a = lo + np.arange(entries)[None, :] * w + off
+        res = np.repeat(np.arange(R), entries)
+        out.append(list(zip(res.tolist(), a.ravel().tolist(), (a + ln).ravel().tolist())))
+    return out
+
+
+def entered_regions_leg(hp, trace, reps=20):
+    """Region evaluation alone (the merged lists already built): the 64 plain
+    regions of the workload, then regions entered repeatedly (every resource
+    32 times per region, 16 regions)."""
+    import torch
+    regions = entered_regions(trace)
+    res = {}
+    for name, multi in (("plain", False), ("entered", True)):
+        s = upload_session(hp, trace) if not multi else None
+        if multi:
+            s = hp.hpop_session_create(trace.n_hosts, trace.n_devices)
+            dev = [(c.resource, c.kind, torch.from_numpy(c.start).cuda(), torch.from_numpy(c.end).cuda())
+                   for c in trace.chunks]
+            torch.cuda.synchronize()
+            hp.hpop_add_events_multi(s, dev, hp.HPOP_MEM_DEVICE)
+            hp.hpop_session_synchronize(s)
+            del dev
+            for ivls in regions:
+                hp.hpop_region_define_multi(s, ivls)
+        try:
+            hp.hpop_session_set_tuning(s, 256, 2048, 2048)
+            hp.hpop_metrics_compute_all(s)  # build once
+            hp.hpop_metrics_compute_all(s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                hp.hpop_metrics_compute_all(s)  # nothing changed: the region kernels only
+            torch.cuda.synchronize()
+            res[name] = (time.perf_counter() - t0) / reps
+        finally:
+            hp.hpop_session_destroy(s)
+    n_ivl = sum(len(r) for r in regions)
+    return {"plain_regions": len(trace.regions), "plain_ms_per_pass": round(res["plain"] * 1e3, 4),
+            "entered_regions": len(regions), "intervals": n_ivl,
+            "entered_ms_per_pass": round(res["entered"] * 1e3, 4),
+            "intervals_per_s": n_ivl / res["entered"]}
 
 
 def streams_leg(hp, steps, warmup, n_devices=256, streams=4, per_device=100_000, n_regions=16, seed=1006):
@@ -500,6 +557,7 @@ def main():
     ap.add_argument("--serving-queries", type=int, default=400)
     ap.add_argument("--serving-lambdas", default="2000,10000")
     ap.add_argument("--serving-host-lambdas", default="2000", help="runs with payloads in host memory")
+    ap.add_argument("--no-entered", action="store_true", help="skip the regions-entered-repeatedly leg")
     ap.add_argument("--no-streams", action="store_true")
     ap.add_argument("--streams-only", action="store_true", help="run only the stream concurrency leg")
     ap.add_argument("--no-collector", action="store_true")
@@ -576,6 +634,10 @@ def main():
         log("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(trace)
         log("cpu baseline: %s" % out["cpu_baseline"])
+    if not args.no_entered:
+        log("regions entered repeatedly")
+        out["entered_regions"] = entered_regions_leg(hp, trace)
+        log("entered regions: %s" % out["entered_regions"])
     del trace
     if not args.no_batched and args.batched_traces > 0:
         log("batched leg: generating %d traces" % args.batched_traces)
