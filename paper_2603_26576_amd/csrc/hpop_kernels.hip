@@ -130,12 +130,21 @@ __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   const long long end = min((long long)cd.count, base + p.tile_elems);
   int bk[IPT];
   int bmin = INT_MAX, bmax = -1;
+  // the loads of all rounds first, from positions clamped into the tile
+  long long svs[IPT], evs[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const long long i = base + threadIdx.x + (long long)k * THREADS;
+    const long long ic = i < end ? i : end - 1;
+    svs[k] = cd.s[ic];
+    evs[k] = cd.e[ic];
+  }
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     const long long i = base + threadIdx.x + (long long)k * THREADS;
     bk[k] = -1;
     if (i < end) {
-      const long long s = cd.s[i], e = cd.e[i];
+      const long long s = svs[k], e = evs[k];
       if (rec_valid(s, e) && s < e) {
         bk[k] = bucket_of(s, g);
         bmin = min(bmin, bk[k]);
@@ -266,6 +275,17 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   bool nr[IPT];
   unsigned int kx[IPT], ex[IPT];
   int bmin = INT_MAX, bmax = -1;
+  // the loads of all rounds first, from positions clamped into the tile
+  // (base < end): they issue back to back instead of one masked block (and
+  // one wait) per round
+  long long svs[IPT], evs[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const long long i = base + threadIdx.x + (long long)k * THREADS;
+    const long long ic = i < end ? i : end - 1;
+    svs[k] = cd.s[ic];
+    evs[k] = cd.e[ic];
+  }
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     const long long i = base + threadIdx.x + (long long)k * THREADS;
@@ -274,7 +294,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
     kx[k] = 0;
     ex[k] = 0;
     if (i < end) {
-      const long long sv = cd.s[i], ev = cd.e[i];
+      const long long sv = svs[k], ev = evs[k];
       if (!rec_valid(sv, ev)) {
         // first bad record of the build: chunk << 40 | index (rare path)
         atomicMin(p.err, ((unsigned long long)cd.chunk_id << 40) | (unsigned long long)i);
