@@ -444,8 +444,8 @@ def cpu_baseline(trace, target_s=12.0):
 CALIB_BYTES = 1 << 30  # plain copy of 1 GiB: reads 1 GiB, writes 1 GiB
 
 
-def calibrate_copy(reps=5):
-    """A plain device copy of known size, for scaling the HBM byte counters."""
+def timed_copy(reps=5):
+    """ms per plain device copy of CALIB_BYTES (reads and writes that many bytes)."""
     import torch
     a = torch.ones(CALIB_BYTES // 8, dtype=torch.int64, device="cuda")
     b = torch.empty_like(a)
@@ -458,6 +458,14 @@ def calibrate_copy(reps=5):
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return ms
+
+
+def calibrate_copy(reps=5):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    ms = timed_copy(reps)
     print(json.dumps({"calibration_copy_bytes": CALIB_BYTES, "reps": reps, "ms_per_copy": round(ms, 4),
                       "read_plus_write_GBs": round(2 * CALIB_BYTES / (ms * 1e-3) / 1e9, 1)}))
 
@@ -502,6 +510,66 @@ def import_traffic(kernel, workload, fetch_csv, write_csv, cal_fetch_csv, cal_wr
         for k, v in rec.items():
             fo.write("%s: %s\n" % (k, v))
     print(path, rec)
+    # every build kernel of the same runs: the whole path's bytes per step
+    fr, wr = _pmc_rows(fetch_csv, "FETCH_SIZE"), _pmc_rows(write_csv, "WRITE_SIZE")
+    names = sorted({k.split("(")[0] for k, _ in fr if "hpop::k_" in k})
+    per = {}
+    for n in names:
+        fm, wm = mean_for(fr, n + "("), mean_for(wr, n + "(")
+        per[n] = int((fm or 0) * 1024 * sf + (wm or 0) * 1024 * sw)
+    path = os.path.join(out_dir, "traffic_path_%s.txt" % workload)
+    with open(path, "w") as fo:
+        fo.write("# HBM traffic of every build kernel on the %s workload (bytes per launch; each kernel\n" % workload)
+        fo.write("# runs once per build), from the same FETCH_SIZE and WRITE_SIZE runs and scales\n")
+        fo.write("workload: %s\nsource_hash: %s\n" % (workload, kernel_source_hash()))
+        for n, v in per.items():
+            fo.write("kernel %s: %d\n" % (n, v))
+        fo.write("bytes_per_step: %d\n" % sum(per.values()))
+    print(path, sum(per.values()))
+
+
+def load_path_traffic(workload):
+    """Counter-measured HBM bytes of one build (all build kernels), if taken on
+    the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", "traffic_path_%s.txt" % workload)
+    if not os.path.exists(p):
+        return None
+    d = {}
+    for line in open(p):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return int(d["bytes_per_step"])
+    except (KeyError, ValueError):
+        return None
+
+
+HBM_PEAK_GBS = 8000.0
+ALGO_BYTES_PER_RECORD = 16  # each record's start and end, read once
+
+
+def path_hbm(r, workload):
+    """Whole-path HBM figures of the single-trace leg: counter-measured bytes of a
+    build over the sum of the kernels' stage times, against the chip's peak and
+    a plain copy on the same GPU; and the algorithmic fraction (16 B per record
+    at the measured record rate)."""
+    kernel_ms = sum(r["stage_ms"].values())
+    copy_ms = timed_copy()
+    copy_gbs = 2 * CALIB_BYTES / (copy_ms * 1e-3) / 1e9
+    b = load_path_traffic(workload)
+    out = {"kernel_ms_per_step": round(kernel_ms, 4), "peak_GBps": HBM_PEAK_GBS,
+           "plain_copy_GBps": round(copy_gbs, 1),
+           "algorithmic_bytes_per_record": ALGO_BYTES_PER_RECORD,
+           "algorithmic_frac": round(ALGO_BYTES_PER_RECORD * r["value"] / (HBM_PEAK_GBS * 1e9), 4),
+           "counter_bytes_per_step": b, "achieved_GBps": None, "frac": None, "frac_of_plain_copy": None}
+    if b is not None:
+        ach = b / (kernel_ms * 1e-3) / 1e9
+        out.update({"achieved_GBps": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "frac_of_plain_copy": round(ach / copy_gbs, 4)})
+    return out
 
 
 def run_collect_app(iters, live_every, prefix, with_tool):
@@ -630,6 +698,8 @@ def main():
            "wide_records": r["wide_records"], "buckets": r["buckets"],
            "oversized_buckets": r["oversized_buckets"],
            "tuning": r["tuning"]}
+    out["path_hbm"] = path_hbm(r, args.workload)
+    log("path HBM: %s" % out["path_hbm"])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(trace)
