@@ -74,11 +74,90 @@ def _without_gpu_runtime(out_dir):
     print("child ok", n)
 
 
+def _threads_and_polls(out_dir):
+    """Run in a fresh interpreter: four threads make HIP runtime calls (traced
+    even with no GPU: each returns an error) while this thread polls. Every
+    Useful gap must be disjoint from every offload call, and gaps plus calls
+    must cover [begin, last frontier) exactly: a gap may never be made final
+    over a call that was still running when the poll took its frontier."""
+    import ctypes
+    import threading
+    collect.collect_lib()  # the tool first: the HIP runtime configures it when it starts
+    hip = ctypes.CDLL("libamdhip64.so")
+    n = ctypes.c_int(0)
+    hip.hipGetDeviceCount(ctypes.byref(n))  # starts the runtime, which configures the tool
+    t = time.time() + 10
+    while not collect.hpop_collect_active() and time.time() < t:
+        time.sleep(0.01)
+    assert collect.hpop_collect_active() == 1
+    stop = threading.Event()
+
+    def worker():
+        m = ctypes.c_int(0)
+        while not stop.is_set():
+            for _ in range(50):
+                hip.hipGetDeviceCount(ctypes.byref(m))
+            time.sleep(0.0002)
+
+    ths = [threading.Thread(target=worker) for _ in range(4)]
+    for th in ths:
+        th.start()
+    frontiers = []
+    t_end = time.time() + 0.5
+    while time.time() < t_end:  # half a second of polls, as often as possible
+        frontiers.append(collect.hpop_collect_poll())
+    stop.set()
+    for th in ths:
+        th.join()
+    last = collect.hpop_collect_poll()
+    frontiers.append(last)
+    assert all(a <= b for a, b in zip(frontiers, frontiers[1:]))
+    b = collect.hpop_collect_begin()
+    nu = collect.hpop_collect_count(0, hp.HPOP_HOST_USEFUL)
+    nw = collect.hpop_collect_count(0, hp.HPOP_HOST_OFFLOAD)
+    us, ue = collect.hpop_collect_copy(0, hp.HPOP_HOST_USEFUL, 0, nu)
+    ws, we = collect.hpop_collect_copy(0, hp.HPOP_HOST_OFFLOAD, 0, nw)
+    assert nw > 1000 and nu > 10, (nw, nu)
+    assert np.all(us < ue) and np.all(ws <= we)
+    # the gaps are made final in time order and never overlap each other
+    assert np.all(us[1:] >= ue[:-1])
+    # union of the offload calls, clipped to [b, last)
+    o = np.argsort(ws, kind="stable")
+    cs, ce = [], []
+    for a0, a1 in zip(ws[o], we[o]):
+        a0, a1 = max(int(a0), b), min(int(a1), last)
+        if a0 >= a1:
+            continue
+        if cs and a0 <= ce[-1]:
+            ce[-1] = max(ce[-1], a1)
+        else:
+            cs.append(a0)
+            ce.append(a1)
+    cs, ce = np.array(cs, np.int64), np.array(ce, np.int64)
+    # no gap overlaps a call: a gap [u0, u1) meets the union iff some call starts before u1 and ends after u0
+    k = np.searchsorted(cs, ue, side="left")  # calls starting before each gap's end
+    prev_end = np.where(k > 0, ce[np.maximum(k - 1, 0)], np.iinfo(np.int64).min)
+    assert np.all(prev_end <= us), "a Useful gap overlaps an offload call"
+    # gaps and calls tile [b, last)
+    covered = int((ue - us).sum()) + int((ce - cs).sum())
+    assert covered == last - b, (covered, last - b)
+    print("child ok", nu, nw)
+
+
+def test_concurrent_calls_and_polls(tmp_path):
+    env = dict(os.environ)
+    env["PYTHONPATH"] = os.pathsep.join([ROOT] + [p for p in env.get("PYTHONPATH", "").split(os.pathsep) if p])
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "threads", str(tmp_path)], capture_output=True,
+                       text=True, timeout=180, cwd=ROOT, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr[-3000:]
+    assert "child ok" in r.stdout
+
+
 def test_without_gpu_runtime(tmp_path):
     env = dict(os.environ)
     env["PYTHONPATH"] = os.pathsep.join([ROOT] + [p for p in env.get("PYTHONPATH", "").split(os.pathsep) if p])
-    r = subprocess.run([sys.executable, os.path.abspath(__file__), str(tmp_path)], capture_output=True, text=True,
-                       timeout=120, cwd=ROOT, env=env)
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "single", str(tmp_path)], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT, env=env)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "child ok" in r.stdout
 
@@ -164,4 +243,7 @@ def test_read_trace_rejects_damage(tmp_path):
 
 
 if __name__ == "__main__":
-    _without_gpu_runtime(sys.argv[1])
+    if sys.argv[1] == "threads":
+        _threads_and_polls(sys.argv[2])
+    else:
+        _without_gpu_runtime(sys.argv[2])
