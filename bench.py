@@ -360,10 +360,12 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
             closes = [S["origin"] for S in sess]
             warm_t = []
             for i in range(n_sessions):
-                arr, k, fr = slices(i, warm, cursors[i])
+                # untimed warm-up in the run's own memory space: a host run also
+                # fills the server's page-locked pool (blocks as large as any query)
+                arr, k, fr = slices(i, warm, cursors[i], host)
                 tk = ctypes.c_uint64()
-                rc = lib.hpop_server_submit(srv, sids[i], arr, k, hp.HPOP_MEM_DEVICE, closes[i], max(fr, closes[i] + 1),
-                                            ctypes.byref(tk))
+                rc = lib.hpop_server_submit(srv, sids[i], arr, k, hp.HPOP_MEM_HOST if host else hp.HPOP_MEM_DEVICE,
+                                            closes[i], max(fr, closes[i] + 1), ctypes.byref(tk))
                 assert rc == 0, rc
                 warm_t.append(tk.value)
                 closes[i] = max(fr, closes[i] + 1)
