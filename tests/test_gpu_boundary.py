@@ -1,4 +1,4 @@
-"""Error behaviour of the C ABI (needs the HIP runtime, so it runs on the GPU machine)."""
+"""Error behaviour of the C ABI (needs the HIP runtime and a GPU)."""
 import ctypes
 
 import numpy as np
