@@ -438,9 +438,18 @@ def cpu_baseline(trace, target_s=12.0):
         t0 = time.perf_counter()
         oracle.compute(sub, threads=threads)
         dt = time.perf_counter() - t0
+    # the same oracle on one thread, on a smaller sample of the same shape
+    k1 = max(1, min(n, m, 16))
+    sub1 = subset(k1)
+    t0 = time.perf_counter()
+    oracle.compute(sub1, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": sub.n_events / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
             "sample": "%d host ranks + %d devices of the workload (%d records), all %d regions, %.1f s"
-                      % (sub.n_hosts, sub.n_devices, sub.n_events, len(trace.regions), dt)}
+                      % (sub.n_hosts, sub.n_devices, sub.n_events, len(trace.regions), dt),
+            "single_thread": {"value": sub1.n_events / dt1, "unit": "events/s", "cores": 1,
+                              "sample": "%d host ranks + %d devices (%d records), all %d regions, %.1f s"
+                                        % (sub1.n_hosts, sub1.n_devices, sub1.n_events, len(trace.regions), dt1)}}
 
 
 CALIB_BYTES = 1 << 30  # plain copy of 1 GiB: reads 1 GiB, writes 1 GiB
