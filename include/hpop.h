@@ -108,7 +108,7 @@ typedef struct {
     int32_t bucket_target;  /* records per time bucket of a resource, before rounding the bucket
                                count up to a power of two (16 .. 4096) */
     int32_t bucket_cap;     /* records a bucket may hold for the on-chip sort: 2048 or 4096 */
-    int32_t tile_elems;     /* records per workgroup in the streaming passes: 2048, 4096 or 8192 */
+    int32_t tile_elems;     /* records per workgroup in the streaming passes: 512, 2048, 4096 or 8192 */
     int32_t scatter_slots;  /* records reserved per bucket by the single-pass scatter: 0 = 4 x
                                bucket_target (at most bucket_cap), -1 = always count first
                                (exact two-pass). A bucket that outgrows its slots makes the

@@ -114,14 +114,16 @@ __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
 // ----------------------------------------------------------------------------
 
 // Buckets of one tile usually span a narrow window (records arrive roughly in
-// time order), so per-tile counting uses an LDS window [bmin, bmin + kHistWin).
+// time order), so per-tile counting uses an LDS window [bmin, bmin + HW): kHistWin
+// buckets, or a quarter of the tile's records for tiles of at most kHistWin records.
 // Wider tiles fall back to global atomics per record.
 
 template <int THREADS, int IPT>
 __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   constexpr int NW = THREADS / 64;
+  constexpr int HW = THREADS * IPT <= kHistWin ? THREADS * IPT / 4 : kHistWin;  // LDS bucket window
   __shared__ int s_rng[2][NW];
-  __shared__ unsigned int hist[kHistWin];
+  __shared__ unsigned int hist[HW];
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
@@ -156,12 +158,12 @@ __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   bmax = wave_reduce_i32<OpMaxI>(bmax, -1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
-  for (int i = threadIdx.x; i < kHistWin; i += THREADS) hist[i] = 0;
+  for (int i = threadIdx.x; i < HW; i += THREADS) hist[i] = 0;
   __syncthreads();
   bmin = INT_MAX; bmax = -1;
   for (int w = 0; w < NW; ++w) { bmin = min(bmin, s_rng[0][w]); bmax = max(bmax, s_rng[1][w]); }
   if (bmax < 0) return;  // uniform: no valid record in this tile
-  const bool windowed = bmax - bmin < kHistWin;
+  const bool windowed = bmax - bmin < HW;
   if (windowed) {
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
@@ -257,11 +259,13 @@ __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
 template <int THREADS, int IPT>
 __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   constexpr int NW = THREADS / 64;
+  // LDS bucket window: a quarter of the tile's records for tiles of at most kHistWin records
+  constexpr int HW = THREADS * IPT <= kHistWin ? THREADS * IPT / 4 : kHistWin;
   __shared__ int s_rng[2][NW];
-  __shared__ unsigned long long hist[kHistWin];   // per window bucket: 8 B records | 16 B records << 32
-  __shared__ unsigned long long bbase[kHistWin];  // the same counts placed before this tile
-  __shared__ unsigned long long bmaxe[kHistWin];  // largest end of the tile's records
-  __shared__ long long bunit[kHistWin];           // first unit of the bucket's region
+  __shared__ unsigned long long hist[HW];   // per window bucket: 8 B records | 16 B records << 32
+  __shared__ unsigned long long bbase[HW];  // the same counts placed before this tile
+  __shared__ unsigned long long bmaxe[HW];  // largest end of the tile's records
+  __shared__ long long bunit[HW];           // first unit of the bucket's region
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
@@ -315,7 +319,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long scap = p.slot_cap;
   if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
-  for (int i = threadIdx.x; i < kHistWin; i += THREADS) { hist[i] = 0; bmaxe[i] = 0; }
+  for (int i = threadIdx.x; i < HW; i += THREADS) { hist[i] = 0; bmaxe[i] = 0; }
   __syncthreads();
   bmin = INT_MAX; bmax = -1;
   for (int w = 0; w < NW; ++w) { bmin = min(bmin, s_rng[0][w]); bmax = max(bmax, s_rng[1][w]); }
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
       *(Elem*)(units + ub + ucap - 2 * ((long long)rank + 1)) = el;
     }
   };
-  if (bmax - bmin < kHistWin) {
+  if (bmax - bmin < HW) {
     unsigned int rk[IPT];
     const unsigned long long lt = (1ull << lane) - 1ull;
 #pragma unroll
@@ -1154,6 +1158,7 @@ hipError_t launch_stats(const Plan& p, hipStream_t st) {
 hipError_t launch_hist(const Plan& p, hipStream_t st) {
   if (p.n_tiles == 0) return hipSuccess;
   switch (p.tile_elems) {
+    case 512: hipLaunchKernelGGL((k_hist<128, 4>), dim3((unsigned)p.n_tiles), dim3(128), 0, st, p); break;
     case 2048: hipLaunchKernelGGL((k_hist<512, 4>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
     case 8192: hipLaunchKernelGGL((k_hist<1024, 8>), dim3((unsigned)p.n_tiles), dim3(1024), 0, st, p); break;
     default: hipLaunchKernelGGL((k_hist<512, 8>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
@@ -1171,6 +1176,7 @@ hipError_t launch_scan(const Plan& p, hipStream_t st) {
 hipError_t launch_scatter(const Plan& p, hipStream_t st) {
   if (p.n_tiles == 0) return hipSuccess;
   switch (p.tile_elems) {
+    case 512: hipLaunchKernelGGL((k_scatter<128, 4>), dim3((unsigned)p.n_tiles), dim3(128), 0, st, p); break;
     case 2048: hipLaunchKernelGGL((k_scatter<512, 4>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;
     case 8192: hipLaunchKernelGGL((k_scatter<1024, 8>), dim3((unsigned)p.n_tiles), dim3(1024), 0, st, p); break;
     default: hipLaunchKernelGGL((k_scatter<512, 8>), dim3((unsigned)p.n_tiles), dim3(512), 0, st, p); break;

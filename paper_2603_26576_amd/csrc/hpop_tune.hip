@@ -106,7 +106,7 @@ extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const c
       double best_t = 1e30;
       const int targets[] = {128, 256, 512, 1024};
       const int caps[] = {2048, 4096};
-      const int tiles[] = {2048, 4096, 8192};
+      const int tiles[] = {512, 2048, 4096, 8192};  // 512: traces of many small record batches
       for (int tg : targets)
         for (int cp : caps)
           for (int tl : tiles) {

@@ -74,6 +74,8 @@ def test_device_pointer_input_matches_host_input():
     {"bucket_target": 4096, "bucket_cap": 4096, "tile_elems": 2048},
     {"bucket_target": 256, "scatter_slots": -1},
     {"bucket_target": 64, "scatter_slots": 64},
+    {"bucket_target": 256, "bucket_cap": 2048, "tile_elems": 512},
+    {"bucket_target": 64, "tile_elems": 512, "scatter_slots": -1},
 ])
 def test_tunings_agree(tuning):
     tr = tg.make_trace(22, 4, 4, 8, 20000, 5000, w_range=(0.5, 1.5), regions="nested", n_regions=6)
@@ -308,6 +310,28 @@ def test_invalid_device_record_reported_and_dropped():
         assert_same(engine_results(s, good), oracle.compute(good), "after drop")
     finally:
         hp.hpop_session_destroy(s)
+
+
+def test_batched_small_tiles():
+    """Many traces of small record batches with 512-record tiles (the tiles of
+    the streaming passes, each holding one batch, mostly partly filled)."""
+    rng = np.random.default_rng(61)
+    traces = [tg.make_trace(int(rng.integers(0, 1 << 30)), int(rng.integers(1, 6)), int(rng.integers(1, 6)),
+                            int(rng.integers(1, 5)), int(rng.integers(50, 3000)), int(rng.integers(20, 800)),
+                            regions="nested", n_regions=3) for _ in range(40)]
+    sessions = [new_session(tr, tuning={"bucket_target": 64, "tile_elems": 512})[0] for tr in traces]
+    try:
+        trees = hp.hpop_batch_compute(sessions)
+        k = 0
+        for tr in traces:
+            want = oracle.compute(tr)
+            for g in range(len(tr.regions)):
+                np.testing.assert_array_equal(hp.tree_sums(trees[k]), want["sums"][g])
+                np.testing.assert_array_equal(hp.tree_ratios(trees[k]).view(np.int64), want["ratios"][g].view(np.int64))
+                k += 1
+    finally:
+        for s in sessions:
+            hp.hpop_session_destroy(s)
 
 
 def test_batched_equals_single():
