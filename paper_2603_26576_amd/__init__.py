@@ -310,12 +310,13 @@ def hpop_resource_times(s, region, resource):
 
 
 def hpop_batch_compute(sessions, flags=0):
+    """Trees of every region of every session, in order (a ctypes array)."""
     k = len(sessions)
     arr = (_P * k)(*sessions)
     total = sum(hpop_num_regions(s) for s in sessions)
     out = (hpop_metric_tree * max(1, total))()
     _check(lib().hpop_batch_compute(arr, k, flags, out))
-    return list(out[:total])
+    return out if total else []
 
 
 def hpop_session_get_info(s):
