@@ -109,6 +109,39 @@ __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
   }
 }
 
+// Small tiles (at most 512 records): one wave per tile, four tiles per
+// workgroup, so a lane reduces 8 records instead of a workgroup reducing 2 per
+// thread (traces of many small record batches have mostly partial tiles).
+__global__ __launch_bounds__(256) void k_stats_small(Plan p) {
+  const int lane = threadIdx.x & 63;
+  const long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (tile >= p.n_tiles) return;
+  const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
+  const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
+  const long long end = min((long long)cd.count, base + p.tile_elems);
+  unsigned long long mn = ULLONG_MAX, mxs = 0;
+  long long v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {  // all loads first, from positions clamped into the tile (base < end)
+    const long long i = base + lane + 64 * k;
+    v[k] = cd.s[i < end ? i : end - 1];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const unsigned long long s = (unsigned long long)v[k];
+    if (base + lane + 64 * k < end && s < (unsigned long long)kTimeLimit) {
+      mn = s < mn ? s : mn;
+      mxs = s > mxs ? s : mxs;
+    }
+  }
+  mn = wave_red_minu(mn);
+  mxs = wave_red_maxu(mxs);
+  if (lane == 0 && mn != ULLONG_MAX) {
+    atomicMin(&p.stats[cd.seg].min_s, mn);
+    atomicMax(&p.stats[cd.seg].max_s, mxs);
+  }
+}
+
 // ----------------------------------------------------------------------------
 // hist / scatter: regroup records by time bucket
 // ----------------------------------------------------------------------------
@@ -1151,7 +1184,10 @@ hipError_t launch_reset(const Plan& p, hipStream_t st) {
 
 hipError_t launch_stats(const Plan& p, hipStream_t st) {
   if (p.n_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stats<256>, dim3((unsigned)p.n_tiles), dim3(256), 0, st, p);
+  if (p.tile_elems <= 512)
+    hipLaunchKernelGGL(k_stats_small, dim3((unsigned)((p.n_tiles + 3) / 4)), dim3(256), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_stats<256>, dim3((unsigned)p.n_tiles), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
