@@ -508,6 +508,7 @@ __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
     }
 #pragma unroll
     for (int j = 0; j < kSegRows; ++j) {
+      if (c0 + 64 * j >= nb) break;  // wave-uniform: rows past the segment change nothing
       const long long b = c0 + 64 * j + lane;
       long long v[3];
       v[0] = m[j][0] ? (long long)m[j][0] : LLONG_MIN;
@@ -546,6 +547,7 @@ __global__ __launch_bounds__(THREADS) void k_base(Plan p) {
     }
 #pragma unroll
     for (int j = 0; j < kSegRows; ++j) {
+      if (c0 + 64 * j >= nb) break;  // wave-uniform: rows past the segment add nothing
       const long long b = c0 + 64 * j + lane;
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
