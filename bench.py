@@ -268,19 +268,26 @@ def entered_regions_leg(hp, trace, reps=20):
             "intervals_per_s": n_ivl / res["entered"]}
 
 
+def streams_workload(n_devices=256, streams=4, per_device=100_000, n_regions=16, seed=1006):
+    """Stream-tagged kernel records of every device and the regions the
+    streams leg reduces: the whole span, then n_regions - 1 tiles of it."""
+    import tracegen as tg
+    n_streams, chunks = tg.stream_kernels(seed, n_devices, streams, per_device)
+    lo = min(int(c[2].min()) for c in chunks)
+    hi = max(int(c[3].max()) for c in chunks)
+    cuts = np.linspace(lo, hi, n_regions).astype(np.int64)
+    regions = [(lo, hi)] + [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])]
+    return n_streams, chunks, regions
+
+
 def streams_leg(hp, steps, warmup, n_devices=256, streams=4, per_device=100_000, n_regions=16, seed=1006):
     """Stream concurrency of every device (hpop_stream_metrics): kernel records
     tagged by stream, in the launch-group shape of the main workload's
     devices, resident in HBM; each step rebuilds the per-stream and per-device
     merged lists and reduces all regions (the whole span and tiles of it)."""
     import torch
-    import tracegen as tg
-    n_streams, chunks = tg.stream_kernels(seed, n_devices, streams, per_device)
+    n_streams, chunks, regions = streams_workload(n_devices, streams, per_device, n_regions, seed)
     n_rec = sum(int(c[2].size) for c in chunks)
-    lo = min(int(c[2].min()) for c in chunks)
-    hi = max(int(c[3].max()) for c in chunks)
-    cuts = np.linspace(lo, hi, n_regions).astype(np.int64)
-    regions = [(lo, hi)] + [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])]
     s = hp.hpop_session_create(0, n_devices)
     try:
         hp.hpop_session_set_tuning(s, 256, 2048, 2048)
