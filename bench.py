@@ -421,7 +421,11 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
                         "max_us": round(float(lat_us[-1]), 1),
                         "mean_batch": round((st.mean_batch * st.device_steps - base.mean_batch * base.device_steps)
                                             / steps_run, 2),
-                        "busy_retries": busy})
+                        "busy_retries": busy,
+                        # over the server's life, warm-up included
+                        "max_submit_us": round(st.max_submit_us, 1), "max_step_us": round(st.max_step_us, 1),
+                        "pinned_blocks": int(st.pinned_blocks),
+                        "max_pinned_alloc_us": round(st.max_pinned_alloc_us, 1)})
         log("serving lambda=%d %s: %s" % (lam, "host" if host else "device", results[-1]))
     return {"sessions": n_sessions, "ranks": ranks, "devices": ranks, "streams": streams,
             "warm_events_per_session": warm,
@@ -654,8 +658,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="profiling aid: run only the serving leg")
     ap.add_argument("--serving-queries", type=int, default=400)
-    ap.add_argument("--serving-lambdas", default="2000,10000")
-    ap.add_argument("--serving-host-lambdas", default="2000", help="runs with payloads in host memory")
+    ap.add_argument("--serving-lambdas", default="2000,5000,10000,20000")
+    ap.add_argument("--serving-host-lambdas", default="2000,5000", help="runs with payloads in host memory")
     ap.add_argument("--no-entered", action="store_true", help="skip the regions-entered-repeatedly leg")
     ap.add_argument("--no-streams", action="store_true")
     ap.add_argument("--streams-only", action="store_true", help="run only the stream concurrency leg")

@@ -321,6 +321,10 @@ typedef struct {
     int64_t device_steps;       /* batched device steps run */
     double mean_batch;          /* mean queries per device step */
     double p50_us, p99_us, max_us;  /* submit -> result latency of finished queries */
+    double max_submit_us;       /* longest hpop_server_submit (host payloads: includes their copy) */
+    double max_step_us;         /* longest device step of the worker, admission to results */
+    int64_t pinned_blocks;      /* page-locked blocks allocated for host payloads */
+    double max_pinned_alloc_us; /* longest single allocation of such a block */
 } hpop_server_stats;
 
 hpop_status hpop_server_create(const hpop_server_config* cfg, hpop_server** out);

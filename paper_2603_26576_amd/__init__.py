@@ -86,7 +86,8 @@ class hpop_server_config(ctypes.Structure):
 class hpop_server_stats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("events", ctypes.c_int64), ("device_steps", ctypes.c_int64),
                 ("mean_batch", ctypes.c_double), ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
-                ("max_us", ctypes.c_double)]
+                ("max_us", ctypes.c_double), ("max_submit_us", ctypes.c_double), ("max_step_us", ctypes.c_double),
+                ("pinned_blocks", ctypes.c_int64), ("max_pinned_alloc_us", ctypes.c_double)]
 
 
 class hpop_replay_query(ctypes.Structure):

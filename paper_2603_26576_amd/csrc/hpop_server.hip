@@ -351,6 +351,7 @@ struct PinnedPool {
   std::mutex mu;
   std::multimap<size_t, void*> free_blocks;
   std::vector<std::pair<void*, size_t>> all;
+  double max_alloc_us = 0.0;  // longest hipHostMalloc so far
   void* get(size_t bytes, size_t& got) {
     std::lock_guard<std::mutex> g(mu);
     auto it = free_blocks.lower_bound(bytes);
@@ -363,10 +364,13 @@ struct PinnedPool {
     size_t b = 4096;
     while (b < bytes) b <<= 1;
     void* p = nullptr;
+    const auto t = std::chrono::steady_clock::now();
     if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
       return nullptr;
     }
+    max_alloc_us = std::max(max_alloc_us,
+                            std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t).count());
     all.push_back({p, b});
     got = b;
     return p;
@@ -444,6 +448,7 @@ struct hpop_server {
   // statistics
   std::vector<double> lat_us;
   long long completed = 0, events = 0, steps = 0, batched = 0;
+  double max_submit_us = 0.0, max_step_us = 0.0;
 };
 
 namespace {
@@ -766,6 +771,7 @@ void worker_loop(hpop_server* S) {
       it = S->queue.erase(it);
     }
     lk.unlock();
+    const auto t_admit = std::chrono::steady_clock::now();
     std::string err;
     hpop_status st;
     {
@@ -781,6 +787,7 @@ void worker_loop(hpop_server* S) {
     lk.lock();
     ++S->steps;
     S->batched += (long long)batch.size();
+    S->max_step_us = std::max(S->max_step_us, std::chrono::duration<double, std::micro>(now - t_admit).count());
     for (Query* Q : batch) {
       if (st != HPOP_OK) {
         Q->status = st;
@@ -932,6 +939,7 @@ hpop_status hpop_server_submit(hpop_server* S, int32_t sid, const hpop_event_chu
     if (!S || !out_ticket || n_chunks < 0 || (n_chunks > 0 && !chunks)) return srv_fail(S, HPOP_E_ARG, "bad arguments");
     if (mem_space != HPOP_MEM_HOST && mem_space != HPOP_MEM_DEVICE) return srv_fail(S, HPOP_E_ARG, "bad mem_space");
     if (!(t0 < t1)) return srv_fail(S, HPOP_E_REGION, "region needs t0 < t1");
+    const auto t_enter = std::chrono::steady_clock::now();
     int32_t nh, nd;
     {
       std::lock_guard<std::mutex> g(S->mu);
@@ -1011,6 +1019,8 @@ hpop_status hpop_server_submit(hpop_server* S, int32_t sid, const hpop_event_chu
         return HPOP_E_BUSY;
       }
       Q->ticket = S->next_ticket++;
+      S->max_submit_us =
+          std::max(S->max_submit_us, std::chrono::duration<double, std::micro>(Q->submitted - t_enter).count());
       S->inflight_bytes += total * 16;
       S->tickets[Q->ticket] = Q;
       S->queue.push_back(Q);
@@ -1044,6 +1054,13 @@ hpop_status hpop_server_get_stats(hpop_server* S, hpop_server_stats* out) {
   out->p50_us = pct(0.50);
   out->p99_us = pct(0.99);
   out->max_us = v.empty() ? 0.0 : v.back();
+  out->max_submit_us = S->max_submit_us;
+  out->max_step_us = S->max_step_us;
+  {
+    std::lock_guard<std::mutex> pg(S->pinned.mu);
+    out->pinned_blocks = (int64_t)S->pinned.all.size();
+    out->max_pinned_alloc_us = S->pinned.max_alloc_us;
+  }
   return HPOP_OK;
 }
 
