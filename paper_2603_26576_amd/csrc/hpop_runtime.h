@@ -98,6 +98,7 @@ struct Engine {
   // timing
   bool exact_forced = false;  // a bucket outgrew its scatter slots: use exact offsets
   std::vector<unsigned long long> forced_versions;
+  long long forced_tuning = 0;  // tuning_key of the plan whose slots overflowed
   std::vector<hipEvent_t> events;
   std::vector<const char*> mark_names;
   int n_marks = 0;

@@ -504,8 +504,9 @@ hpop_status Engine::run(hpop_session* const* ss, int k, uint32_t flags, hpop_met
   }
   const bool build = !same || (flags & HPOP_FORCE_REBUILD);
   if (!same && exact_forced) {
-    // new records or another session set: try the single-pass scatter again
-    bool changed = (int)forced_versions.size() != k;
+    // new records, another session set or another tuning (slots follow the
+    // bucket size): try the single-pass scatter again
+    bool changed = (int)forced_versions.size() != k || forced_tuning != tuning_key(ss[0]->tuning);
     for (int i = 0; !changed && i < k; ++i) changed = forced_versions[i] != ss[i]->version;
     if (changed) {
       exact_forced = false;
@@ -583,6 +584,7 @@ hpop_status Engine::run(hpop_session* const* ss, int k, uint32_t flags, hpop_met
     exact_forced = true;
     forced_versions.clear();
     for (int i = 0; i < k; ++i) forced_versions.push_back(ss[i]->version);
+    forced_tuning = tuning_key(ss[0]->tuning);
     key_sessions.clear();
     return run(ss, k, flags | HPOP_FORCE_REBUILD, out, timing, err);
   }

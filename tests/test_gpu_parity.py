@@ -82,6 +82,37 @@ def test_tunings_agree(tuning):
     check(tr, tuning=tuning)
 
 
+def test_slot_overflow_does_not_outlive_its_tuning():
+    """A tuning whose scatter slots overflow falls back to exact offsets
+    (k_hist); a later tuning with large enough slots takes the single-pass
+    scatter again, single session and batched, with the same results."""
+    tr = tg.make_trace(23, 3, 3, 4, 20000, 5000, w_range=(0.5, 1.5), regions="nested", n_regions=4)
+    want = oracle.compute(tr)
+    s, keep = new_session(tr)
+    s2, keep2 = new_session(tr)
+    try:
+        for ss in ([s], [s, s2]):
+            for x in ss:
+                hp.hpop_session_enable_timing(x, 1)
+            for tuning, exact in (({"bucket_target": 256, "scatter_slots": 64}, True),
+                                  ({"bucket_target": 256}, False)):
+                print("case: sessions=%d tuning=%s" % (len(ss), tuning), flush=True)
+                for x in ss:
+                    hp.hpop_session_set_tuning(x, **tuning)
+                if len(ss) == 1:
+                    got = engine_results(s, tr, hp.HPOP_FORCE_REBUILD)
+                    assert_same(got, want, str(tuning))
+                else:
+                    trees = hp.hpop_batch_compute(ss, hp.HPOP_FORCE_REBUILD)
+                    for g, t in enumerate(trees):
+                        np.testing.assert_array_equal(hp.tree_sums(t), want["sums"][g % len(tr.regions)])
+                names = [n for n, _ in hp.hpop_session_stage_times(s)]
+                assert ("hist" in names) == exact, (tuning, names)
+    finally:
+        hp.hpop_session_destroy(s)
+        hp.hpop_session_destroy(s2)
+
+
 def test_oversized_bucket_slow_path():
     """Most starts packed in a few ns with one far outlier: one bucket gets
     every record and must take the global-memory sort path."""
