@@ -34,6 +34,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -386,6 +387,50 @@ struct PinnedPool {
     free_blocks.clear();
   }
 };
+
+// One contiguous copy of a host payload into its page-locked block.
+struct CopySpan {
+  char* dst;
+  const char* src;
+  size_t bytes;
+};
+
+// Copies the spans; payloads of kParallelCopyBytes and more are split in
+// equal byte ranges over a few threads (one copying thread reaches only
+// part of the host's memory bandwidth), the calling thread taking one.
+constexpr size_t kParallelCopyBytes = size_t(4) << 20;
+constexpr int kCopyThreads = 4;
+
+void copy_range(const std::vector<CopySpan>& spans, size_t lo, size_t hi) {
+  size_t base = 0;
+  for (const CopySpan& c : spans) {
+    const size_t a = std::max(lo, base), b = std::min(hi, base + c.bytes);
+    if (a < b) memcpy(c.dst + (a - base), c.src + (a - base), b - a);
+    base += c.bytes;
+    if (base >= hi) break;
+  }
+}
+
+void copy_spans(const std::vector<CopySpan>& spans, size_t total) {
+  if (total < kParallelCopyBytes) {
+    copy_range(spans, 0, total);
+    return;
+  }
+  std::vector<std::thread> th;
+  const size_t part = (total + kCopyThreads - 1) / kCopyThreads;
+  try {
+    for (int t = 1; t < kCopyThreads; ++t) {
+      const size_t lo = std::min(total, t * part), hi = std::min(total, (t + 1) * part);
+      th.emplace_back(copy_range, std::cref(spans), lo, hi);
+    }
+  } catch (const std::system_error&) {
+    // no thread available: the calling thread copies what no thread took
+    const size_t done_from = (th.size() + 1) * part;
+    copy_range(spans, std::min(total, done_from), total);
+  }
+  copy_range(spans, 0, std::min(total, part));
+  for (std::thread& x : th) x.join();
+}
 
 struct Query {
   uint64_t ticket = 0;
@@ -993,18 +1038,20 @@ hpop_status hpop_server_submit(hpop_server* S, int32_t sid, const hpop_event_chu
         }
       }
       Q->host_words = (size_t)2 * total;
+      std::vector<CopySpan> spans;
       long long o = 0;
       for (int32_t i = 0; i < n_chunks; ++i) {
         const hpop_event_chunk& c = chunks[i];
         if (c.count == 0) continue;
-        memcpy(Q->host + o, c.start, c.count * 8);
-        memcpy(Q->host + o + c.count, c.end, c.count * 8);
+        spans.push_back({(char*)(Q->host + o), (const char*)c.start, (size_t)c.count * 8});
+        spans.push_back({(char*)(Q->host + o + c.count), (const char*)c.end, (size_t)c.count * 8});
         hpop_event_chunk cc = c;
         cc.start = Q->host + o;
         cc.end = Q->host + o + c.count;
         Q->chunks.push_back(cc);
         o += 2 * c.count;
       }
+      copy_spans(spans, (size_t)total * 16);
     } else {
       Q->chunks.assign(chunks, chunks + n_chunks);
     }

@@ -133,6 +133,27 @@ def test_large_batches_take_the_global_sort_path():
         hp.hpop_server_destroy(srv)
 
 
+def test_large_host_payloads_copied_in_parts():
+    """Host payloads of several MB (copied into page-locked memory by more
+    than one thread) give the oracle's trees, query after query."""
+    ranks = 2
+    plan = make_queries(29, 1, ranks, 3, mean_events=400000, p_early=0.5)
+    srv = hp.hpop_server_create(max_sessions=1, max_inflight=4)
+    try:
+        origin, qs = plan[0]
+        sid = hp.hpop_server_open_session(srv, ranks, ranks, origin)
+        for q, (chunks, t0, t1) in enumerate(qs):
+            n = sum(len(c.start) for c in chunks)
+            print("case: query %d, %d records (%.1f MB)" % (q, n, n * 16 / 2 ** 20), flush=True)
+            t = hp.hpop_server_submit(srv, sid, as_payload(chunks, False), hp.HPOP_MEM_HOST, t0, t1)
+            reg, glob = hp.hpop_server_wait(srv, t)
+            want = expected(ranks, origin, qs, q)
+            check_tree(reg, want, 0, "query %d region" % q)
+            check_tree(glob, want, 1, "query %d global" % q)
+    finally:
+        hp.hpop_server_destroy(srv)
+
+
 @pytest.mark.parametrize("device", [True, False])
 def test_bad_record_rejected_and_state_unchanged(device):
     import torch
