@@ -398,7 +398,7 @@ struct CopySpan {
 // Copies the spans; payloads of kParallelCopyBytes and more are split in
 // equal byte ranges over a few threads (one copying thread reaches only
 // part of the host's memory bandwidth), the calling thread taking one.
-constexpr size_t kParallelCopyBytes = size_t(4) << 20;
+constexpr size_t kParallelCopyBytes = size_t(1) << 20;
 constexpr int kCopyThreads = 4;
 
 void copy_range(const std::vector<CopySpan>& spans, size_t lo, size_t hi) {
