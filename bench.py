@@ -275,8 +275,9 @@ def streams_workload(n_devices=256, streams=4, per_device=100_000, n_regions=16,
     n_streams, chunks = tg.stream_kernels(seed, n_devices, streams, per_device)
     lo = min(int(c[2].min()) for c in chunks)
     hi = max(int(c[3].max()) for c in chunks)
-    cuts = np.linspace(lo, hi, n_regions).astype(np.int64)
-    regions = [(lo, hi)] + [(int(a), int(b)) for a, b in zip(cuts[:-1], cuts[1:])]
+    # exact integer cuts (float64 cannot hold ns timestamps near 1.7e18)
+    cuts = [lo + (hi - lo) * i // (n_regions - 1) for i in range(n_regions)]
+    regions = [(lo, hi)] + list(zip(cuts[:-1], cuts[1:]))
     return n_streams, chunks, regions
 
 

@@ -1,0 +1,75 @@
+"""Host-side pieces of bench.py, CPU only: the one-GPU refusal, the oracle
+baseline object, the traffic records' source check, and the synthetic
+workloads of the regions-entered and stream legs (their shape is what the
+oracle and the engine assume)."""
+import os
+import shutil
+import subprocess
+import sys
+
+import numpy as np
+
+import bench
+import tracegen as tg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout + r.stderr
+
+
+def test_cpu_baseline_object():
+    tr = tg.small()
+    out = bench.cpu_baseline(tr, target_s=0.3)
+    assert out["kind"] == "oracle" and out["unit"] == "events/s"
+    assert out["cores"] >= 1 and out["value"] > 0 and isinstance(out["sample"], str)
+    one = out["single_thread"]
+    assert one["cores"] == 1 and one["value"] > 0
+
+
+def test_traffic_records_are_tied_to_the_kernel_sources(tmp_path, monkeypatch):
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
+    for b in (bench.load_traffic("merge_wave", "large"), bench.load_path_traffic("large")):
+        assert b is None or b > 0
+    # a record taken on other sources is not used
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    shutil.copy(os.path.join(ROOT, "profiles", "traffic_merge_wave_large.txt"), prof)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.load_traffic("merge_wave", "large") is None
+    assert bench.load_traffic("merge_wave", "absent") is None
+
+
+def test_entered_regions_are_disjoint_per_resource():
+    tr = tg.make_trace(5, 3, 2, 2, 2000, 500, regions="tiles", n_regions=2)
+    R = tr.n_hosts + tr.n_devices
+    regions = bench.entered_regions(tr, n_regions=4, entries=8)
+    assert len(regions) == 4
+    lo, hi = tr.info["t0"], tr.info["t_end"]
+    for ivls in regions:
+        assert len(ivls) == 8 * R
+        per = {}
+        for r, a, b in ivls:
+            assert 0 <= r < R and lo <= a < b <= hi
+            per.setdefault(r, []).append((a, b))
+        for lst in per.values():
+            lst.sort()
+            assert all(b0 <= a1 for (_, b0), (a1, _) in zip(lst, lst[1:]))
+
+
+def test_streams_workload_tiles_its_span():
+    n_streams, chunks, regions = bench.streams_workload(n_devices=3, streams=2, per_device=500, n_regions=5)
+    assert n_streams == [2, 2, 2]
+    lo = min(int(c[2].min()) for c in chunks)
+    hi = max(int(c[3].max()) for c in chunks)
+    assert regions[0] == (lo, hi) and len(regions) == 5
+    tiles = np.array(regions[1:])
+    assert tiles[0, 0] == lo and tiles[-1, 1] == hi and (tiles[1:, 0] == tiles[:-1, 1]).all()
+    for g, k, s, e in chunks:
+        assert 0 <= g < 3 and 0 <= k < 2 and (s <= e).all()
