@@ -316,6 +316,150 @@ def streams_leg(hp, steps, warmup, n_devices=256, streams=4, per_device=100_000,
             "stream_eff": trees[0].stream_eff, "mean_active": trees[0].mean_active}
 
 
+def serving_workload(n_queries, seed=1005, n_sessions=32, ranks=16, streams=4, warm=1_000_000, device=True):
+    """Record streams of the serving workload: per session one trace of
+    `ranks` hosts and devices, long enough for its warm-up slice and every
+    query that targets it; query sizes log-uniform 10^4-10^6 records, owners
+    uniform over the sessions. With device=True each chunk is also uploaded
+    to the GPU (device-resident payloads)."""
+    import tracegen as tg
+    rng = np.random.default_rng(seed)
+    sizes = np.rint(10 ** rng.uniform(4, 6, size=n_queries)).astype(np.int64)
+    owner = rng.integers(0, n_sessions, size=n_queries)
+    kids = np.random.SeedSequence(seed).spawn(n_sessions)
+    sess = []
+    for i in range(n_sessions):
+        need = warm + int(sizes[owner == i].sum())
+        per_res = max(4, need // (2 * ranks))
+        tr = tg.make_trace(0, ranks, ranks, streams, (8 * per_res) // 5, (2 * per_res) // 5 + 3,
+                           w_range=(0.8, 1.2), seed_seq=kids[i])
+        chunks = []
+        for c in tr.chunks:
+            if device:
+                import torch
+                ds, de = torch.from_numpy(c.start).cuda(), torch.from_numpy(c.end).cuda()
+            else:
+                ds = de = None
+            chunks.append((c.resource, c.kind, ds, de, np.maximum.accumulate(c.end), c.start, c.end))
+        sess.append({"origin": tr.info["t0"], "chunks": chunks, "total": tr.n_events})
+    if device:
+        import torch
+        torch.cuda.synchronize()
+    return {"rng": rng, "sizes": sizes, "owner": owner, "sess": sess, "n_sessions": n_sessions, "ranks": ranks,
+            "streams": streams, "warm": warm}
+
+
+def serving_slices(hp, W, sidx, n_rec, cursor, host):
+    """hpop_event_chunk array for the next n_rec records of a session (spread
+    over its chunks in proportion), the number of chunks used and the largest
+    end among them; advances cursor."""
+    S = W["sess"][sidx]
+    arr = (hp.hpop_event_chunk * len(S["chunks"]))()
+    frontier = S["origin"]
+    k = 0
+    for j, (r, kind, st, en, pmax, hst, hen) in enumerate(S["chunks"]):
+        ln = hst.size
+        a = cursor[j]
+        b = min(ln, a + max(1, int(round(n_rec * ln / S["total"]))))
+        if b > a:
+            ps = hst.ctypes.data if host else st.data_ptr()
+            pe = hen.ctypes.data if host else en.data_ptr()
+            arr[k] = hp.hpop_event_chunk(r, kind, ps + 8 * a, pe + 8 * a, b - a)
+            k += 1
+            frontier = max(frontier, int(pmax[b - 1]))
+        cursor[j] = b
+    return arr, k, frontier
+
+
+def serving_run(hp, W, lam, host, keep=False):
+    """One Poisson run of the serving workload at `lam` queries/s: a fresh
+    server, every session warmed with its first W["warm"] records (untimed, in
+    the run's own memory space), then the queries replayed natively. With
+    keep=True also returns, per warm-up and per query, (session, t0, t1,
+    record count per chunk so far) and the trees the server answered."""
+    import ctypes
+    lib = hp.lib()
+    n_sessions, ranks = W["n_sessions"], W["ranks"]
+    sizes, owner = W["sizes"], W["owner"]
+    n_queries = int(sizes.size)
+    mem = hp.HPOP_MEM_HOST if host else hp.HPOP_MEM_DEVICE
+    srv = hp.hpop_server_create(max_sessions=n_sessions, max_inflight=n_sessions, queue_capacity=1 << 16,
+                                mem_budget_bytes=64 << 30)
+    kept = {"warm": [], "queries": []}
+    try:
+        sids = [hp.hpop_server_open_session(srv, ranks, ranks, S["origin"]) for S in W["sess"]]
+        cursors = [[0] * len(S["chunks"]) for S in W["sess"]]
+        closes = [S["origin"] for S in W["sess"]]
+        warm_t = []
+        for i in range(n_sessions):
+            # a host run also fills the server's page-locked pool here (blocks as large as any query)
+            arr, k, fr = serving_slices(hp, W, i, W["warm"], cursors[i], host)
+            tk = ctypes.c_uint64()
+            t1 = max(fr, closes[i] + 1)
+            rc = lib.hpop_server_submit(srv, sids[i], arr, k, mem, closes[i], t1, ctypes.byref(tk))
+            if rc != hp.HPOP_OK:
+                raise hp.HpopError(rc, "warm-up submission of session %d" % i)
+            warm_t.append(tk.value)
+            kept["warm"].append((i, closes[i], t1, list(cursors[i])))
+            closes[i] = t1
+        warm_trees = [hp.hpop_server_wait(srv, t) for t in warm_t]
+        base = hp.hpop_server_get_stats(srv)
+        plan = []
+        for q in range(n_queries):
+            i = int(owner[q])
+            arr, k, fr = serving_slices(hp, W, i, int(sizes[q]), cursors[i], host)
+            t1 = max(fr, closes[i] + 1)
+            plan.append((sids[i], arr, k, closes[i], t1))
+            kept["queries"].append((i, closes[i], t1, list(cursors[i])))
+            closes[i] = t1
+        arrivals = np.cumsum(W["rng"].exponential(1.0 / lam, size=n_queries))
+        queries = [(sid, (arr, k), a, b, int(arrivals[q] * 1e9)) for q, (sid, arr, k, a, b) in enumerate(plan)]
+        reg, glob, lat_ns, wall_ns, busy = hp.hpop_server_replay(srv, queries, mem)
+        st = hp.hpop_server_get_stats(srv)
+    finally:
+        hp.hpop_server_destroy(srv)
+    wall = wall_ns * 1e-9
+    ev = int(sizes.sum())
+    lat_us = np.sort(lat_ns) * 1e-3
+    steps_run = max(1, st.device_steps - base.device_steps)
+    res = {"lambda_req_s": lam, "payload": "host" if host else "device", "queries": n_queries,
+           "events": ev,
+           "offered_events_per_s": ev / float(arrivals[-1]),
+           "events_per_s": ev / wall,
+           "achieved_req_s": n_queries / wall,
+           "p50_us": round(float(np.percentile(lat_us, 50)), 1),
+           "p99_us": round(float(np.percentile(lat_us, 99)), 1),
+           "max_us": round(float(lat_us[-1]), 1),
+           "mean_batch": round((st.mean_batch * st.device_steps - base.mean_batch * base.device_steps)
+                               / steps_run, 2),
+           "busy_retries": busy,
+           # over the server's life, warm-up included
+           "max_submit_us": round(st.max_submit_us, 1), "max_step_us": round(st.max_step_us, 1),
+           "pinned_blocks": int(st.pinned_blocks),
+           "max_pinned_alloc_us": round(st.max_pinned_alloc_us, 1)}
+    if keep:
+        kept["warm_trees"] = warm_trees
+        kept["query_trees"] = list(zip(reg, glob))
+        return res, kept
+    return res
+
+
+def serving_expected_trace(W, entry):
+    """The records a session had received up to and including one query, with
+    that query's region and the session's global region: (session, t0, t1,
+    records per chunk so far) -> tracegen.Trace for the oracle."""
+    import tracegen as tg
+    i, t0, t1, cur = entry
+    S = W["sess"][i]
+    chunks = []
+    gmax = S["origin"]
+    for (r, kind, _, _, pmax, hst, hen), b in zip(S["chunks"], cur):
+        if b > 0:
+            chunks.append(tg.Chunk(r, kind, hst[:b], hen[:b]))
+            gmax = max(gmax, int(pmax[b - 1]))
+    return tg.Trace(W["ranks"], W["ranks"], chunks, [(t0, t1), (S["origin"], gmax)])
+
+
 def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, streams=4, warm=1_000_000,
                 host_lambdas=()):
     """Poisson region-close queries against device-resident sessions.
@@ -329,104 +473,10 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
     `host_lambdas` hand the same slices over from host memory (copied at
     submission, staged through pinned memory), so they include PCIe.
     """
-    import ctypes
-    import threading
-    import torch
-    import tracegen as tg
-    rng = np.random.default_rng(seed)
-    total_q = n_queries * len(lambdas)
-    sizes = np.rint(10 ** rng.uniform(4, 6, size=n_queries)).astype(np.int64)
-    owner = rng.integers(0, n_sessions, size=n_queries)
-    kids = np.random.SeedSequence(seed).spawn(n_sessions)
-    sess = []
-    for i in range(n_sessions):
-        need = warm + int(sizes[owner == i].sum())
-        per_res = max(4, need // (2 * ranks))
-        tr = tg.make_trace(0, ranks, ranks, streams, (8 * per_res) // 5, (2 * per_res) // 5 + 3,
-                           w_range=(0.8, 1.2), seed_seq=kids[i])
-        chunks = []
-        for c in tr.chunks:
-            chunks.append((c.resource, c.kind, torch.from_numpy(c.start).cuda(), torch.from_numpy(c.end).cuda(),
-                           np.maximum.accumulate(c.end), c.start, c.end))
-        sess.append({"origin": tr.info["t0"], "chunks": chunks, "total": tr.n_events})
-    torch.cuda.synchronize()
-
-    def slices(sidx, n_rec, cursor, host=False):
-        """hpop_event_chunk array for the next n_rec records of a session, and the new frontier."""
-        S = sess[sidx]
-        arr = (hp.hpop_event_chunk * len(S["chunks"]))()
-        frontier = S["origin"]
-        k = 0
-        for j, (r, kind, st, en, pmax, hst, hen) in enumerate(S["chunks"]):
-            ln = st.numel()
-            a = cursor[j]
-            b = min(ln, a + max(1, int(round(n_rec * ln / S["total"]))))
-            if b > a:
-                ps = hst.ctypes.data if host else st.data_ptr()
-                pe = hen.ctypes.data if host else en.data_ptr()
-                arr[k] = hp.hpop_event_chunk(r, kind, ps + 8 * a, pe + 8 * a, b - a)
-                k += 1
-                frontier = max(frontier, int(pmax[b - 1]))
-            cursor[j] = b
-        return arr, k, frontier
-
-    lib = hp.lib()
+    W = serving_workload(n_queries, seed, n_sessions, ranks, streams, warm)
     results = []
     for lam, host in [(l, False) for l in lambdas] + [(l, True) for l in host_lambdas]:
-        srv = hp.hpop_server_create(max_sessions=n_sessions, max_inflight=n_sessions, queue_capacity=1 << 16,
-                                    mem_budget_bytes=64 << 30)
-        try:
-            sids = [hp.hpop_server_open_session(srv, ranks, ranks, S["origin"]) for S in sess]
-            cursors = [[0] * len(S["chunks"]) for S in sess]
-            closes = [S["origin"] for S in sess]
-            warm_t = []
-            for i in range(n_sessions):
-                # untimed warm-up in the run's own memory space: a host run also
-                # fills the server's page-locked pool (blocks as large as any query)
-                arr, k, fr = slices(i, warm, cursors[i], host)
-                tk = ctypes.c_uint64()
-                rc = lib.hpop_server_submit(srv, sids[i], arr, k, hp.HPOP_MEM_HOST if host else hp.HPOP_MEM_DEVICE,
-                                            closes[i], max(fr, closes[i] + 1), ctypes.byref(tk))
-                assert rc == 0, rc
-                warm_t.append(tk.value)
-                closes[i] = max(fr, closes[i] + 1)
-            for t in warm_t:
-                hp.hpop_server_wait(srv, t)
-            base = hp.hpop_server_get_stats(srv)
-            plan = []
-            for q in range(n_queries):
-                i = int(owner[q])
-                arr, k, fr = slices(i, int(sizes[q]), cursors[i], host)
-                t1 = max(fr, closes[i] + 1)
-                plan.append((sids[i], arr, k, closes[i], t1, int(sizes[q])))
-                closes[i] = t1
-            arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_queries))
-            queries = [(sid, (arr, k), a, b, int(arrivals[q] * 1e9))
-                       for q, (sid, arr, k, a, b, n_rec) in enumerate(plan)]
-            _, _, lat_ns, wall_ns, busy = hp.hpop_server_replay(srv, queries,
-                                                                hp.HPOP_MEM_HOST if host else hp.HPOP_MEM_DEVICE)
-            st = hp.hpop_server_get_stats(srv)
-        finally:
-            hp.hpop_server_destroy(srv)
-        wall = wall_ns * 1e-9
-        ev = int(sizes.sum())
-        lat_us = np.sort(lat_ns) * 1e-3
-        steps_run = max(1, st.device_steps - base.device_steps)
-        results.append({"lambda_req_s": lam, "payload": "host" if host else "device", "queries": n_queries,
-                        "events": ev,
-                        "offered_events_per_s": ev / float(arrivals[-1]),
-                        "events_per_s": ev / wall,
-                        "achieved_req_s": n_queries / wall,
-                        "p50_us": round(float(np.percentile(lat_us, 50)), 1),
-                        "p99_us": round(float(np.percentile(lat_us, 99)), 1),
-                        "max_us": round(float(lat_us[-1]), 1),
-                        "mean_batch": round((st.mean_batch * st.device_steps - base.mean_batch * base.device_steps)
-                                            / steps_run, 2),
-                        "busy_retries": busy,
-                        # over the server's life, warm-up included
-                        "max_submit_us": round(st.max_submit_us, 1), "max_step_us": round(st.max_step_us, 1),
-                        "pinned_blocks": int(st.pinned_blocks),
-                        "max_pinned_alloc_us": round(st.max_pinned_alloc_us, 1)})
+        results.append(serving_run(hp, W, lam, host))
         log("serving lambda=%d %s: %s" % (lam, "host" if host else "device", results[-1]))
     return {"sessions": n_sessions, "ranks": ranks, "devices": ranks, "streams": streams,
             "warm_events_per_session": warm,

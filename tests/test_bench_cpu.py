@@ -73,3 +73,37 @@ def test_streams_workload_tiles_its_span():
     assert tiles[0, 0] == lo and tiles[-1, 1] == hi and (tiles[1:, 0] == tiles[:-1, 1]).all()
     for g, k, s, e in chunks:
         assert 0 <= g < 3 and 0 <= k < 2 and (s <= e).all()
+
+
+def test_serving_slices_are_consecutive_prefixes():
+    """The serving workload's queries take consecutive slices of each session's
+    chunks, and the oracle's input for a query is exactly the prefix its
+    session had received up to it (with the query's region and the global one)."""
+    import paper_2603_26576_amd as hp
+    W = bench.serving_workload(12, n_sessions=3, ranks=2, streams=2, warm=3000, device=False)
+    assert W["sizes"].size == 12 and ((W["sizes"] >= 10 ** 4) & (W["sizes"] <= 10 ** 6)).all()
+    cursors = [[0] * len(S["chunks"]) for S in W["sess"]]
+    closes = [S["origin"] for S in W["sess"]]
+    for q in [None] * 3 + list(range(12)):
+        i = int(W["owner"][q]) if q is not None else sum(1 for c in closes if c != W["sess"][0]["origin"]) % 3
+        before = list(cursors[i])
+        arr, k, fr = bench.serving_slices(hp, W, i, 3000 if q is None else int(W["sizes"][q]), cursors[i], True)
+        S = W["sess"][i]
+        j = 0
+        for c, (r, kind, _, _, pmax, hst, hen) in enumerate(S["chunks"]):
+            assert before[c] <= cursors[i][c] <= hst.size
+            if cursors[i][c] > before[c]:
+                got = arr[j]
+                assert (got.resource, got.kind, got.count) == (r, kind, cursors[i][c] - before[c])
+                assert got.start == hst.ctypes.data + 8 * before[c] and got.end == hen.ctypes.data + 8 * before[c]
+                assert fr >= int(hen[:cursors[i][c]].max())
+                j += 1
+        assert j == k
+        t1 = max(fr, closes[i] + 1)
+        tr = bench.serving_expected_trace(W, (i, closes[i], t1, list(cursors[i])))
+        assert tr.regions[0] == (closes[i], t1) and tr.regions[1][0] == S["origin"]
+        want_n = sum(cursors[i])
+        assert tr.n_events == want_n
+        if want_n:
+            assert tr.regions[1][1] == max(int(c.end.max()) for c in tr.chunks)
+        closes[i] = t1
