@@ -215,6 +215,17 @@ hpop_status hpop_metrics_compute_all(hpop_session* s, uint32_t flags, hpop_metri
  * host -> {Useful, Offloading, MPI, Other}, device -> {Kernel, Memory, Idle, 0}. */
 hpop_status hpop_resource_times(hpop_session* s, int32_t region, int32_t resource, int64_t out[4]);
 
+/* One region's report for a user (the run-time report of Sec. 3.2: the
+ * metric trees with the raw times they come from): the rendering of
+ * hpop_tree_format followed by every resource's state times in the region
+ * (hosts: useful, offload, MPI, other; devices: kernels, memory operations,
+ * idle), as text lines or as a "resources" array inside the JSON object.
+ * Computes the region first, as hpop_metrics_compute does. Buffer rules as
+ * hpop_tree_format. Errors: HPOP_E_ARG, HPOP_E_REGION, and those of
+ * hpop_metrics_compute. */
+hpop_status hpop_region_format(hpop_session* s, int32_t region, int32_t format, char* buf, int64_t cap,
+                               int64_t* needed);
+
 /* Batched evaluation: the records and regions of k sessions reduced together
  * in one launch sequence (captured once in a HIP graph and replayed while no
  * session changes). out receives every region of every session, session by
@@ -237,7 +248,13 @@ hpop_status hpop_session_stage_times(const hpop_session* s, int32_t cap, const c
 /* Autotuner: times candidate tunings on the given sessions (batched when
  * k > 1), keeps the fastest, applies it to every session and returns it.
  * With cache_path != NULL the choice is read from / appended to that JSON
- * file, keyed by the workload's size class, so later calls skip the search. */
+ * file ({"<size class>": [bucket_target, bucket_cap, tile_elems], ...}),
+ * keyed by the workload's size class (log2 of records, resources and
+ * sessions, rounded), so later calls skip the search. A cache file that
+ * cannot be read, does not parse or holds a value outside the ranges of
+ * hpop_tuning fails with HPOP_E_ARG (message in hpop_last_error(NULL)); so
+ * does a failed trial build or a cache that cannot be written, and in every
+ * failing case the sessions keep the tunings they had. */
 hpop_status hpop_autotune(hpop_session* const* sessions, int32_t k, const char* cache_path,
                           hpop_tuning* out);
 

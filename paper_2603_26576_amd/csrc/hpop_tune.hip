@@ -7,14 +7,13 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
-#include <fstream>
 #include <map>
-#include <sstream>
 #include <string>
 #include <vector>
 
 #include "hpop.h"
 #include "hpop_runtime.h"
+#include "hpop_tune_cache.h"
 
 using namespace hpop;
 
@@ -31,45 +30,6 @@ std::string size_key(hpop_session* const* ss, int k) {
   snprintf(buf, sizeof buf, "ev2^%d_res2^%d_k2^%d", (int)std::lround(std::log2((double)std::max(1ll, ev))),
            (int)std::lround(std::log2((double)std::max(1ll, res))), (int)std::lround(std::log2((double)k)));
   return buf;
-}
-
-// cache file: {"key": [bucket_target, bucket_cap, tile_elems], ...}
-std::map<std::string, std::vector<int>> read_cache(const char* path) {
-  std::map<std::string, std::vector<int>> m;
-  std::ifstream f(path);
-  if (!f) return m;
-  std::stringstream ss;
-  ss << f.rdbuf();
-  const std::string s = ss.str();
-  size_t i = 0;
-  while (true) {
-    size_t q0 = s.find('"', i);
-    if (q0 == std::string::npos) break;
-    size_t q1 = s.find('"', q0 + 1);
-    if (q1 == std::string::npos) break;
-    size_t b0 = s.find('[', q1), b1 = s.find(']', q1);
-    if (b0 == std::string::npos || b1 == std::string::npos || b1 < b0) break;
-    int a = 0, b = 0, c = 0;
-    if (sscanf(s.c_str() + b0 + 1, "%d , %d , %d", &a, &b, &c) == 3) m[s.substr(q0 + 1, q1 - q0 - 1)] = {a, b, c};
-    i = b1 + 1;
-  }
-  return m;
-}
-
-bool write_cache(const char* path, const std::map<std::string, std::vector<int>>& m) {
-  const std::string tmp = std::string(path) + ".tmp";
-  {
-    std::ofstream f(tmp);
-    if (!f) return false;
-    f << "{\n";
-    size_t n = 0;
-    for (auto& kv : m) {
-      f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", " << kv.second[2] << "]"
-        << (++n < m.size() ? "," : "") << "\n";
-    }
-    f << "}\n";
-  }
-  return std::rename(tmp.c_str(), path) == 0;
 }
 
 hpop_status run_once(hpop_session* const* ss, int k, std::vector<hpop_metric_tree>& out) {
@@ -91,8 +51,12 @@ extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const c
         return HPOP_E_ARG;
       }
     const std::string key = size_key(ss, k);
-    std::map<std::string, std::vector<int>> cache;
-    if (cache_path) cache = read_cache(cache_path);
+    TuneCache cache;
+    std::string cerr;
+    if (cache_path && !read_tune_cache(cache_path, cache, cerr)) {
+      g_thread_error = cerr;
+      return HPOP_E_ARG;
+    }
     hpop_tuning best{};
     auto it = cache.find(key);
     if (it != cache.end()) {
@@ -100,6 +64,12 @@ extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const c
       best.bucket_cap = it->second[1];
       best.tile_elems = it->second[2];
     } else {
+      std::vector<hpop_tuning> saved(k);
+      for (int i = 0; i < k; ++i) saved[i] = ss[i]->tuning;
+      auto restore = [&](hpop_status st) {
+        for (int i = 0; i < k; ++i) ss[i]->tuning = saved[i];
+        return st;
+      };
       size_t nreg = 0;
       for (int i = 0; i < k; ++i) nreg += ss[i]->regions.size();
       std::vector<hpop_metric_tree> trees(std::max<size_t>(1, nreg));
@@ -114,13 +84,13 @@ extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const c
             hpop_tuning t{tg, cp, tl, 0};
             for (int i = 0; i < k; ++i) ss[i]->tuning = t;
             hpop_status st = run_once(ss, k, trees);  // warm-up: plan, allocations, graph
-            if (st != HPOP_OK) return st;
+            if (st != HPOP_OK) return restore(st);
             std::vector<double> v;
             for (int r = 0; r < 3; ++r) {
               auto t0 = std::chrono::steady_clock::now();
               st = run_once(ss, k, trees);
               auto t1 = std::chrono::steady_clock::now();
-              if (st != HPOP_OK) return st;
+              if (st != HPOP_OK) return restore(st);
               v.push_back(std::chrono::duration<double>(t1 - t0).count());
             }
             std::sort(v.begin(), v.end());
@@ -131,9 +101,9 @@ extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const c
           }
       if (cache_path) {
         cache[key] = {best.bucket_target, best.bucket_cap, best.tile_elems};
-        if (!write_cache(cache_path, cache)) {
+        if (!write_tune_cache(cache_path, cache)) {
           g_thread_error = std::string("cannot write tuning cache ") + cache_path;
-          return HPOP_E_ARG;
+          return restore(HPOP_E_ARG);
         }
       }
     }
