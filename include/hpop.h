@@ -77,7 +77,12 @@ typedef int32_t hpop_status;
 typedef struct hpop_session hpop_session;
 typedef struct hpop_server hpop_server;
 
-/* Optional device allocator. `stream` is the hipStream_t the memory is used on. */
+/* Optional device allocator. `stream` is the hipStream_t the memory is used on.
+ * alloc returns NULL when it cannot serve the request: the call that needed the
+ * memory then fails with HPOP_E_OOM and leaves the session as it was. free may
+ * be handed a block that work already queued on `stream` still uses: it must
+ * not reuse the block before that stream passes this point (a stream-ordered
+ * free, or a synchronisation of `stream` first). */
 typedef void* (*hpop_alloc_fn)(void* ctx, size_t bytes, void* stream);
 typedef void (*hpop_free_fn)(void* ctx, void* ptr, void* stream);
 

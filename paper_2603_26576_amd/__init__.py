@@ -143,6 +143,7 @@ _SIGS = {
     "hpop_server_get_stats": (_I32, [_P, ctypes.POINTER(hpop_server_stats)]),
     "hpop_server_last_error": (ctypes.c_char_p, [_P]),
     "hpop_tree_format": (_I32, [ctypes.POINTER(hpop_metric_tree), _I32, ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
+    "hpop_region_format": (_I32, [_P, _I32, _I32, ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
     "hpop_session_set_streams": (_I32, [_P, _P]),
     "hpop_add_stream_events": (_I32, [_P, _I32, _I32, _P, _P, _I64, _I32]),
     "hpop_stream_metrics": (_I32, [_P, _U32, ctypes.c_void_p, _P]),
@@ -197,8 +198,16 @@ def hpop_status_string(status):
     return lib().hpop_status_string(status).decode()
 
 
-def hpop_session_create(n_hosts, n_devices, stream=None):
-    cfg = hpop_session_config(n_hosts, n_devices, stream or 0, None, None, None)
+# hpop_alloc_fn / hpop_free_fn of include/hpop.h (the caller keeps the objects alive)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def hpop_session_create(n_hosts, n_devices, stream=None, alloc=None, free=None, alloc_ctx=None):
+    """alloc / free: optional ALLOC_FN / FREE_FN objects for every device allocation."""
+    cfg = hpop_session_config(n_hosts, n_devices, stream or 0,
+                              ctypes.cast(alloc, ctypes.c_void_p) if alloc else None,
+                              ctypes.cast(free, ctypes.c_void_p) if free else None, alloc_ctx)
     h = _P()
     _check(lib().hpop_session_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h.value
@@ -449,6 +458,15 @@ def hpop_tree_format(t, fmt=HPOP_FORMAT_TEXT):
     _check(lib().hpop_tree_format(ctypes.byref(t), fmt, None, 0, ctypes.byref(need)))
     buf = ctypes.create_string_buffer(int(need.value))
     _check(lib().hpop_tree_format(ctypes.byref(t), fmt, buf, need.value, None))
+    return buf.value.decode()
+
+
+def hpop_region_format(s, region, fmt=HPOP_FORMAT_TEXT):
+    """A region's report (its trees and every resource's state times) as text or JSON (a str)."""
+    need = _I64()
+    _check(lib().hpop_region_format(s, region, fmt, None, 0, ctypes.byref(need)), s)
+    buf = ctypes.create_string_buffer(int(need.value))
+    _check(lib().hpop_region_format(s, region, fmt, buf, need.value, None), s)
     return buf.value.decode()
 
 

@@ -50,12 +50,18 @@ double value(const hpop_metric_tree& t, int bit) {
 
 void appendf(std::string& s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 void appendf(std::string& s, const char* fmt, ...) {
-  char buf[256];
-  va_list ap;
+  va_list ap, ap2;
   va_start(ap, fmt);
-  const int k = vsnprintf(buf, sizeof buf, fmt, ap);
+  va_copy(ap2, ap);
+  const int k = vsnprintf(nullptr, 0, fmt, ap);  // the full length, however long
   va_end(ap);
-  if (k > 0) s.append(buf, (size_t)(k < (int)sizeof buf ? k : (int)sizeof buf - 1));
+  if (k > 0) {
+    const size_t at = s.size();
+    s.resize(at + (size_t)k + 1);
+    vsnprintf(&s[at], (size_t)k + 1, fmt, ap2);
+    s.resize(at + (size_t)k);
+  }
+  va_end(ap2);
 }
 
 std::string text(const hpop_metric_tree& t) {
@@ -104,13 +110,46 @@ std::string json(const hpop_metric_tree& t) {
   return s;
 }
 
+// One line (text) or object (JSON) per resource: hosts 0..n-1 with their
+// useful, offload, MPI and other times, devices n..n+m-1 with kernel,
+// memory-operation and idle times (times: 4 int64 per resource, in that order).
+std::string resources_text(int n, int m, const int64_t* times) {
+  std::string s = "Resource times in the region (ns):\n";
+  for (int r = 0; r < n + m; ++r) {
+    const int64_t* x = times + 4 * (size_t)r;
+    if (r < n)
+      appendf(s, "  host %d: useful %" PRId64 ", offload %" PRId64 ", MPI %" PRId64 ", other %" PRId64 "\n", r, x[0],
+              x[1], x[2], x[3]);
+    else
+      appendf(s, "  device %d: kernels %" PRId64 ", memory operations %" PRId64 ", idle %" PRId64 "\n", r - n, x[0],
+              x[1], x[2]);
+  }
+  return s;
+}
+
+std::string resources_json(int n, int m, const int64_t* times) {
+  std::string s = "\"resources\": [";
+  for (int r = 0; r < n + m; ++r) {
+    const int64_t* x = times + 4 * (size_t)r;
+    if (r < n)
+      appendf(s, "%s{\"host\": %d, \"useful\": %" PRId64 ", \"offload\": %" PRId64 ", \"mpi\": %" PRId64
+              ", \"other\": %" PRId64 "}", r ? ", " : "", r, x[0], x[1], x[2], x[3]);
+    else
+      appendf(s, "%s{\"device\": %d, \"kernel\": %" PRId64 ", \"memory_operations\": %" PRId64 ", \"idle\": %" PRId64
+              "}", r ? ", " : "", r - n, x[0], x[1], x[2]);
+  }
+  s += "]";
+  return s;
+}
+
 }  // namespace
 
-extern "C" hpop_status hpop_tree_format(const hpop_metric_tree* tree, int32_t format, char* buf, int64_t cap,
-                                        int64_t* needed) {
-  if (!tree || (format != HPOP_FORMAT_TEXT && format != HPOP_FORMAT_JSON) || cap < 0 || (cap > 0 && !buf))
-    return HPOP_E_ARG;
-  const std::string s = format == HPOP_FORMAT_TEXT ? text(*tree) : json(*tree);
+namespace hpop {
+
+// The string, NUL-terminated and cut to cap - 1 characters, into buf; the
+// full size with the terminator into *needed.
+hpop_status emit_string(const std::string& s, char* buf, int64_t cap, int64_t* needed) {
+  if (cap < 0 || (cap > 0 && !buf)) return HPOP_E_ARG;
   if (needed) *needed = (int64_t)s.size() + 1;
   if (cap > 0) {
     const size_t k = s.size() < (size_t)cap - 1 ? s.size() : (size_t)cap - 1;
@@ -118,4 +157,22 @@ extern "C" hpop_status hpop_tree_format(const hpop_metric_tree* tree, int32_t fo
     buf[k] = '\0';
   }
   return HPOP_OK;
+}
+
+// A region's report: the tree rendering followed by every resource's state
+// times (the run-time report with raw metrics, Sec. 3.2).
+std::string render_region(const hpop_metric_tree& t, int32_t format, int n, int m, const int64_t* times) {
+  if (format == HPOP_FORMAT_TEXT) return text(t) + resources_text(n, m, times);
+  std::string s = json(t);
+  s.pop_back();  // the closing brace of the tree object
+  return s + ", " + resources_json(n, m, times) + "}";
+}
+
+}  // namespace hpop
+
+extern "C" hpop_status hpop_tree_format(const hpop_metric_tree* tree, int32_t format, char* buf, int64_t cap,
+                                        int64_t* needed) {
+  if (!tree || (format != HPOP_FORMAT_TEXT && format != HPOP_FORMAT_JSON) || cap < 0 || (cap > 0 && !buf))
+    return HPOP_E_ARG;
+  return hpop::emit_string(format == HPOP_FORMAT_TEXT ? text(*tree) : json(*tree), buf, cap, needed);
 }

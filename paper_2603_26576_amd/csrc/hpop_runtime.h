@@ -16,6 +16,12 @@ const char* status_name(hpop_status s);
 int slot_of_kind(int kind);
 long long tuning_key(const hpop_tuning& t);
 
+// Renderings (hpop_format.hip): a region's report with per-resource times
+// (4 int64 per resource, hosts then devices), and the buffer rule of the
+// formatting calls.
+std::string render_region(const hpop_metric_tree& t, int32_t format, int n, int m, const int64_t* times);
+hpop_status emit_string(const std::string& s, char* buf, int64_t cap, int64_t* needed);
+
 // Stream-ordered device allocator: the caller's callbacks or hipMallocAsync.
 struct Alloc {
   hipStream_t stream = nullptr;

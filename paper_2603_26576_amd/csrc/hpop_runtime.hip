@@ -192,15 +192,15 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   small += carve_bytes(9 * n_regions, sizeof(unsigned long long));
   small += carve_bytes(n_ivls, sizeof(IvlDesc)) + carve_bytes(n_ivls ? 4 * n_times : 0, sizeof(long long));
   small += carve_bytes(4 * n_times, sizeof(long long));
-  if (!meta.reserve(a, small, false)) {
-    err = "device allocation of " + std::to_string(small) + " bytes (build metadata) failed";
-    return HPOP_E_OOM;
-  }
   // bucketed records: fixed slots per bucket (n_slots > 0) or exact offsets,
   // where oversized buckets also need a scratch copy for their global sort
   const size_t big_e = carve_bytes(n_slots > 0 ? n_slots : n_elems, sizeof(Elem));
   const size_t big_e2 = carve_bytes(n_slots > 0 ? 1 : n_elems, sizeof(Elem));
   const size_t big_c = carve_bytes(n_elems, sizeof(Comp)), big_n = carve_bytes(n_elems, sizeof(CompN));
+  if (!meta.reserve(a, small, false)) {
+    err = "device allocation of " + std::to_string(small) + " bytes (build metadata) failed";
+    return HPOP_E_OOM;
+  }
   if (!elems.reserve(a, big_e, false) || !elems2.reserve(a, big_e2, false) || !comp[0].reserve(a, big_c, false) ||
       !comp[1].reserve(a, big_c, false) || !comp[2].reserve(a, big_c, false) || !compn[0].reserve(a, big_n, false) ||
       !compn[1].reserve(a, big_n, false) || !compn[2].reserve(a, big_n, false)) {
@@ -396,9 +396,9 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
 }
 
 hpop_status Engine::upload(std::string& err) {
-  // descriptors go through pinned memory so the copies are stream-ordered
   const size_t bc = h_chunks.size() * sizeof(ChunkDesc), bs = h_segs.size() * sizeof(SegDesc),
                br = h_regions.size() * sizeof(RegionDesc), bi = h_ivls.size() * sizeof(IvlDesc);
+  // descriptors go through pinned memory so the copies are stream-ordered
   if (!ws.pinned_desc.reserve(bc + bs + br + bi + 64)) {
     err = "pinned host allocation failed";
     return HPOP_E_OOM;
@@ -964,6 +964,28 @@ hpop_status hpop_resource_times(hpop_session* s, int32_t region, int32_t resourc
   hipError_t e = hipMemcpy(out, s->engine.ws.d_times + row * 4, 32, hipMemcpyDeviceToHost);
   if (e != hipSuccess) return fail(s, HPOP_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
   return HPOP_OK;
+  HPOP_GUARD_END(s)
+}
+
+hpop_status hpop_region_format(hpop_session* s, int32_t region, int32_t format, char* buf, int64_t cap,
+                               int64_t* needed) {
+  HPOP_GUARD_BEGIN
+  if (!s) return fail(s, HPOP_E_ARG, "null session");
+  if ((format != HPOP_FORMAT_TEXT && format != HPOP_FORMAT_JSON) || cap < 0 || (cap > 0 && !buf))
+    return fail(s, HPOP_E_ARG, "bad format or buffer");
+  hpop_metric_tree tree;
+  hpop_status st = hpop_metrics_compute(s, region, &tree);
+  if (st != HPOP_OK) return st;
+  // the region's state times are one contiguous row block (4 int64 per resource)
+  const int R = s->n_hosts + s->n_devices;
+  std::vector<int64_t> times(4 * (size_t)R + 1);
+  if (R > 0) {
+    const long long row = s->engine.h_regions[region].times_off;
+    hipError_t e = hipMemcpy(times.data(), s->engine.ws.d_times + row * 4, 32 * (size_t)R, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(s, HPOP_E_HIP, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  return hpop::emit_string(hpop::render_region(tree, format, s->n_hosts, s->n_devices, times.data()), buf, cap,
+                           needed);
   HPOP_GUARD_END(s)
 }
 

@@ -81,3 +81,27 @@ def test_bad_arguments_and_truncation():
     buf = ctypes.create_string_buffer(16)
     assert L.hpop_tree_format(ctypes.byref(t), 1, buf, 16, ctypes.byref(need)) == 0
     assert len(buf.value) == 15 and need.value > 16
+
+
+def test_json_and_text_keep_long_values_whole():
+    """Every integer at its widest (20 characters) and ratios with 17 significant
+    digits: the JSON still parses and gives back every value exactly, and the
+    text shows every integer in full."""
+    t = hp.hpop_metric_tree()
+    t.E, t.n, t.m = -(2 ** 63) + 1, 2 ** 31 - 1, -(2 ** 31)
+    big = [-(2 ** 63) + 1 + i for i in range(10)]
+    for f, v in zip(hp.SUM_FIELDS, big):
+        setattr(t, f, v)
+    vals = [1.2345678901234567e-300 * (i + 1) for i in range(9)]
+    for f, v in zip(hp.RATIO_FIELDS, vals):
+        setattr(t, f, v)
+    t.undefined_mask = 0x1ff
+    d = json.loads(hp.hpop_tree_format(t, hp.HPOP_FORMAT_JSON))
+    assert (d["E"], d["n"], d["m"]) == (t.E, t.n, t.m)
+    times = d["times"]
+    assert [times[k] for k in ("useful", "offload", "mpi", "other", "useful_plus_offload", "max_useful_plus_offload",
+                               "kernel", "memory_operations", "max_kernel", "max_kernel_plus_memory")] == big
+    assert len(d["undefined"]) == 9
+    text = hp.hpop_tree_format(t, hp.HPOP_FORMAT_TEXT)
+    for v in big[:4] + big[6:8]:
+        assert str(v) in text
