@@ -231,6 +231,32 @@ hpop_status hpop_resource_times(hpop_session* s, int32_t region, int32_t resourc
 hpop_status hpop_region_format(hpop_session* s, int32_t region, int32_t format, char* buf, int64_t cap,
                                int64_t* needed);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one-shot
+ * evaluation with no session and no allocation. The results are those of a
+ * session with n_hosts hosts and n_devices devices, the chunks added with
+ * HPOP_MEM_DEVICE, the regions [region_t0[g], region_t1[g]) defined in
+ * order, then hpop_metrics_compute_all (trees into out[0..n_regions)) and
+ * hpop_resource_times (into times_out, optional: [n_regions][n + m][4]).
+ * Chunk arrays must be device memory and are read in place. Every
+ * intermediate lives in a library-owned device array of
+ * HPOP_STATIC_SCRATCH_BYTES per GPU, taken when the first call on that GPU
+ * loads it and held until the process ends; each call overwrites it. A call
+ * whose build needs more than that fails with HPOP_E_ARG (message in
+ * hpop_last_error(NULL) with the size needed). Calls on one GPU share that
+ * array: within a process they are serialised by the library; work of one
+ * call overlapping another's on the same GPU by other means would race.
+ * The call runs on `stream` (a hipStream_t, NULL for the null stream) and
+ * synchronises it before returning. Errors: HPOP_E_ARG, HPOP_E_RESOURCE,
+ * HPOP_E_KIND, HPOP_E_REGION, HPOP_E_OVERFLOW as for the session calls;
+ * HPOP_E_BAD_INTERVAL naming the chunk and index of an invalid record (no
+ * tree is written); HPOP_E_HIP. */
+#define HPOP_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+hpop_status hpop_metrics_compute_static(int32_t n_hosts, int32_t n_devices, const hpop_event_chunk* chunks,
+                                        int32_t n_chunks, const int64_t* region_t0, const int64_t* region_t1,
+                                        int32_t n_regions, void* stream, hpop_metric_tree* out,
+                                        int64_t* times_out);
+
 /* Batched evaluation: the records and regions of k sessions reduced together
  * in one launch sequence (captured once in a HIP graph and replayed while no
  * session changes). out receives every region of every session, session by

@@ -144,6 +144,9 @@ _SIGS = {
     "hpop_server_last_error": (ctypes.c_char_p, [_P]),
     "hpop_tree_format": (_I32, [ctypes.POINTER(hpop_metric_tree), _I32, ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
     "hpop_region_format": (_I32, [_P, _I32, _I32, ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
+    "hpop_metrics_compute_static": (_I32, [_I32, _I32, ctypes.POINTER(hpop_event_chunk), _I32,
+                                           ctypes.POINTER(_I64), ctypes.POINTER(_I64), _I32, _P,
+                                           ctypes.POINTER(hpop_metric_tree), ctypes.POINTER(_I64)]),
     "hpop_session_set_streams": (_I32, [_P, _P]),
     "hpop_add_stream_events": (_I32, [_P, _I32, _I32, _P, _P, _I64, _I32]),
     "hpop_stream_metrics": (_I32, [_P, _U32, ctypes.c_void_p, _P]),
@@ -311,6 +314,31 @@ def hpop_metrics_compute_all(s, flags=0):
     out = (hpop_metric_tree * max(1, n))()
     _check(lib().hpop_metrics_compute_all(s, flags, out), s)
     return list(out[:n])
+
+
+HPOP_STATIC_SCRATCH_BYTES = 256 << 20
+
+
+def hpop_metrics_compute_static(n_hosts, n_devices, chunks, regions, stream=None, times=False):
+    """One-shot evaluation without allocation: chunks are (resource, kind, start, end)
+    device tensors, regions (t0, t1) pairs. Returns the trees (a ctypes array),
+    and with times=True also an int64 array [regions][n_hosts + n_devices][4]."""
+    arr = (hpop_event_chunk * max(1, len(chunks)))()
+    for i, (r, k, st, en) in enumerate(chunks):
+        ps, _ = _ptr(st)
+        pe, _ = _ptr(en)
+        if len(st) != len(en):
+            raise ValueError("start and end must have the same length")
+        arr[i] = hpop_event_chunk(r, k, ps, pe, len(st))
+    nreg = len(regions)
+    t0 = (_I64 * max(1, nreg))(*[a for a, _ in regions])
+    t1 = (_I64 * max(1, nreg))(*[b for _, b in regions])
+    out = (hpop_metric_tree * max(1, nreg))()
+    tout = np.zeros((nreg, n_hosts + n_devices, 4), np.int64) if times else None
+    _check(lib().hpop_metrics_compute_static(
+        n_hosts, n_devices, arr, len(chunks), t0, t1, nreg, stream or 0, out,
+        tout.ctypes.data_as(ctypes.POINTER(_I64)) if times else None))
+    return (out, tout) if times else out
 
 
 def hpop_resource_times(s, region, resource):

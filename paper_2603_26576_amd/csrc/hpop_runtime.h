@@ -73,6 +73,11 @@ struct Workspace {
   long long* d_macc = nullptr;   // [n_times][4] their per-resource accumulators
   hipGraphExec_t graph_exec = nullptr;
   long long layout_gen = 0;
+  // set: everything is carved from this one device region of fixed_bytes
+  // (no allocation, no page-locked staging); fixed_needed is the last plan's size
+  char* fixed = nullptr;
+  size_t fixed_bytes = 0;
+  size_t fixed_needed = 0;
   hpop_status prepare(Alloc& a, long long n_chunks, long long n_tiles, long long n_segs, long long n_buckets,
                       long long n_elems,
                       long long n_slots, long long n_regions, long long n_times, long long n_owners,
@@ -101,6 +106,7 @@ struct Engine {
   bool use_graphs = true;
   int graph_replays = 0;
   long long last_oversized = 0;
+  char* result_host = nullptr;  // set: enqueue copies the results here instead of the page-locked buffer
   // timing
   bool exact_forced = false;  // a bucket outgrew its scatter slots: use exact offsets
   std::vector<unsigned long long> forced_versions;

@@ -197,17 +197,53 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   const size_t big_e = carve_bytes(n_slots > 0 ? n_slots : n_elems, sizeof(Elem));
   const size_t big_e2 = carve_bytes(n_slots > 0 ? 1 : n_elems, sizeof(Elem));
   const size_t big_c = carve_bytes(n_elems, sizeof(Comp)), big_n = carve_bytes(n_elems, sizeof(CompN));
-  if (!meta.reserve(a, small, false)) {
-    err = "device allocation of " + std::to_string(small) + " bytes (build metadata) failed";
-    return HPOP_E_OOM;
+  char* meta_p;
+  char* elems_p;
+  char* elems2_p;
+  char* comp_p[3];
+  char* compn_p[3];
+  if (fixed) {
+    // one caller-provided region holds everything, in this order
+    fixed_needed = small + big_e + big_e2 + 3 * (big_c + big_n);
+    if (fixed_needed > fixed_bytes) {
+      err = "the build needs " + std::to_string(fixed_needed) + " bytes of scratch; " +
+            std::to_string(fixed_bytes) + " are available";
+      return HPOP_E_ARG;
+    }
+    char* c = fixed;
+    meta_p = c;
+    c += small;
+    elems_p = c;
+    c += big_e;
+    elems2_p = c;
+    c += big_e2;
+    for (int l = 0; l < 3; ++l) {
+      comp_p[l] = c;
+      c += big_c;
+      compn_p[l] = c;
+      c += big_n;
+    }
+  } else {
+    if (!meta.reserve(a, small, false)) {
+      err = "device allocation of " + std::to_string(small) + " bytes (build metadata) failed";
+      return HPOP_E_OOM;
+    }
+    if (!elems.reserve(a, big_e, false) || !elems2.reserve(a, big_e2, false) || !comp[0].reserve(a, big_c, false) ||
+        !comp[1].reserve(a, big_c, false) || !comp[2].reserve(a, big_c, false) ||
+        !compn[0].reserve(a, big_n, false) || !compn[1].reserve(a, big_n, false) ||
+        !compn[2].reserve(a, big_n, false)) {
+      err = "device allocation for " + std::to_string(n_elems) + " records failed";
+      return HPOP_E_OOM;
+    }
+    meta_p = (char*)meta.ptr;
+    elems_p = (char*)elems.ptr;
+    elems2_p = (char*)elems2.ptr;
+    for (int l = 0; l < 3; ++l) {
+      comp_p[l] = (char*)comp[l].ptr;
+      compn_p[l] = (char*)compn[l].ptr;
+    }
   }
-  if (!elems.reserve(a, big_e, false) || !elems2.reserve(a, big_e2, false) || !comp[0].reserve(a, big_c, false) ||
-      !comp[1].reserve(a, big_c, false) || !comp[2].reserve(a, big_c, false) || !compn[0].reserve(a, big_n, false) ||
-      !compn[1].reserve(a, big_n, false) || !compn[2].reserve(a, big_n, false)) {
-    err = "device allocation for " + std::to_string(n_elems) + " records failed";
-    return HPOP_E_OOM;
-  }
-  char* cur = (char*)meta.ptr;
+  char* cur = meta_p;
   Plan& p = plan;
   p.chunks = d_chunks = carve<ChunkDesc>(cur, n_chunks);
   p.tile_chunk = carve<int32_t>(cur, n_tiles);
@@ -238,11 +274,11 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   d_times = carve<long long>(cur, 4 * n_times);
   d_ivls = carve<IvlDesc>(cur, n_ivls);
   d_macc = carve<long long>(cur, n_ivls ? 4 * n_times : 0);
-  p.elems = (Elem*)elems.ptr;
-  p.elems2 = (Elem*)elems2.ptr;
+  p.elems = (Elem*)elems_p;
+  p.elems2 = (Elem*)elems2_p;
   for (int l = 0; l < 3; ++l) {
-    p.comp[l] = (Comp*)comp[l].ptr;
-    p.compn[l] = (CompN*)compn[l].ptr;
+    p.comp[l] = (Comp*)comp_p[l];
+    p.compn[l] = (CompN*)compn_p[l];
   }
   p.n_chunks = (int32_t)n_chunks;
   p.n_segs = (int32_t)n_segs;
@@ -398,6 +434,19 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
 hpop_status Engine::upload(std::string& err) {
   const size_t bc = h_chunks.size() * sizeof(ChunkDesc), bs = h_segs.size() * sizeof(SegDesc),
                br = h_regions.size() * sizeof(RegionDesc), bi = h_ivls.size() * sizeof(IvlDesc);
+  if (ws.fixed) {
+    // no page-locked staging (it would be an allocation): copies straight from
+    // the host vectors, which stay untouched until the caller synchronises
+    if (bc) HPOP_HIP(hipMemcpyAsync(ws.d_chunks, h_chunks.data(), bc, hipMemcpyHostToDevice, alloc.stream), "upload chunks");
+    if (bs) HPOP_HIP(hipMemcpyAsync(ws.d_segs, h_segs.data(), bs, hipMemcpyHostToDevice, alloc.stream), "upload segments");
+    if (br)
+      HPOP_HIP(hipMemcpyAsync(ws.d_regions, h_regions.data(), br, hipMemcpyHostToDevice, alloc.stream),
+               "upload regions");
+    if (bi)
+      HPOP_HIP(hipMemcpyAsync(ws.d_ivls, h_ivls.data(), bi, hipMemcpyHostToDevice, alloc.stream),
+               "upload region intervals");
+    return HPOP_OK;
+  }
   // descriptors go through pinned memory so the copies are stream-ordered
   if (!ws.pinned_desc.reserve(bc + bs + br + bi + 64)) {
     err = "pinned host allocation failed";
@@ -473,7 +522,7 @@ hpop_status Engine::enqueue(bool build, bool with_timing, std::string& err) {
   n_marks = ev;
   // results: trees, first bad record, oversized buckets, slot overflow
   const size_t bt = (size_t)nreg * sizeof(Tree);
-  char* h = (char*)ws.pinned.ptr;
+  char* h = result_host ? result_host : (char*)ws.pinned.ptr;
   if (bt) HPOP_HIP(hipMemcpyAsync(h, ws.d_trees, bt, hipMemcpyDeviceToHost, st), "copy trees");
   HPOP_HIP(hipMemcpyAsync(h + bt, p.err, 8, hipMemcpyDeviceToHost, st), "copy error word");
   HPOP_HIP(hipMemcpyAsync(h + bt + 8, p.oversized, 16, hipMemcpyDeviceToHost, st), "copy counters");
