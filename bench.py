@@ -34,6 +34,7 @@ COLLECT_APP = os.path.join(ROOT, "tests", "apps", "collect_app")
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+ALGO_BYTES_PER_RECORD = 16  # each record's start and end, read once
 METRIC = "trace events/sec reduced to full metric tree"
 
 # algorithmic bytes per unit of each build kernel (a unit is a record, except
@@ -153,17 +154,26 @@ def bench_single(hp, trace, steps, warmup, workload, tune_cache=None):
         hp.hpop_session_destroy(s)
     stage_ms = {k: v / steps for k, v in stage_tot.items()}
     dom = max((k for k in stage_ms if k in ALGO_BYTES), key=lambda k: stage_ms[k])
-    if dom == "merge_wave":
-        algo = 8 * n_events + 8 * info.n_wide_records + 8 * info.n_components + 8 * info.n_wide_components
-    elif dom == "scatter":
-        algo = 24 * n_events + 8 * info.n_wide_records
-    else:
-        algo = ALGO_BYTES[dom] * n_events
+    # algorithmic bytes of one launch: 16 B per record (its start and end,
+    # read once) times the records one launch processes (all of them)
+    algo = ALGO_BYTES_PER_RECORD * n_events
     achieved = algo / (stage_ms[dom] * 1e-3) / 1e9
+    # beside it, the minimum bytes of the kernel's own role (its reads and
+    # writes in the engine's data layout)
+    if dom == "merge_wave":
+        role = 8 * n_events + 8 * info.n_wide_records + 8 * info.n_components + 8 * info.n_wide_components
+    elif dom == "scatter":
+        role = 24 * n_events + 8 * info.n_wide_records
+    else:
+        role = ALGO_BYTES[dom] * n_events
+    role_gbs = role / (stage_ms[dom] * 1e-3) / 1e9
     traffic = load_traffic(dom, workload)
     roof = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": int(algo), "avg_launch_ms": round(stage_ms[dom], 4)}
+            "algorithmic_bytes_per_launch": int(algo), "bytes_per_unit": ALGO_BYTES_PER_RECORD,
+            "units_per_launch": int(n_events), "avg_launch_ms": round(stage_ms[dom], 4),
+            "kernel_role_bytes_per_launch": int(role), "kernel_role_GBps": round(role_gbs, 1),
+            "kernel_role_frac": round(role_gbs / HBM_PEAK_GBS, 4)}
     tuning = {"bucket_target": tun.bucket_target, "bucket_cap": tun.bucket_cap, "tile_elems": tun.tile_elems}
     return {"tuning": tuning, "ms_per_step": dt * 1e3, "ms_per_step_graph": dt_graph * 1e3, "events": n_events,
             "value": n_events / dt, "value_graph": n_events / dt_graph, "stage_ms": stage_ms, "roofline": roof,
@@ -171,6 +181,110 @@ def bench_single(hp, trace, steps, warmup, workload, tune_cache=None):
             "wide_records": int(info.n_wide_records),
             "buckets": int(info.n_buckets),
             "oversized_buckets": int(info.n_oversized), "trees": trees}
+
+
+def small_leg(hp, reps=20):
+    """Small trace (4 ranks x 4 devices x 2 streams, 8e4 records, the whole
+    span as one region): latency of one full rebuild and reduction, with the
+    records resident in HBM, median of `reps` calls of the C entry points
+    (arguments prepared once): kernels launched one by one, the captured HIP
+    graph replayed, and the entry point that allocates nothing; the sum of
+    the kernels' HIP-event times; the oracle timed beside it (one warm-up,
+    median of 5)."""
+    import ctypes
+
+    import oracle
+    import torch
+    import tracegen as tg
+    tr = tg.small()
+    L = hp.lib()
+    nreg = len(tr.regions)
+    out = (hp.hpop_metric_tree * nreg)()
+    s = upload_session(hp, tr)
+
+    def med_us(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return round(float(np.median(ts)) * 1e6, 1)
+
+    def call(flags):
+        def f():
+            st = L.hpop_metrics_compute_all(s, flags, out)
+            if st != hp.HPOP_OK:
+                raise hp.HpopError(st, hp.hpop_status_string(st))
+        return f
+
+    try:
+        for _ in range(3):
+            call(hp.HPOP_FORCE_REBUILD)()
+        direct_us = med_us(call(hp.HPOP_FORCE_REBUILD | hp.HPOP_NO_GRAPH))
+        graph_us = med_us(call(hp.HPOP_FORCE_REBUILD))
+        hp.hpop_session_enable_timing(s, True)
+        ks = []
+        for _ in range(reps):
+            call(hp.HPOP_FORCE_REBUILD)()
+            ks.append(sum(ms for _, ms in hp.hpop_session_stage_times(s)))
+        hp.hpop_session_enable_timing(s, False)
+        kernel_us = round(float(np.median(ks)) * 1e3, 1)
+        want = [bytes(t) for t in hp.hpop_metrics_compute_all(s)]
+    finally:
+        hp.hpop_session_destroy(s)
+    # the same records and region through the entry point that allocates nothing
+    dev = [(c.resource, c.kind, torch.from_numpy(c.start).cuda(), torch.from_numpy(c.end).cuda()) for c in tr.chunks]
+    torch.cuda.synchronize()
+    arr = (hp.hpop_event_chunk * len(dev))(*[hp.hpop_event_chunk(r, k, a.data_ptr(), b.data_ptr(), a.numel())
+                                              for r, k, a, b in dev])
+    t0s = (ctypes.c_int64 * nreg)(*[a for a, _ in tr.regions])
+    t1s = (ctypes.c_int64 * nreg)(*[b for _, b in tr.regions])
+    sout = (hp.hpop_metric_tree * nreg)()
+
+    def static_call():
+        st = L.hpop_metrics_compute_static(tr.n_hosts, tr.n_devices, arr, len(dev), t0s, t1s, nreg, None, sout, None)
+        if st != hp.HPOP_OK:
+            raise hp.HpopError(st, hp.hpop_status_string(st))
+
+    static_us = med_us(static_call)
+    if [bytes(t) for t in sout] != want:
+        raise RuntimeError("the entry point without allocation disagrees with the session path")
+    del dev
+    ora1 = timed_median(lambda: oracle.compute(tr, threads=1))
+    thr = oracle_threads()
+    oran = timed_median(lambda: oracle.compute(tr, threads=thr))
+    n = tr.n_events
+    return {"workload": "small trace", "ranks": 4, "devices": 4, "streams": 2, "regions": nreg, "events": n,
+            "timing": "median of %d calls after warm-up" % reps,
+            "us_per_compute": direct_us, "us_per_compute_graph": graph_us, "us_per_compute_no_alloc": static_us,
+            "kernel_us": kernel_us, "events_per_s": n / (graph_us * 1e-6),
+            "oracle": {"us_per_compute": round(ora1 * 1e6, 1), "cores": 1,
+                       "us_per_compute_threads": round(oran * 1e6, 1), "threads": thr,
+                       "timing": "1 warm-up, median of 5"}}
+
+
+def mid_leg(hp, steps, warmup, tune_cache=None):
+    """Mid trace (64 ranks x 64 devices x 8 streams, 1.25e7 records, 16
+    nested regions): the single-trace leg at that size, its whole-path HBM
+    figures (the records, 200 MB, and much of the build's traffic fit the
+    256 MB last-level cache, so the counter fraction is flagged as
+    cache-resident) and the oracle beside it."""
+    import tracegen as tg
+    t = time.time()
+    tr = tg.mid()
+    log("mid: generated %d records in %.1f s" % (tr.n_events, time.time() - t))
+    r = bench_single(hp, tr, steps, warmup, "mid", tune_cache)
+    out = {"workload": "mid trace", "ranks": 64, "devices": 64, "streams": 8, "regions": len(tr.regions),
+           "events": tr.n_events, "ms_per_step": round(r["ms_per_step"], 4), "events_per_s": r["value"],
+           "graph_replay": {"ms_per_step": round(r["ms_per_step_graph"], 4), "events_per_s": r["value_graph"]},
+           "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()}, "roofline": r["roofline"],
+           "tuning": r["tuning"]}
+    ph = path_hbm(r, "mid")
+    ph["cache_resident"] = True
+    out["path_hbm"] = ph
+    out["cpu_baseline"] = cpu_baseline(tr)
+    return out
 
 
 def bench_batched(hp, traces, steps, warmup, tune_cache=None):
@@ -327,12 +441,19 @@ def serving_workload(n_queries, seed=1005, n_sessions=32, ranks=16, streams=4, w
     sizes = np.rint(10 ** rng.uniform(4, 6, size=n_queries)).astype(np.int64)
     owner = rng.integers(0, n_sessions, size=n_queries)
     kids = np.random.SeedSequence(seed).spawn(n_sessions)
-    sess = []
-    for i in range(n_sessions):
+
+    def gen(i):
         need = warm + int(sizes[owner == i].sum())
         per_res = max(4, need // (2 * ranks))
-        tr = tg.make_trace(0, ranks, ranks, streams, (8 * per_res) // 5, (2 * per_res) // 5 + 3,
-                           w_range=(0.8, 1.2), seed_seq=kids[i])
+        return tg.make_trace(0, ranks, ranks, streams, (8 * per_res) // 5, (2 * per_res) // 5 + 3,
+                             w_range=(0.8, 1.2), seed_seq=kids[i])
+
+    # sessions are independent (a seed each): generated on the host's threads
+    import concurrent.futures
+    with concurrent.futures.ThreadPoolExecutor(max_workers=oracle_threads()) as ex:
+        traces = list(ex.map(gen, range(n_sessions)))
+    sess = []
+    for i, tr in enumerate(traces):
         chunks = []
         for c in tr.chunks:
             if device:
@@ -485,11 +606,41 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
             "runs": results}
 
 
-def cpu_baseline(trace, target_s=12.0):
-    """Oracle on a bounded sample: a subset of the resources, all regions."""
+def cpu_model():
+    """The host CPU's model name and logical CPU count (Linux)."""
+    name = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": name, "logical_cpus": os.cpu_count()}
+
+
+def timed_median(fn, reps=5):
+    """One untimed warm-up call, then the median wall time of `reps` calls."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def oracle_threads():
+    """The oracle's threads: the host's CPUs, at most 16 (one GPU's share of its host)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def cpu_baseline(trace, target_s=2.5, target_1_s=1.5):
+    """Oracle on a bounded sample: a subset of the resources, all regions; one
+    warm-up and the median of 5 runs, with the host's threads and on one thread."""
     import oracle
     import tracegen as tg
-    threads = os.cpu_count() or 1
+    threads = oracle_threads()
     n, m = trace.n_hosts, trace.n_devices
 
     def subset(k):
@@ -501,29 +652,30 @@ def cpu_baseline(trace, target_s=12.0):
         chunks = [tg.Chunk(remap[c.resource], c.kind, c.start, c.end) for c in trace.chunks if c.resource in keep]
         return tg.Trace(len(hosts), len(devs), chunks, trace.regions)
 
-    k = max(1, min(n, m, threads))
-    sub = subset(k)
-    t0 = time.perf_counter()
-    oracle.compute(sub, threads=threads)
-    dt = time.perf_counter() - t0
-    # grow the sample to about target_s of work
-    while dt < target_s / 3 and k < max(n, m):
-        k = min(max(n, m), k * 2)
+    def sized(k, thr, target):
+        # grow the sample until one run takes about `target` seconds
         sub = subset(k)
         t0 = time.perf_counter()
-        oracle.compute(sub, threads=threads)
+        oracle.compute(sub, threads=thr)
         dt = time.perf_counter() - t0
-    # the same oracle on one thread, on a smaller sample of the same shape
-    k1 = max(1, min(n, m, 16))
-    sub1 = subset(k1)
-    t0 = time.perf_counter()
-    oracle.compute(sub1, threads=1)
-    dt1 = time.perf_counter() - t0
+        while dt < target / 2 and k < max(n, m):
+            k = min(max(n, m), k * 2)
+            sub = subset(k)
+            t0 = time.perf_counter()
+            oracle.compute(sub, threads=thr)
+            dt = time.perf_counter() - t0
+        return sub
+
+    sub = sized(max(1, min(n, m, threads)), threads, target_s)
+    dt = timed_median(lambda: oracle.compute(sub, threads=threads))
+    sub1 = sized(1, 1, target_1_s)
+    dt1 = timed_median(lambda: oracle.compute(sub1, threads=1))
     return {"value": sub.n_events / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
-            "sample": "%d host ranks + %d devices of the workload (%d records), all %d regions, %.1f s"
+            "cpu": cpu_model(), "timing": "1 warm-up, median of 5",
+            "sample": "%d host ranks + %d devices of the workload (%d records), all %d regions, %.2f s per run"
                       % (sub.n_hosts, sub.n_devices, sub.n_events, len(trace.regions), dt),
             "single_thread": {"value": sub1.n_events / dt1, "unit": "events/s", "cores": 1,
-                              "sample": "%d host ranks + %d devices (%d records), all %d regions, %.1f s"
+                              "sample": "%d host ranks + %d devices (%d records), all %d regions, %.2f s per run"
                                         % (sub1.n_hosts, sub1.n_devices, sub1.n_events, len(trace.regions), dt1)}}
 
 
@@ -633,10 +785,6 @@ def load_path_traffic(workload):
         return None
 
 
-HBM_PEAK_GBS = 8000.0
-ALGO_BYTES_PER_RECORD = 16  # each record's start and end, read once
-
-
 def path_hbm(r, workload):
     """Whole-path HBM figures of the single-trace leg: counter-measured bytes of a
     build over the sum of the kernels' stage times, against the chip's peak and
@@ -708,9 +856,12 @@ def main():
     ap.add_argument("--batched-traces", type=int, default=1000)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true", help="profiling aid: run only the serving leg")
-    ap.add_argument("--serving-queries", type=int, default=400)
+    ap.add_argument("--serving-queries", type=int, default=2000)
     ap.add_argument("--serving-lambdas", default="2000,5000,10000,20000")
-    ap.add_argument("--serving-host-lambdas", default="2000,5000", help="runs with payloads in host memory")
+    ap.add_argument("--serving-host-lambdas", default="2000,5000,10000,20000",
+                    help="runs with payloads in host memory")
+    ap.add_argument("--no-small", action="store_true", help="skip the small-trace latency leg")
+    ap.add_argument("--no-mid", action="store_true", help="skip the mid-trace leg")
     ap.add_argument("--no-entered", action="store_true", help="skip the regions-entered-repeatedly leg")
     ap.add_argument("--no-streams", action="store_true")
     ap.add_argument("--streams-only", action="store_true", help="run only the stream concurrency leg")
@@ -790,6 +941,14 @@ def main():
         log("cpu baseline (oracle on a sample)")
         out["cpu_baseline"] = cpu_baseline(trace)
         log("cpu baseline: %s" % out["cpu_baseline"])
+    if not args.no_small:
+        log("small-trace leg")
+        out["small"] = small_leg(hp)
+        log("small: %s" % out["small"])
+    if not args.no_mid:
+        log("mid-trace leg")
+        out["mid"] = mid_leg(hp, args.steps, args.warmup, args.tune_cache)
+        log("mid: %s" % {k: v for k, v in out["mid"].items() if k != "stage_ms"})
     if not args.no_entered:
         log("regions entered repeatedly")
         out["entered_regions"] = entered_regions_leg(hp, trace)

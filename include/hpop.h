@@ -73,6 +73,7 @@ typedef int32_t hpop_status;
 
 /* flags of hpop_metrics_compute_all and hpop_batch_compute */
 #define HPOP_FORCE_REBUILD 1u /* rebuild the merged interval lists even if no record was added */
+#define HPOP_NO_GRAPH 2u      /* launch the kernels one by one instead of replaying the captured HIP graph */
 
 typedef struct hpop_session hpop_session;
 typedef struct hpop_server hpop_server;

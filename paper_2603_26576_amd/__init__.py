@@ -42,6 +42,7 @@ HPOP_DEV_MEMOP = 4
 HPOP_MEM_HOST = 0
 HPOP_MEM_DEVICE = 1
 HPOP_FORCE_REBUILD = 1
+HPOP_NO_GRAPH = 2
 
 RATIO_FIELDS = ["host_pe", "host_mpi_pe", "host_mpi_lb", "host_mpi_ce", "host_oe",
                 "dev_pe", "dev_lb", "dev_ce", "dev_oe"]

@@ -591,7 +591,7 @@ hpop_status Engine::run(hpop_session* const* ss, int k, uint32_t flags, hpop_met
     return run(ss, k, flags, out, timing, err);
   }
   built = false;
-  if (build && use_graphs && !timing) {
+  if (build && use_graphs && !timing && !(flags & HPOP_NO_GRAPH)) {
     // capture the whole launch sequence once per plan and replay it
     if (!ws.graph_exec) {
       hipGraph_t g = nullptr;
@@ -977,7 +977,7 @@ hpop_status hpop_num_regions(const hpop_session* s, int32_t* out) {
 hpop_status hpop_metrics_compute_all(hpop_session* s, uint32_t flags, hpop_metric_tree* out) {
   HPOP_GUARD_BEGIN
   if (!s) return fail(nullptr, HPOP_E_ARG, "null session");
-  if (flags & ~HPOP_FORCE_REBUILD) return fail(s, HPOP_E_ARG, "unknown flags");
+  if (flags & ~(HPOP_FORCE_REBUILD | HPOP_NO_GRAPH)) return fail(s, HPOP_E_ARG, "unknown flags");
   if (!s->regions.empty() && !out) return fail(s, HPOP_E_ARG, "null output");
   std::string err;
   hpop_session* one[1] = {s};
@@ -1041,7 +1041,7 @@ hpop_status hpop_region_format(hpop_session* s, int32_t region, int32_t format, 
 hpop_status hpop_batch_compute(hpop_session* const* sessions, int32_t k, uint32_t flags, hpop_metric_tree* out) {
   HPOP_GUARD_BEGIN
   if (!sessions || k <= 0) return fail(nullptr, HPOP_E_ARG, "empty session list");
-  if (flags & ~HPOP_FORCE_REBUILD) return fail(nullptr, HPOP_E_ARG, "unknown flags");
+  if (flags & ~(HPOP_FORCE_REBUILD | HPOP_NO_GRAPH)) return fail(nullptr, HPOP_E_ARG, "unknown flags");
   for (int i = 0; i < k; ++i) {
     if (!sessions[i]) return fail(nullptr, HPOP_E_ARG, "null session in list");
     if (sessions[i]->device != sessions[0]->device) return fail(nullptr, HPOP_E_ARG, "sessions on different devices");

@@ -6,6 +6,7 @@ import os
 import shutil
 import subprocess
 import sys
+import time
 
 import numpy as np
 
@@ -24,11 +25,24 @@ def test_more_than_one_gpu_is_refused():
 
 def test_cpu_baseline_object():
     tr = tg.small()
-    out = bench.cpu_baseline(tr, target_s=0.3)
+    out = bench.cpu_baseline(tr, target_s=0.3, target_1_s=0.1)
     assert out["kind"] == "oracle" and out["unit"] == "events/s"
     assert out["cores"] >= 1 and out["value"] > 0 and isinstance(out["sample"], str)
+    assert out["timing"] == "1 warm-up, median of 5"
+    assert out["cpu"]["logical_cpus"] == os.cpu_count() and out["cpu"]["model"]
     one = out["single_thread"]
     assert one["cores"] == 1 and one["value"] > 0
+
+
+def test_timed_median_warms_up_then_takes_the_median():
+    calls = []
+
+    def fn():
+        calls.append(time.perf_counter())
+        time.sleep(0.02 if len(calls) == 1 else 0.001)  # a slow first (warm-up) call
+
+    dt = bench.timed_median(fn, reps=5)
+    assert len(calls) == 6 and dt < 0.015
 
 
 def test_traffic_records_are_tied_to_the_kernel_sources(tmp_path, monkeypatch):

@@ -302,7 +302,14 @@ def test_repeated_builds_identical_and_graph_replay():
         for _ in range(5):
             got = engine_results(s, tr, flags=hp.HPOP_FORCE_REBUILD)
             assert_same(got, want, "replay")
-        assert hp.hpop_session_get_info(s).graph_replays >= 4
+        replays = hp.hpop_session_get_info(s).graph_replays
+        assert replays >= 4
+        # kernels launched one by one: same results, no replay
+        for _ in range(2):
+            got = engine_results(s, tr, flags=hp.HPOP_FORCE_REBUILD | hp.HPOP_NO_GRAPH)
+            assert_same(got, want, "direct launches")
+        assert hp.hpop_session_get_info(s).graph_replays == replays
+        assert_same(engine_results(s, tr, flags=hp.HPOP_FORCE_REBUILD), want, "replay after direct launches")
     finally:
         hp.hpop_session_destroy(s)
 
