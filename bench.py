@@ -430,6 +430,13 @@ def streams_leg(hp, steps, warmup, n_devices=256, streams=4, per_device=100_000,
             "stream_eff": trees[0].stream_eff, "mean_active": trees[0].mean_active}
 
 
+# device memory taken up front for the serving sessions' lists: every
+# component of a run (about 1.5 per record over the levels, 16 B each, for
+# 2000 queries of 2.2e5 records and 3.2e7 warm records) with room for lists
+# that move as they grow
+SERVING_LIST_HEAP = 32 << 30
+
+
 def serving_workload(n_queries, seed=1005, n_sessions=32, ranks=16, streams=4, warm=1_000_000, device=True):
     """Record streams of the serving workload: per session one trace of
     `ranks` hosts and devices, long enough for its warm-up slice and every
@@ -505,7 +512,7 @@ def serving_run(hp, W, lam, host, keep=False):
     n_queries = int(sizes.size)
     mem = hp.HPOP_MEM_HOST if host else hp.HPOP_MEM_DEVICE
     srv = hp.hpop_server_create(max_sessions=n_sessions, max_inflight=n_sessions, queue_capacity=1 << 16,
-                                mem_budget_bytes=64 << 30)
+                                mem_budget_bytes=64 << 30, list_heap_bytes=SERVING_LIST_HEAP)
     kept = {"warm": [], "queries": []}
     try:
         sids = [hp.hpop_server_open_session(srv, ranks, ranks, S["origin"]) for S in W["sess"]]
@@ -524,6 +531,7 @@ def serving_run(hp, W, lam, host, keep=False):
             kept["warm"].append((i, closes[i], t1, list(cursors[i])))
             closes[i] = t1
         warm_trees = [hp.hpop_server_wait(srv, t) for t in warm_t]
+        hp.hpop_server_reset_stats(srv)  # the figures below cover the timed queries only
         base = hp.hpop_server_get_stats(srv)
         plan = []
         for q in range(n_queries):
@@ -554,10 +562,16 @@ def serving_run(hp, W, lam, host, keep=False):
            "mean_batch": round((st.mean_batch * st.device_steps - base.mean_batch * base.device_steps)
                                / steps_run, 2),
            "busy_retries": busy,
-           # over the server's life, warm-up included
+           # over the timed queries (statistics restarted after the warm-up)
            "max_submit_us": round(st.max_submit_us, 1), "max_step_us": round(st.max_step_us, 1),
-           "pinned_blocks": int(st.pinned_blocks),
-           "max_pinned_alloc_us": round(st.max_pinned_alloc_us, 1)}
+           "host_staging_bytes": int(st.host_staging_bytes),
+           "max_host_staging_used": int(st.max_host_staging_used),
+           "staging_alloc_us": round(st.max_pinned_alloc_us, 1),
+           # longest time of each phase of a device step, in us
+           "max_phase_us": {k: round(getattr(st, "max_%s_us" % k), 1)
+                            for k in ("prep", "grow", "wait", "h2d", "build", "move", "splice", "region")},
+           "mean_phase_us": {k: round(getattr(st, "mean_%s_us" % k), 1)
+                             for k in ("prep", "grow", "wait", "h2d", "build", "move", "splice", "region")}}
     if keep:
         kept["warm_trees"] = warm_trees
         kept["query_trees"] = list(zip(reg, glob))
@@ -600,7 +614,7 @@ def serving_leg(hp, lambdas, n_queries, seed=1005, n_sessions=32, ranks=16, stre
         results.append(serving_run(hp, W, lam, host))
         log("serving lambda=%d %s: %s" % (lam, "host" if host else "device", results[-1]))
     return {"sessions": n_sessions, "ranks": ranks, "devices": ranks, "streams": streams,
-            "warm_events_per_session": warm,
+            "warm_events_per_session": warm, "list_heap_bytes": SERVING_LIST_HEAP,
             "payload": "device-resident, or host memory (copied at submission) where a run says so",
             "latency": "scheduled arrival to trees on the host",
             "runs": results}

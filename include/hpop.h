@@ -360,8 +360,12 @@ typedef struct {
     int32_t max_sessions;       /* sessions the server may open */
     int32_t max_inflight;       /* queries admitted per device step (1 .. 4096) */
     int32_t queue_capacity;     /* queued queries before hpop_server_submit returns HPOP_E_BUSY */
-    int32_t reserved;
+    int32_t host_staging_mib;   /* page-locked MiB holding host payloads of queued queries: > 0 taken at
+                                   hpop_server_create; 0: 1024 MiB taken at the first host payload */
     int64_t mem_budget_bytes;   /* device bytes for staged records of admitted queries */
+    int64_t list_heap_bytes;    /* device bytes taken at creation for the session lists (0: grown on
+                                   demand); lists move within it as they grow and are compacted into
+                                   a new heap only when it is full */
 } hpop_server_config;
 
 typedef struct {
@@ -372,8 +376,21 @@ typedef struct {
     double p50_us, p99_us, max_us;  /* submit -> result latency of finished queries */
     double max_submit_us;       /* longest hpop_server_submit (host payloads: includes their copy) */
     double max_step_us;         /* longest device step of the worker, admission to results */
-    int64_t pinned_blocks;      /* page-locked blocks allocated for host payloads */
-    double max_pinned_alloc_us; /* longest single allocation of such a block */
+    int64_t host_staging_bytes; /* page-locked staging area of host payloads (0 before it is taken) */
+    double max_pinned_alloc_us; /* its allocation */
+    int64_t max_host_staging_used; /* most of it held by queued payloads at once */
+    /* Longest time of each phase of one device step. Host clocks: prep =
+     * admission to the first enqueue (planning, growth of device buffers),
+     * grow = the device allocations within prep, wait = the worker blocked on
+     * the step's end. Device times (HIP events on the server stream): h2d =
+     * host payload copies, build = bucketed build of the new records, move =
+     * list moves, splice = the merge into the session lists, region = the
+     * region trees and the copies of the results. */
+    double max_prep_us, max_grow_us, max_wait_us;
+    double max_h2d_us, max_build_us, max_move_us, max_splice_us, max_region_us;
+    /* the same phases' mean per step */
+    double mean_prep_us, mean_grow_us, mean_wait_us;
+    double mean_h2d_us, mean_build_us, mean_move_us, mean_splice_us, mean_region_us;
 } hpop_server_stats;
 
 hpop_status hpop_server_create(const hpop_server_config* cfg, hpop_server** out);
@@ -383,12 +400,15 @@ hpop_status hpop_server_destroy(hpop_server* srv);
 hpop_status hpop_server_open_session(hpop_server* srv, int32_t n_hosts, int32_t n_devices,
                                      int64_t t_origin, int32_t* out_sid);
 /* Non-blocking. Records in `chunks` are HPOP_MEM_HOST (copied into the
- * server's page-locked memory before return) or HPOP_MEM_DEVICE (read by the
- * server's stream; keep them unchanged until the ticket completes). Records
- * are validated on the device in both cases: a query holding an invalid one
- * (start < 0, start > end or end >= 2^62) is not applied and its
+ * server's page-locked staging area before return) or HPOP_MEM_DEVICE (read
+ * by the server's stream; keep them unchanged until the ticket completes).
+ * Records are validated on the device in both cases: a query holding an
+ * invalid one (start < 0, start > end or end >= 2^62) is not applied and its
  * hpop_server_wait returns HPOP_E_BAD_INTERVAL. Returns HPOP_E_BUSY when the
- * queue or the memory budget is full (nothing is copied then). */
+ * queue, the memory budget or the staging area is full (nothing is copied
+ * then); HPOP_E_ARG for a host payload larger than the whole staging area.
+ * No call on this path allocates page-locked memory except the first host
+ * payload's, when the staging area is taken then. */
 hpop_status hpop_server_submit(hpop_server* srv, int32_t sid, const hpop_event_chunk* chunks,
                                int32_t n_chunks, int32_t mem_space, int64_t t0, int64_t t1,
                                uint64_t* out_ticket);
@@ -397,6 +417,9 @@ hpop_status hpop_server_submit(hpop_server* srv, int32_t sid, const hpop_event_c
 hpop_status hpop_server_wait(hpop_server* srv, uint64_t ticket, int64_t timeout_ns,
                              hpop_metric_tree* out_region, hpop_metric_tree* out_global);
 hpop_status hpop_server_get_stats(hpop_server* srv, hpop_server_stats* out);
+/* Restart the statistics (counts, latencies, maxima, means) from now, e.g.
+ * after a warm-up; the staging area's figures are kept. */
+hpop_status hpop_server_reset_stats(hpop_server* srv);
 
 /* One query of an arrival schedule replayed by hpop_server_replay. */
 typedef struct {

@@ -80,15 +80,23 @@ class hpop_session_info(ctypes.Structure):
 
 class hpop_server_config(ctypes.Structure):
     _fields_ = [("max_sessions", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("queue_capacity", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("mem_budget_bytes", ctypes.c_int64)]
+                ("queue_capacity", ctypes.c_int32), ("host_staging_mib", ctypes.c_int32),
+                ("mem_budget_bytes", ctypes.c_int64), ("list_heap_bytes", ctypes.c_int64)]
 
 
 class hpop_server_stats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("events", ctypes.c_int64), ("device_steps", ctypes.c_int64),
                 ("mean_batch", ctypes.c_double), ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("max_us", ctypes.c_double), ("max_submit_us", ctypes.c_double), ("max_step_us", ctypes.c_double),
-                ("pinned_blocks", ctypes.c_int64), ("max_pinned_alloc_us", ctypes.c_double)]
+                ("host_staging_bytes", ctypes.c_int64), ("max_pinned_alloc_us", ctypes.c_double),
+                ("max_host_staging_used", ctypes.c_int64),
+                ("max_prep_us", ctypes.c_double), ("max_grow_us", ctypes.c_double), ("max_wait_us", ctypes.c_double),
+                ("max_h2d_us", ctypes.c_double), ("max_build_us", ctypes.c_double), ("max_move_us", ctypes.c_double),
+                ("max_splice_us", ctypes.c_double), ("max_region_us", ctypes.c_double),
+                ("mean_prep_us", ctypes.c_double), ("mean_grow_us", ctypes.c_double), ("mean_wait_us", ctypes.c_double),
+                ("mean_h2d_us", ctypes.c_double), ("mean_build_us", ctypes.c_double),
+                ("mean_move_us", ctypes.c_double), ("mean_splice_us", ctypes.c_double),
+                ("mean_region_us", ctypes.c_double)]
 
 
 class hpop_replay_query(ctypes.Structure):
@@ -142,6 +150,7 @@ _SIGS = {
     "hpop_server_wait": (_I32, [_P, _U64, _I64, ctypes.POINTER(hpop_metric_tree),
                                 ctypes.POINTER(hpop_metric_tree)]),
     "hpop_server_get_stats": (_I32, [_P, ctypes.POINTER(hpop_server_stats)]),
+    "hpop_server_reset_stats": (_I32, [_P]),
     "hpop_server_last_error": (ctypes.c_char_p, [_P]),
     "hpop_tree_format": (_I32, [ctypes.POINTER(hpop_metric_tree), _I32, ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
     "hpop_region_format": (_I32, [_P, _I32, _I32, ctypes.c_char_p, _I64, ctypes.POINTER(_I64)]),
@@ -395,8 +404,10 @@ def hpop_autotune(sessions, cache_path=None):
     return out
 
 
-def hpop_server_create(max_sessions=64, max_inflight=64, queue_capacity=4096, mem_budget_bytes=8 << 30):
-    cfg = hpop_server_config(max_sessions, max_inflight, queue_capacity, 0, mem_budget_bytes)
+def hpop_server_create(max_sessions=64, max_inflight=64, queue_capacity=4096, mem_budget_bytes=8 << 30,
+                       host_staging_mib=0, list_heap_bytes=0):
+    cfg = hpop_server_config(max_sessions, max_inflight, queue_capacity, host_staging_mib, mem_budget_bytes,
+                             list_heap_bytes)
     h = _P()
     _check(lib().hpop_server_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h.value
@@ -442,6 +453,10 @@ def hpop_server_get_stats(srv):
     out = hpop_server_stats()
     _check_srv(lib().hpop_server_get_stats(srv, ctypes.byref(out)), srv)
     return out
+
+
+def hpop_server_reset_stats(srv):
+    _check_srv(lib().hpop_server_reset_stats(srv), srv)
 
 
 def hpop_server_replay(srv, queries, mem_space):

@@ -12,6 +12,8 @@
 namespace hpop {
 
 extern thread_local std::string g_thread_error;
+// microseconds this thread has spent in device and page-locked allocations (statistics)
+extern thread_local double g_alloc_us;
 const char* status_name(hpop_status s);
 int slot_of_kind(int kind);
 long long tuning_key(const hpop_tuning& t);
@@ -63,6 +65,7 @@ struct Workspace {
   DevBuf meta, elems, elems2, comp[3], compn[3];
   PinnedBuf pinned;       // trees and status words copied back
   PinnedBuf pinned_desc;  // descriptor uploads
+  hipEvent_t desc_done = nullptr;  // recorded after the last upload from pinned_desc
   Plan plan{};
   ChunkDesc* d_chunks = nullptr;
   SegDesc* d_segs = nullptr;

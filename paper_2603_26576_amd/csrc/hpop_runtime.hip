@@ -24,6 +24,7 @@ static_assert(sizeof(Tree) == sizeof(hpop_metric_tree), "tree layout");
 namespace hpop {
 
 thread_local std::string g_thread_error;
+thread_local double g_alloc_us = 0.0;
 
 const char* status_name(hpop_status s) {
   switch (s) {
@@ -94,9 +95,11 @@ void* Alloc::get(size_t bytes) {
   if (bytes == 0) bytes = 256;
   void* p = nullptr;
   if (fn_alloc) return fn_alloc(ctx, bytes, (void*)stream);
+  const auto t0 = std::chrono::steady_clock::now();
   int dev = 0;
   hipMemPool_t pool = hipGetDevice(&dev) == hipSuccess ? library_pool(dev) : nullptr;
   const hipError_t e = pool ? hipMallocFromPoolAsync(&p, bytes, pool, stream) : hipMallocAsync(&p, bytes, stream);
+  g_alloc_us += std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
   if (e != hipSuccess) {
     (void)hipGetLastError();
     p = nullptr;
@@ -140,7 +143,10 @@ bool PinnedBuf::reserve(size_t need) {
   size_t nb = std::max(need, bytes * 2);
   nb = std::max<size_t>(nb, 4096);
   void* q = nullptr;
-  if (hipHostMalloc(&q, nb, hipHostMallocDefault) != hipSuccess) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const hipError_t e = hipHostMalloc(&q, nb, hipHostMallocDefault);
+  g_alloc_us += std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  if (e != hipSuccess) {
     (void)hipGetLastError();
     return false;
   }
@@ -296,7 +302,13 @@ void Workspace::release(Alloc& a) {
   for (auto& c : compn) c.release(a);
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   graph_exec = nullptr;
+  if (desc_done) {
+    (void)hipEventSynchronize(desc_done);
+    (void)hipEventDestroy(desc_done);
+  }
+  desc_done = nullptr;
   pinned.release();
+  pinned_desc.release();
 }
 
 // ----------------------------------------------------------------------------
@@ -447,13 +459,15 @@ hpop_status Engine::upload(std::string& err) {
                "upload region intervals");
     return HPOP_OK;
   }
-  // descriptors go through pinned memory so the copies are stream-ordered
+  // descriptors go through pinned memory so the copies are stream-ordered;
+  // the previous upload from this buffer must have left it (an event, not a
+  // wait for everything else queued on the stream)
+  if (ws.desc_done) HPOP_HIP(hipEventSynchronize(ws.desc_done), "hipEventSynchronize");
+  else HPOP_HIP(hipEventCreateWithFlags(&ws.desc_done, hipEventDisableTiming), "hipEventCreate");
   if (!ws.pinned_desc.reserve(bc + bs + br + bi + 64)) {
     err = "pinned host allocation failed";
     return HPOP_E_OOM;
   }
-  // the previous upload from this buffer must have finished
-  HPOP_HIP(hipStreamSynchronize(alloc.stream), "hipStreamSynchronize");
   char* h = (char*)ws.pinned_desc.ptr;
   if (bc) memcpy(h, h_chunks.data(), bc);
   if (bs) memcpy(h + bc, h_segs.data(), bs);
@@ -466,6 +480,7 @@ hpop_status Engine::upload(std::string& err) {
   if (bi)
     HPOP_HIP(hipMemcpyAsync(ws.d_ivls, h + bc + bs + br, bi, hipMemcpyHostToDevice, alloc.stream),
              "upload region intervals");
+  HPOP_HIP(hipEventRecord(ws.desc_done, alloc.stream), "hipEventRecord");
   return HPOP_OK;
 }
 
@@ -594,6 +609,8 @@ hpop_status Engine::run(hpop_session* const* ss, int k, uint32_t flags, hpop_met
   if (build && use_graphs && !timing && !(flags & HPOP_NO_GRAPH)) {
     // capture the whole launch sequence once per plan and replay it
     if (!ws.graph_exec) {
+      // capture starts on an idle stream: the descriptor upload has landed
+      HPOP_HIP(hipStreamSynchronize(alloc.stream), "hipStreamSynchronize");
       hipGraph_t g = nullptr;
       HPOP_HIP(hipStreamBeginCapture(alloc.stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
       hpop_status st = enqueue(true, false, err);

@@ -346,47 +346,79 @@ using namespace hpop;
 
 namespace {
 
-// Page-locked host blocks reused across queries (best fit by size), so a
-// host payload is copied once, at submission, and DMA-ed from there.
-struct PinnedPool {
+// Page-locked staging of host payloads: one area, taken once, cut first-fit
+// into 256-byte-aligned ranges (freed ranges merge with their neighbours). A
+// payload is copied into it once, at submission, and DMA-ed from there; a
+// payload that does not fit while others hold the area waits (HPOP_E_BUSY),
+// so the request path never allocates page-locked memory.
+struct HostArena {
   std::mutex mu;
-  std::multimap<size_t, void*> free_blocks;
-  std::vector<std::pair<void*, size_t>> all;
-  double max_alloc_us = 0.0;  // longest hipHostMalloc so far
-  void* get(size_t bytes, size_t& got) {
-    std::lock_guard<std::mutex> g(mu);
-    auto it = free_blocks.lower_bound(bytes);
-    if (it != free_blocks.end()) {
-      got = it->first;
-      void* p = it->second;
-      free_blocks.erase(it);
-      return p;
-    }
-    size_t b = 4096;
-    while (b < bytes) b <<= 1;
-    void* p = nullptr;
+  char* base = nullptr;
+  size_t bytes = 0;
+  std::map<size_t, size_t> free_ranges;  // offset -> length
+  size_t used = 0, max_used = 0;
+  double alloc_us = 0.0;
+  static size_t round_up(size_t n) { return (n + 255) & ~size_t(255); }
+  // takes the area (called with mu held); false if the allocation failed
+  bool take(size_t n) {
     const auto t = std::chrono::steady_clock::now();
-    if (hipHostMalloc(&p, b, hipHostMallocDefault) != hipSuccess) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, n, hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
-      return nullptr;
+      return false;
     }
-    max_alloc_us = std::max(max_alloc_us,
-                            std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t).count());
-    all.push_back({p, b});
-    got = b;
-    return p;
+    alloc_us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t).count();
+    base = (char*)p;
+    bytes = n;
+    free_ranges.clear();
+    free_ranges[0] = n;
+    return true;
   }
-  void put(void* p, size_t bytes) {
+  // a range of n bytes, or nullptr if none is free now
+  char* get(size_t n) {
+    std::lock_guard<std::mutex> g(mu);
+    n = round_up(n);
+    for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+      if (it->second < n) continue;
+      const size_t off = it->first, len = it->second;
+      free_ranges.erase(it);
+      if (len > n) free_ranges[off + n] = len - n;
+      used += n;
+      max_used = std::max(max_used, used);
+      return base + off;
+    }
+    return nullptr;
+  }
+  void put(char* p, size_t n) {
     if (!p) return;
     std::lock_guard<std::mutex> g(mu);
-    free_blocks.insert({bytes, p});
+    n = round_up(n);
+    used -= n;
+    size_t off = (size_t)(p - base), len = n;
+    auto next = free_ranges.lower_bound(off);
+    if (next != free_ranges.end() && next->first == off + len) {
+      len += next->second;
+      next = free_ranges.erase(next);
+    }
+    if (next != free_ranges.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        off = prev->first;
+        len += prev->second;
+        free_ranges.erase(prev);
+      }
+    }
+    free_ranges[off] = len;
   }
   void release() {
-    for (auto& b : all) (void)hipHostFree(b.first);
-    all.clear();
-    free_blocks.clear();
+    if (base) (void)hipHostFree(base);
+    base = nullptr;
+    bytes = 0;
+    free_ranges.clear();
   }
 };
+
+constexpr size_t kDefaultStagingBytes = size_t(1024) << 20;
 
 // One contiguous copy of a host payload into its page-locked block.
 struct CopySpan {
@@ -439,7 +471,7 @@ struct Query {
   int64_t t0 = 0, t1 = 0;
   std::vector<hpop_event_chunk> chunks;  // device pointers, or pointers into `host`
   int64_t* host = nullptr;               // copied host records (pinned): start arrays then end arrays
-  size_t host_words = 0, host_block = 0;
+  size_t host_words = 0;
   long long n_records = 0;
   std::chrono::steady_clock::time_point submitted, finished;
   bool done = false;
@@ -488,12 +520,20 @@ struct hpop_server {
   DevBuf heap;  // every session list, Comp entries; bump-allocated, compacted when full
   long long heap_cap = 0, heap_used = 0;
   PinnedBuf h_out;
-  PinnedPool pinned;  // host payloads of queued queries
+  HostArena staging;  // host payloads of queued queries
   long long pool_cap = 0;
   // statistics
   std::vector<double> lat_us;
   long long completed = 0, events = 0, steps = 0, batched = 0;
   double max_submit_us = 0.0, max_step_us = 0.0;
+  // phases of a step: host clocks and HIP events on the server stream
+  double max_prep_us = 0.0, max_grow_us = 0.0, max_wait_us = 0.0;
+  double max_phase_us[5] = {0, 0, 0, 0, 0};  // h2d, move, build, splice, region
+  double sum_phase_us[5] = {0, 0, 0, 0, 0};
+  double sum_prep_us = 0.0, sum_grow_us = 0.0, sum_wait_us = 0.0;
+  hipEvent_t ev[6] = {};
+  bool have_events = false;
+  double step_prep_us = 0.0, step_wait_us = 0.0;  // of the step just run (set by run_step)
 };
 
 namespace {
@@ -535,6 +575,11 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   std::vector<ServReq> reqs(nq);
   std::vector<long long> level_new(S->lists.size(), 0);
   size_t hoff = 0;
+  const auto t_start = std::chrono::steady_clock::now();
+  auto mark = [&](int i) {
+    if (S->have_events) (void)hipEventRecord(S->ev[i], st);
+  };
+  mark(0);
   for (int q = 0; q < nq; ++q) {
     Query* Q = batch[q];
     const SessionState& ss = S->sessions[Q->sid];
@@ -591,6 +636,7 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
       for (int l = d.slot; l < nlev; ++l) level_new[ss.list_begin + ch.resource * 3 + l] += ch.count;
     }
   }
+  mark(1);  // payload copies
   hpop_tuning tun{};
   hpop_status rc = En.assemble_plan(tun, seg_count, seg_host, std::max(1, nq), 0, err);
   if (rc != HPOP_OK) return rc;
@@ -686,6 +732,7 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
       return HPOP_E_HIP;
     }
   }
+  mark(2);  // list moves
   if (new_heap.ptr) {
     S->heap.release(A);  // stream-ordered: after the moves out of it
     S->heap = new_heap;
@@ -715,6 +762,7 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   rc = En.upload(err);
   if (rc == HPOP_OK) rc = En.enqueue(true, false, err);
   if (rc != HPOP_OK) return rc;
+  mark(3);  // build of the new records
   char* h = (char*)S->h_out.ptr;
   memcpy(h, ld.data(), b_lists);
   memcpy(h + b_lists, items.data(), b_items);
@@ -741,6 +789,7 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
                          (const ServItem*)S->d_items.ptr, P, (ListDev*)S->d_lists.ptr, (Elem*)S->d_pool.ptr,
                          (const ServCtl*)S->d_ctl.ptr);
     }
+    mark(4);  // prep and splice
     // on a scratch overflow no list was written and these trees are discarded
     hipLaunchKernelGGL(k_serv_region, dim3((unsigned)(2 * nq)), dim3(256), 0, st, (const ServReq*)S->d_reqs.ptr,
                        (const ListDev*)S->d_lists.ptr, (const long long*)S->d_frontier.ptr, (Tree*)S->d_trees.ptr);
@@ -750,7 +799,12 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     if (e == hipSuccess && b_lists)
       e = hipMemcpyAsync(o + b_trees, S->d_lists.ptr, b_lists, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipMemcpyAsync(o + b_trees + b_lists, P.owner_err, nq * 4, hipMemcpyDeviceToHost, st);
+    mark(5);  // region trees and result copies
+    const auto t_sync = std::chrono::steady_clock::now();
+    if (attempt == 0) S->step_prep_us = std::chrono::duration<double, std::micro>(t_sync - t_start).count();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    S->step_wait_us +=
+        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t_sync).count();
     if (e != hipSuccess) return err = std::string("serving step: ") + hipGetErrorString(e), HPOP_E_HIP;
     ServCtl got;
     memcpy(&got, hres, sizeof got);
@@ -766,6 +820,15 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     if (attempt == 3) {
       err = "scratch pool kept overflowing";
       return HPOP_E_OOM;
+    }
+  }
+  if (S->have_events) {
+    for (int i = 0; i < 5; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, S->ev[i], S->ev[i + 1]) == hipSuccess) {
+        S->max_phase_us[i] = std::max(S->max_phase_us[i], 1e3 * (double)ms);
+        S->sum_phase_us[i] += 1e3 * (double)ms;
+      }
     }
   }
   unsigned long long slot_over;
@@ -819,18 +882,27 @@ void worker_loop(hpop_server* S) {
     const auto t_admit = std::chrono::steady_clock::now();
     std::string err;
     hpop_status st;
+    S->step_prep_us = S->step_wait_us = 0.0;
+    const double alloc0 = g_alloc_us;
     {
       std::lock_guard<std::mutex> sg(S->state_mu);
       st = run_step(S, batch, err);
     }
+    const double grow_us = g_alloc_us - alloc0;
     // every step ends synchronised: the host payloads have been copied
     for (Query* Q : batch) {
-      S->pinned.put(Q->host, Q->host_block);
+      S->staging.put((char*)Q->host, Q->host_words * 8);
       Q->host = nullptr;
     }
     const auto now = std::chrono::steady_clock::now();
     lk.lock();
     ++S->steps;
+    S->max_prep_us = std::max(S->max_prep_us, S->step_prep_us);
+    S->max_wait_us = std::max(S->max_wait_us, S->step_wait_us);
+    S->max_grow_us = std::max(S->max_grow_us, grow_us);
+    S->sum_prep_us += S->step_prep_us;
+    S->sum_wait_us += S->step_wait_us;
+    S->sum_grow_us += grow_us;
     S->batched += (long long)batch.size();
     S->max_step_us = std::max(S->max_step_us, std::chrono::duration<double, std::micro>(now - t_admit).count());
     for (Query* Q : batch) {
@@ -889,14 +961,37 @@ hpop_status hpop_server_create(const hpop_server_config* cfg, hpop_server** out)
     if (!cfg || !out) return srv_fail(nullptr, HPOP_E_ARG, "null argument");
     *out = nullptr;
     if (cfg->max_sessions <= 0 || cfg->max_inflight <= 0 || cfg->max_inflight > 4096 || cfg->queue_capacity <= 0 ||
-        cfg->mem_budget_bytes <= 0)
-      return srv_fail(nullptr, HPOP_E_ARG, "server limits must be positive (max_inflight <= 4096)");
+        cfg->mem_budget_bytes <= 0 || cfg->host_staging_mib < 0 || cfg->list_heap_bytes < 0)
+      return srv_fail(nullptr, HPOP_E_ARG,
+                      "server limits must be positive (max_inflight <= 4096, host_staging_mib >= 0)");
     hpop_server* S = new hpop_server();
     S->cfg = *cfg;
     if (hipGetDevice(&S->device) != hipSuccess ||
         hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
       delete S;
       return srv_fail(nullptr, HPOP_E_HIP, "stream creation failed");
+    }
+    if (cfg->host_staging_mib > 0 && !S->staging.take((size_t)cfg->host_staging_mib << 20)) {
+      (void)hipStreamDestroy(S->stream);
+      delete S;
+      return srv_fail(nullptr, HPOP_E_OOM, "page-locked staging allocation failed");
+    }
+    S->have_events = true;
+    for (hipEvent_t& e : S->ev)
+      if (hipEventCreate(&e) != hipSuccess) S->have_events = false;
+    if (cfg->list_heap_bytes > 0) {
+      const long long cap = cfg->list_heap_bytes / (long long)sizeof(Comp);
+      if (!S->heap.reserve(S->alloc, (size_t)cap * sizeof(Comp), false) ||
+          hipStreamSynchronize(S->stream) != hipSuccess) {
+        S->heap.release(S->alloc);
+        S->staging.release();
+        for (hipEvent_t e : S->ev)
+          if (e) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(S->stream);
+        delete S;
+        return srv_fail(nullptr, HPOP_E_OOM, "device allocation of the list heap failed");
+      }
+      S->heap_cap = cap;
     }
     S->alloc.stream = S->stream;
     S->engine.alloc = S->alloc;
@@ -923,7 +1018,9 @@ hpop_status hpop_server_destroy(hpop_server* S) {
   for (DevBuf* b : {&S->d_lists, &S->d_items, &S->d_reqs, &S->d_pool, &S->d_frontier, &S->d_ctl, &S->d_trees,
                     &S->d_stage, &S->d_moves})
     b->release(S->alloc);
-  S->pinned.release();
+  S->staging.release();
+  for (hipEvent_t e : S->ev)
+    if (e) (void)hipEventDestroy(e);
   S->h_out.release();
   (void)hipStreamSynchronize(S->stream);
   (void)hipStreamDestroy(S->stream);
@@ -1028,13 +1125,31 @@ hpop_status hpop_server_submit(hpop_server* S, int32_t sid, const hpop_event_chu
           return HPOP_E_BUSY;
         }
       }
-      // one copy into pinned memory; the records are validated on the device
-      // like device payloads (an invalid one fails the query at hpop_server_wait)
+      // one copy into the page-locked staging area; the records are validated
+      // on the device like device payloads (an invalid one fails the query at
+      // hpop_server_wait)
       if (total > 0) {
-        Q->host = (int64_t*)S->pinned.get((size_t)total * 16, Q->host_block);
-        if (!Q->host) {
+        size_t area;
+        {
+          std::lock_guard<std::mutex> g(S->staging.mu);
+          if (!S->staging.base) {
+            const size_t want = S->cfg.host_staging_mib > 0 ? (size_t)S->cfg.host_staging_mib << 20
+                                                            : kDefaultStagingBytes;
+            if (!S->staging.take(want)) {
+              delete Q;
+              return srv_fail(S, HPOP_E_OOM, "page-locked staging allocation failed");
+            }
+          }
+          area = S->staging.bytes;
+        }
+        if ((size_t)total * 16 > area) {
           delete Q;
-          return srv_fail(S, HPOP_E_OOM, "pinned host allocation failed");
+          return srv_fail(S, HPOP_E_ARG, "host payload larger than the page-locked staging area");
+        }
+        Q->host = (int64_t*)S->staging.get((size_t)total * 16);
+        if (!Q->host) {  // the area is held by queued payloads: back-pressure
+          delete Q;
+          return srv_fail(S, HPOP_E_BUSY, "page-locked staging area full");
         }
       }
       Q->host_words = (size_t)2 * total;
@@ -1061,7 +1176,7 @@ hpop_status hpop_server_submit(hpop_server* S, int32_t sid, const hpop_event_chu
       std::lock_guard<std::mutex> g(S->mu);
       if (busy()) {
         S->last_error = "queue full";
-        S->pinned.put(Q->host, Q->host_block);
+        S->staging.put((char*)Q->host, (size_t)total * 16);
         delete Q;
         return HPOP_E_BUSY;
       }
@@ -1103,11 +1218,41 @@ hpop_status hpop_server_get_stats(hpop_server* S, hpop_server_stats* out) {
   out->max_us = v.empty() ? 0.0 : v.back();
   out->max_submit_us = S->max_submit_us;
   out->max_step_us = S->max_step_us;
+  out->max_prep_us = S->max_prep_us;
+  out->max_grow_us = S->max_grow_us;
+  out->max_wait_us = S->max_wait_us;
+  out->max_h2d_us = S->max_phase_us[0];
+  out->max_move_us = S->max_phase_us[1];
+  out->max_build_us = S->max_phase_us[2];
+  out->max_splice_us = S->max_phase_us[3];
+  out->max_region_us = S->max_phase_us[4];
+  const double ns = S->steps ? (double)S->steps : 1.0;
+  out->mean_prep_us = S->sum_prep_us / ns;
+  out->mean_grow_us = S->sum_grow_us / ns;
+  out->mean_wait_us = S->sum_wait_us / ns;
+  out->mean_h2d_us = S->sum_phase_us[0] / ns;
+  out->mean_move_us = S->sum_phase_us[1] / ns;
+  out->mean_build_us = S->sum_phase_us[2] / ns;
+  out->mean_splice_us = S->sum_phase_us[3] / ns;
+  out->mean_region_us = S->sum_phase_us[4] / ns;
   {
-    std::lock_guard<std::mutex> pg(S->pinned.mu);
-    out->pinned_blocks = (int64_t)S->pinned.all.size();
-    out->max_pinned_alloc_us = S->pinned.max_alloc_us;
+    std::lock_guard<std::mutex> pg(S->staging.mu);
+    out->host_staging_bytes = (int64_t)S->staging.bytes;
+    out->max_pinned_alloc_us = S->staging.alloc_us;
+    out->max_host_staging_used = (int64_t)S->staging.max_used;
   }
+  return HPOP_OK;
+}
+
+hpop_status hpop_server_reset_stats(hpop_server* S) {
+  if (!S) return srv_fail(nullptr, HPOP_E_ARG, "null server");
+  std::lock_guard<std::mutex> g(S->mu);
+  S->lat_us.clear();
+  S->completed = S->events = S->steps = S->batched = 0;
+  S->max_submit_us = S->max_step_us = 0.0;
+  S->max_prep_us = S->max_grow_us = S->max_wait_us = 0.0;
+  S->sum_prep_us = S->sum_grow_us = S->sum_wait_us = 0.0;
+  for (int i = 0; i < 5; ++i) S->max_phase_us[i] = S->sum_phase_us[i] = 0.0;
   return HPOP_OK;
 }
 

@@ -209,12 +209,78 @@ def test_backpressure_busy():
         hp.hpop_server_destroy(srv)
 
 
-def test_replay_equals_oracle():
+def test_host_staging_area_bounds_and_phase_statistics():
+    """A 1 MiB page-locked staging area: a larger host payload is refused
+    with HPOP_E_ARG; payloads that would overfill it while others are queued
+    get HPOP_E_BUSY and fit again once those completed; the area is taken
+    once, at creation; every query's trees still equal the oracle's; the step
+    phases are measured."""
+    ranks = 1
+    srv = hp.hpop_server_create(max_sessions=1, max_inflight=1, queue_capacity=64, host_staging_mib=1)
+    try:
+        st0 = hp.hpop_server_get_stats(srv)
+        assert st0.host_staging_bytes == 1 << 20 and st0.max_pinned_alloc_us > 0
+        sid = hp.hpop_server_open_session(srv, ranks, ranks, 0)
+        big = np.arange(0, 10 * 70000, 10, dtype=np.int64)  # 70000 records: 1.07 MiB with their ends
+        with pytest.raises(hp.HpopError) as ei:
+            hp.hpop_server_submit(srv, sid, [(1, hp.HPOP_DEV_KERNEL, big, big + 5)], hp.HPOP_MEM_HOST, 0, 10 ** 7)
+        assert ei.value.status == hp.HPOP_E_ARG
+        # a query of 60000 records (960 KB) holds nearly all of the area until
+        # its step ends: a second one submitted right after it has to wait
+        chunks_all, tickets, busy, q, step = [], [], 0, 0, 10 ** 6
+        for rep in range(5):
+            for n in (60000, 20000):
+                s = np.arange(q * step, q * step + 10 * n, 10, dtype=np.int64)
+                e = s + 7
+                while True:
+                    try:
+                        t = hp.hpop_server_submit(srv, sid, [(1, hp.HPOP_DEV_KERNEL, s, e)], hp.HPOP_MEM_HOST,
+                                                  q * step, (q + 1) * step)
+                        break
+                    except hp.HpopError as err:
+                        assert err.status == hp.HPOP_E_BUSY
+                        busy += 1
+                        for tk, _ in tickets:  # the held area comes back once they completed
+                            hp.hpop_server_wait(srv, tk)
+                        tickets = []
+                tickets.append((t, q))
+                chunks_all.append(tg.Chunk(1, tg.DEV_KERNEL, s, e))
+                q += 1
+        for tk, _ in tickets:
+            hp.hpop_server_wait(srv, tk)
+        st = hp.hpop_server_get_stats(srv)
+        assert st.host_staging_bytes == 1 << 20 and st.max_host_staging_used <= 1 << 20
+        assert st.max_pinned_alloc_us == st0.max_pinned_alloc_us  # no second allocation
+        assert st.completed == q
+        for f in ("max_prep_us", "max_wait_us", "max_h2d_us", "max_build_us", "max_splice_us", "max_region_us"):
+            assert getattr(st, f) > 0, f
+            assert 0 < getattr(st, f.replace("max_", "mean_")) <= getattr(st, f), f
+        hp.hpop_server_reset_stats(srv)
+        st = hp.hpop_server_get_stats(srv)
+        assert st.completed == 0 and st.device_steps == 0 and st.max_step_us == 0 and st.max_build_us == 0
+        assert st.host_staging_bytes == 1 << 20
+        # the session's lists hold every query's records: one more (empty) query reads them back
+        frontier = max(int(c.end.max()) for c in chunks_all)
+        tr = tg.Trace(ranks, ranks, chunks_all, [((q - 1) * step, q * step), (0, frontier)])
+        t = hp.hpop_server_submit(srv, sid, [], hp.HPOP_MEM_HOST, (q - 1) * step, q * step)
+        reg, glob = hp.hpop_server_wait(srv, t)
+        want = oracle.compute(tr)
+        check_tree(reg, want, 0, "last region")
+        check_tree(glob, want, 1, "global")
+    finally:
+        hp.hpop_server_destroy(srv)
+    assert busy >= 1
+
+
+@pytest.mark.parametrize("heap", [0, 1 << 20, 64 << 20])
+def test_replay_equals_oracle(heap):
     """The native load generator returns the same trees as submit/wait, with a
-    latency per query and a wall time covering every completion."""
+    latency per query and a wall time covering every completion; with the
+    list heap grown on demand, taken too small at creation (lists then move
+    into a new heap) and taken large enough for every list."""
     ranks, n_sessions, n_queries = 2, 3, 4
     plan = make_queries(41, n_sessions, ranks, n_queries)
-    srv = hp.hpop_server_create(max_sessions=4, max_inflight=4)
+    srv = hp.hpop_server_create(max_sessions=4, max_inflight=4, list_heap_bytes=heap)
     try:
         sids = [hp.hpop_server_open_session(srv, ranks, ranks, origin) for origin, _ in plan]
         queries, keys = [], []
