@@ -4,6 +4,7 @@
 
 #include <climits>
 
+#include "hpop_geom.h"
 #include "hpop_internal.h"
 
 namespace hpop {
@@ -18,29 +19,7 @@ __device__ __forceinline__ bool rec_valid(long long s, long long e) {
   return s >= 0 && s <= e && e < kTimeLimit;
 }
 
-struct Geom {
-  long long min_s;
-  long long max_e;
-  int shift;
-  int log_nb;
-  bool empty;
-};
-
-__device__ __forceinline__ Geom seg_geom(const SegStats& st, const SegDesc& sd) {
-  Geom g;
-  g.empty = st.min_s > st.max_s;
-  g.min_s = (long long)st.min_s;
-  g.max_e = (long long)st.max_e;
-  g.log_nb = sd.log_nb;
-  const int bl = g.empty ? 0 : bitlen64(st.max_s - st.min_s);
-  g.shift = bl > sd.log_nb ? bl - sd.log_nb : 0;
-  return g;
-}
-
-// first time of bucket b (segment-relative) of a segment
-__device__ __forceinline__ long long bucket_lo(const Geom& g, long long b) { return g.min_s + (b << g.shift); }
-
-__device__ __forceinline__ bool seg_narrow(const Geom& g) { return g.shift <= kNarrowShift; }
+__device__ __forceinline__ Geom seg_geom(const Plan& p, long long seg) { return p.geom[seg]; }
 
 // The components of one bucket at one level, in either storage form.
 struct CompView {
@@ -114,13 +93,8 @@ __device__ __forceinline__ Elem widen(uint2 x, long long lo, const unsigned long
   return el;
 }
 
-// bucket of a record start inside its segment (clamped; start >= min_s for valid records)
-__device__ __forceinline__ int bucket_of(long long s, const Geom& g) {
-  unsigned long long rel = (unsigned long long)(s - g.min_s);
-  unsigned long long b = rel >> g.shift;
-  const unsigned long long nb = 1ull << g.log_nb;
-  return (int)(b < nb ? b : nb - 1);
-}
+// bucket of a valid record start inside its segment (min_s <= start <= max_s)
+__device__ __forceinline__ int bucket_of(long long s, const Geom& g) { return bucket_of_start(g, s); }
 
 // index of the last entry with key <= x in a sorted array of n int64 (n >= 1, a[0] <= x)
 __device__ __forceinline__ int upper_index_chunk(const ChunkDesc* c, int n, long long x) {

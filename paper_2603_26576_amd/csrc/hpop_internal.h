@@ -50,8 +50,24 @@ struct ChunkDesc {
 
 struct SegDesc {
   int64_t bucket_begin;  // first global bucket of the segment
-  int32_t log_nb;        // the segment has 1 << log_nb buckets
+  int32_t nb;            // the segment has nb buckets (any count: records / target)
   int32_t n_levels;      // 2 for devices, 3 for hosts
+};
+
+// Time buckets of one segment, fixed per build from its start range: bucket b
+// holds the records starting in [lo_b, lo_b + W) with lo_b = min_s + b * W and
+// W = wx * 2^s0 ns, s0 chosen so that (max_s - min_s) >> s0 < 2^31 and
+// wx = ((max_s - min_s) >> s0) / nb + 1, so nb buckets of equal width cover
+// the range. The bucket of x = (start - min_s) >> s0 is x / wx, computed as
+// the high half of x * minv (minv = floor(2^32 / wx)) plus one correction.
+struct SegGeom {
+  int64_t min_s;
+  uint32_t wx;
+  uint32_t minv;  // floor(2^32 / wx) for wx >= 2, else 0
+  int32_t s0;
+  int32_t nb;
+  int32_t empty;  // no valid record with a start
+  int32_t pad;
 };
 
 struct SegStats {
@@ -128,6 +144,7 @@ struct Plan {
   int32_t pad1;
   const SegDesc* segs;
   SegStats* stats;
+  SegGeom* geom;                     // [n_segs] bucket geometry (filled by the geometry kernel)
   int64_t n_buckets;
   unsigned int* counts;              // [n_buckets]
   int32_t* bucket_seg;               // [n_buckets] segment of each bucket (filled by the carry kernel)

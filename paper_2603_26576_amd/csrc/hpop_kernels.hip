@@ -142,6 +142,13 @@ __global__ __launch_bounds__(256) void k_stats_small(Plan p) {
   }
 }
 
+// The bucket geometry of every segment from its start range (one thread per
+// segment, after the start-range pass).
+__global__ void k_geom(Plan p) {
+  const long long seg = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (seg < p.n_segs) p.geom[seg] = make_geom(p.stats[seg], p.segs[seg]);
+}
+
 // ----------------------------------------------------------------------------
 // hist / scatter: regroup records by time bucket
 // ----------------------------------------------------------------------------
@@ -160,7 +167,7 @@ __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
-  const Geom g = seg_geom(p.stats[cd.seg], sd);
+  const Geom g = seg_geom(p, cd.seg);
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
   const long long end = min((long long)cd.count, base + p.tile_elems);
   int bk[IPT];
@@ -302,7 +309,7 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
-  const Geom g = seg_geom(p.stats[cd.seg], sd);
+  const Geom g = seg_geom(p, cd.seg);
   const bool seg_n = seg_narrow(g);
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
   const long long end = min((long long)cd.count, base + p.tile_elems);
@@ -488,7 +495,7 @@ __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
   if (seg >= p.n_segs) return;
   const SegDesc sd = p.segs[seg];
   const SegStats st = p.stats[seg];
-  const long long nb = 1ll << sd.log_nb;
+  const long long nb = sd.nb;
   // the running max end before any record: just below the first start
   const long long init = st.min_s > st.max_s ? -1 : (long long)st.min_s - 1;
   long long run[3] = {init, init, init};
@@ -535,7 +542,7 @@ __global__ __launch_bounds__(THREADS) void k_base(Plan p) {
   const long long seg = (long long)blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6);
   if (seg >= p.n_segs) return;
   const SegDesc sd = p.segs[seg];
-  const long long nb = 1ll << sd.log_nb;
+  const long long nb = sd.nb;
   long long run[3] = {0, 0, 0};
   for (long long c0 = 0; c0 < nb; c0 += 64 * kSegRows) {
     long long v[kSegRows][3];
@@ -575,7 +582,7 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
   __syncthreads();
   const int seg = *s_seg;
   const SegDesc sd = p.segs[seg];
-  const Geom g = seg_geom(p.stats[seg], sd);
+  const Geom g = seg_geom(p, seg);
   const long long bl = gb - sd.bucket_begin;
   const BucketRecs br = bucket_recs(p, gb);
   // a slot overflow makes the host redo the build: write an empty bucket
@@ -593,7 +600,7 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
   CompN* compn_b[3] = {p.compn[0] + off, p.compn[1] + off, p.compn[2] + off};
   CompN* const* compn = seg_narrow(g) ? compn_b : nullptr;
   if (n > 0) {
-    const long long lo = g.min_s + (bl << g.shift);
+    const long long lo = bucket_lo(g, bl);
     if (n <= CAP) {
       const int ni = (int)n;
       const unsigned long long* mx = p.maxend + gb * 3;
@@ -846,7 +853,7 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   }
   // the segment's geometry only now, while the records are in flight
   const SegDesc sd = p.segs[p.bucket_seg[gb]];
-  const long long lo = bucket_lo(seg_geom(p.stats[p.bucket_seg[gb]], sd), gb - sd.bucket_begin);
+  const long long lo = bucket_lo(seg_geom(p, p.bucket_seg[gb]), gb - sd.bucket_begin);
   const int nlev = sd.n_levels;
   kor >>= 2;
   kor = (unsigned int)wave_reduce_i32<OpOrI>((int)kor, 0);
@@ -994,14 +1001,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // Measure of level l of segment seg before time t.
 __device__ long long measure_before(const Plan& p, int seg, int l, long long t) {
   const SegDesc sd = p.segs[seg];
-  const Geom g = seg_geom(p.stats[seg], sd);
+  const Geom g = seg_geom(p, seg);
   if (g.empty || t <= g.min_s) return 0;
-  if (t >= g.max_e) return p.seg_total[seg * 3 + l];
-  const unsigned long long rel = (unsigned long long)(t - g.min_s);
-  unsigned long long b = rel >> g.shift;
-  const unsigned long long nb = 1ull << g.log_nb;
-  if (b >= nb) b = nb - 1;
-  const long long gb = sd.bucket_begin + (long long)b;
+  if (t >= (long long)p.stats[seg].max_e) return p.seg_total[seg * 3 + l];
+  const long long gb = sd.bucket_begin + bucket_index(g, (unsigned long long)(t - g.min_s));
   const long long carry = p.carry[gb * 3 + l];
   const long long base = p.base[gb * 3 + l];
   const long long bs = p.bsum[gb * 3 + l];
@@ -1185,11 +1188,13 @@ hipError_t launch_reset(const Plan& p, hipStream_t st) {
 }
 
 hipError_t launch_stats(const Plan& p, hipStream_t st) {
-  if (p.n_tiles == 0) return hipSuccess;
-  if (p.tile_elems <= 512)
-    hipLaunchKernelGGL(k_stats_small, dim3((unsigned)((p.n_tiles + 3) / 4)), dim3(256), 0, st, p);
-  else
-    hipLaunchKernelGGL(k_stats<256>, dim3((unsigned)p.n_tiles), dim3(256), 0, st, p);
+  if (p.n_tiles > 0) {
+    if (p.tile_elems <= 512)
+      hipLaunchKernelGGL(k_stats_small, dim3((unsigned)((p.n_tiles + 3) / 4)), dim3(256), 0, st, p);
+    else
+      hipLaunchKernelGGL(k_stats<256>, dim3((unsigned)p.n_tiles), dim3(256), 0, st, p);
+  }
+  if (p.n_segs > 0) hipLaunchKernelGGL(k_geom, dim3((unsigned)((p.n_segs + 255) / 256)), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 

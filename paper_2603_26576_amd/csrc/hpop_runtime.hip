@@ -55,12 +55,6 @@ int slot_of_kind(int kind) {
   }
 }
 
-static int ceil_log2(long long x) {
-  int l = 0;
-  while ((1ll << l) < x) ++l;
-  return l;
-}
-
 // ----------------------------------------------------------------------------
 // device memory
 // ----------------------------------------------------------------------------
@@ -184,6 +178,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   small += carve_bytes(n_tiles, sizeof(int32_t));
   small += carve_bytes(n_segs, sizeof(SegDesc));
   small += carve_bytes(n_segs, sizeof(SegStats));
+  small += carve_bytes(n_segs, sizeof(SegGeom));
   small += carve_bytes(n_buckets, sizeof(unsigned int)) * 2;
   small += carve_bytes(n_buckets + 1, sizeof(unsigned long long));
   small += carve_bytes(n_buckets, sizeof(unsigned long long));
@@ -255,6 +250,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   p.tile_chunk = carve<int32_t>(cur, n_tiles);
   p.segs = d_segs = carve<SegDesc>(cur, n_segs);
   p.stats = carve<SegStats>(cur, n_segs);
+  p.geom = carve<SegGeom>(cur, n_segs);
   p.counts = carve<unsigned int>(cur, n_buckets);
   p.bucket_seg = carve<int32_t>(cur, n_buckets);
   p.offsets = carve<unsigned long long>(cur, n_buckets + 1);
@@ -333,7 +329,7 @@ static int pow2ceil(int x) {
 }
 
 static void tuned(const hpop_tuning& t, int& target, int& cap, int& tile, int& slots) {
-  target = t.bucket_target > 0 ? std::min(4096, std::max(16, t.bucket_target)) : 256;
+  target = t.bucket_target > 0 ? std::min(4096, std::max(16, t.bucket_target)) : 320;
   cap = t.bucket_cap == 4096 ? 4096 : 2048;
   tile = t.tile_elems == 512 || t.tile_elems == 2048 || t.tile_elems == 8192 ? t.tile_elems : 4096;
   // single-pass scatter slots: 4x the mean bucket, within the on-chip capacity
@@ -425,9 +421,9 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
     SegDesc sd;
     sd.bucket_begin = buckets;
     const long long want = (seg_count[r] + target - 1) / target;
-    sd.log_nb = std::min(24, ceil_log2(std::max(1ll, want)));
+    sd.nb = (int32_t)std::min(1ll << 24, std::max(1ll, want));
     sd.n_levels = seg_host[r] ? 3 : 2;
-    buckets += 1ll << sd.log_nb;
+    buckets += sd.nb;
     h_segs.push_back(sd);
   }
   hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), tiles, n_segs, buckets, elems,
@@ -1094,21 +1090,18 @@ hpop_status hpop_session_get_info(const hpop_session* s, hpop_session_info* out)
     const long long nb = En.ws.plan.n_buckets;
     const size_t ns = En.h_segs.size();
     std::vector<unsigned int> nc((size_t)(3 * nb));
-    std::vector<SegStats> st(ns);
+    std::vector<SegGeom> geo(ns);
     std::vector<unsigned long long> cur((size_t)nb);
     if (hipStreamSynchronize(s->stream) == hipSuccess &&
         hipMemcpy(cur.data(), En.ws.plan.cursor, cur.size() * 8, hipMemcpyDeviceToHost) == hipSuccess &&
         hipMemcpy(nc.data(), En.ws.plan.ncomp, nc.size() * 4, hipMemcpyDeviceToHost) == hipSuccess &&
-        (ns == 0 || hipMemcpy(st.data(), En.ws.plan.stats, ns * sizeof(SegStats), hipMemcpyDeviceToHost) == hipSuccess)) {
+        (ns == 0 || hipMemcpy(geo.data(), En.ws.plan.geom, ns * sizeof(SegGeom), hipMemcpyDeviceToHost) == hipSuccess)) {
       long long t = 0, w = 0;
       for (unsigned int v : nc) t += v;
       for (size_t g = 0; g < ns; ++g) {
-        if (st[g].min_s > st[g].max_s) continue;
-        const unsigned long long span = st[g].max_s - st[g].min_s;
-        const int bl = span ? 64 - __builtin_clzll(span) : 0;
-        const int shift = bl > En.h_segs[g].log_nb ? bl - En.h_segs[g].log_nb : 0;
-        if (shift <= kNarrowShift) continue;
-        const long long b0 = En.h_segs[g].bucket_begin, b1 = b0 + (1ll << En.h_segs[g].log_nb);
+        // buckets wider than 2^kNarrowShift ns keep their components in the 16 B form
+        if (geo[g].empty || ((unsigned long long)geo[g].wx << geo[g].s0) <= (1ull << kNarrowShift)) continue;
+        const long long b0 = En.h_segs[g].bucket_begin, b1 = b0 + En.h_segs[g].nb;
         for (long long b = b0; b < b1; ++b) w += (long long)nc[3 * b] + nc[3 * b + 1] + nc[3 * b + 2];
       }
       out->n_components = t;

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(64) void k_serv_prep(ServItem* items, int n_items, 
   const SegDesc sd = p.segs[it.seg];
   const SegStats stt = p.stats[it.seg];
   if (l == 0 && stt.max_e > stt.min_s) atomicMax((unsigned long long*)&frontier[it.sid], stt.max_e);
-  const long long nb = 1ll << sd.log_nb;
+  const long long nb = sd.nb;
   // first bucket with a new merged interval of this level
   long long b0 = -1;
   for (long long b = 0; b < nb; ++b)
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(64) void k_serv_prep(ServItem* items, int n_items, 
     }
   if (b0 < 0) return;  // no new interval at this level
   const ListDev L = lists[it.list0 + l];
-  const Geom g0 = seg_geom(stt, sd);
+  const Geom g0 = seg_geom(p, it.seg);
   const long long x = comp_view(p, g0, sd.bucket_begin, sd.bucket_begin + b0, l).cs(0);
   long long lo = 0, hi = L.len;
   while (lo < hi) {
@@ -148,11 +148,7 @@ __global__ __launch_bounds__(64) void k_serv_prep(ServItem* items, int n_items, 
   long long xb = -1;
   if (L.len > 0) {
     const long long X = list_ce(L, L.len - 1);
-    const Geom g = seg_geom(stt, sd);
-    if (X >= g.min_s) {
-      const unsigned long long rel = (unsigned long long)(X - g.min_s) >> g.shift;
-      xb = rel < (unsigned long long)nb ? (long long)rel : nb - 1;
-    }
+    if (X >= g0.min_s) xb = bucket_index(g0, (unsigned long long)(X - g0.min_s));
   }
   long long need = L.len - k0;
   for (long long b = 0; b <= xb; ++b) need += p.counts[sd.bucket_begin + b];
@@ -181,7 +177,7 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   ListDev& Lr = lists[it.list0 + l];
   const ListDev L = Lr;
   const SegDesc sd = p.segs[it.seg];
-  const long long nb = 1ll << sd.log_nb;
+  const long long nb = sd.nb;
   const long long k0 = it.k0[l], xb = it.xb[l];
   const long long nS = L.len - k0;
   const long long total = it.scr_len[l];
@@ -197,7 +193,7 @@ __global__ __launch_bounds__(kServThreads) void k_serv_splice(const ServItem* it
   st.P[0] = k0 < L.len ? L.base[k0].pl : L.total;
   st.R[0] = k0;
   Comp* out[3] = {L.base, nullptr, nullptr};
-  const Geom gs = seg_geom(p.stats[it.seg], sd);
+  const Geom gs = seg_geom(p, it.seg);
   if (total > 0) {
     // old entries from k0 on, then the level's new records of buckets 0..xb
     for (long long i = threadIdx.x; i < nS; i += kServThreads) {
