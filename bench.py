@@ -53,7 +53,7 @@ def log(*a):
 
 
 # the sources that define the build kernels (their code, launch shapes and data layout)
-KERNEL_SOURCES = ("hpop_kernels.hip", "hpop_kernels.h", "hpop_device.h", "hpop_internal.h")
+KERNEL_SOURCES = ("hpop_kernels.hip", "hpop_kernels.h", "hpop_device.h", "hpop_geom.h", "hpop_internal.h")
 
 
 def kernel_source_hash():

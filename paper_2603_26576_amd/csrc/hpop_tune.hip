@@ -86,7 +86,7 @@ extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const c
             hpop_status st = run_once(ss, k, trees);  // warm-up: plan, allocations, graph
             if (st != HPOP_OK) return restore(st);
             std::vector<double> v;
-            for (int r = 0; r < 3; ++r) {
+            for (int r = 0; r < 5; ++r) {
               auto t0 = std::chrono::steady_clock::now();
               st = run_once(ss, k, trees);
               auto t1 = std::chrono::steady_clock::now();
@@ -94,8 +94,8 @@ extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const c
               v.push_back(std::chrono::duration<double>(t1 - t0).count());
             }
             std::sort(v.begin(), v.end());
-            if (v[1] < best_t) {
-              best_t = v[1];
+            if (v[2] < best_t) {  // the median of five
+              best_t = v[2];
               best = t;
             }
           }
