@@ -967,6 +967,7 @@ hpop_status hpop_server_create(const hpop_server_config* cfg, hpop_server** out)
       delete S;
       return srv_fail(nullptr, HPOP_E_HIP, "stream creation failed");
     }
+    S->alloc.stream = S->stream;  // every device allocation of the server is ordered on its stream
     if (cfg->host_staging_mib > 0 && !S->staging.take((size_t)cfg->host_staging_mib << 20)) {
       (void)hipStreamDestroy(S->stream);
       delete S;
@@ -989,7 +990,6 @@ hpop_status hpop_server_create(const hpop_server_config* cfg, hpop_server** out)
       }
       S->heap_cap = cap;
     }
-    S->alloc.stream = S->stream;
     S->engine.alloc = S->alloc;
     S->engine.use_graphs = false;
     S->worker = std::thread(worker_loop, S);
