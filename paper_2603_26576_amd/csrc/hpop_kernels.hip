@@ -685,15 +685,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// N consecutive LDS words from a position that is a multiple of N
+// N consecutive LDS words from a position that is a multiple of N: 16-byte
+// reads when N is a multiple of 4, 8-byte reads when it is even, else words
 template <int N>
 __device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (&dst)[N]) {
-  if constexpr (N == 1) {
-    dst[0] = src[0];
-  } else if constexpr (N == 2) {
-    const uint2 v = *(const uint2*)src;
-    dst[0] = v.x;
-    dst[1] = v.y;
+  if constexpr (N % 2 == 1) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) dst[j] = src[j];
+  } else if constexpr (N % 4 == 2) {
+#pragma unroll
+    for (int j = 0; j < N; j += 2) {
+      const uint2 v = *(const uint2*)(src + j);
+      dst[j] = v.x;
+      dst[j + 1] = v.y;
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < N; j += 4) {
@@ -900,6 +905,7 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
     unsigned int pos[G];
 #pragma unroll
     for (int u = 0; u < G; ++u) {  // the reads of a group first (past the bucket: word `lane`)
+      if (r0 + u >= IPL) break;  // a last group shorter than G
       const bool in = lane + 64 * (r0 + u) < ni;
       const unsigned int d = in ? (kr[r0 + u] >> 2) >> dsh : 2u * (unsigned int)lane;
       pos[u] = ((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu) + rk[r0 + u];
@@ -909,6 +915,7 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
       // a position past the bucket stores to its own index (>= ni): never
       // read as a record, and no branch around the stores (distinct addresses)
       const int r = r0 + u;
+      if (r >= IPL) break;
       const bool in = lane + 64 * r < ni;
       const unsigned int q = in ? pos[u] : (unsigned int)(lane + 64 * r);
       W.key[q] = kr[r];
@@ -986,9 +993,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
     const int ni = (int)n;
     const uint2* rec = br.narrow;
+    // as many records per lane as the bucket needs: every slot costs the
+    // same instructions, filled or not
     if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry, maxe);
     else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry, maxe);
+    else if (ni <= 192) done = wave_bucket<3>(p, W, gb, off, ni, rec, carry, maxe);
     else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, rec, carry, maxe);
+    else if (ni <= 320) done = wave_bucket<5>(p, W, gb, off, ni, rec, carry, maxe);
+    else if (ni <= 384) done = wave_bucket<6>(p, W, gb, off, ni, rec, carry, maxe);
+    else if (ni <= 448) done = wave_bucket<7>(p, W, gb, off, ni, rec, carry, maxe);
     else done = wave_bucket<8>(p, W, gb, off, ni, rec, carry, maxe);
   }
   if (!done && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;

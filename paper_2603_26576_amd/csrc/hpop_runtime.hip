@@ -329,7 +329,7 @@ static int pow2ceil(int x) {
 }
 
 static void tuned(const hpop_tuning& t, int& target, int& cap, int& tile, int& slots) {
-  target = t.bucket_target > 0 ? std::min(4096, std::max(16, t.bucket_target)) : 320;
+  target = t.bucket_target > 0 ? std::min(4096, std::max(16, t.bucket_target)) : 352;
   cap = t.bucket_cap == 4096 ? 4096 : 2048;
   tile = t.tile_elems == 512 || t.tile_elems == 2048 || t.tile_elems == 8192 ? t.tile_elems : 4096;
   // single-pass scatter slots: 4x the mean bucket, within the on-chip capacity

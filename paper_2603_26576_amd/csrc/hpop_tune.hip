@@ -74,7 +74,7 @@ extern "C" hpop_status hpop_autotune(hpop_session* const* ss, int32_t k, const c
       for (int i = 0; i < k; ++i) nreg += ss[i]->regions.size();
       std::vector<hpop_metric_tree> trees(std::max<size_t>(1, nreg));
       double best_t = 1e30;
-      const int targets[] = {192, 256, 320, 384};  // mean records per time bucket
+      const int targets[] = {256, 320, 352, 384};  // mean records per time bucket
       const int caps[] = {2048, 4096};
       const int tiles[] = {512, 2048, 4096, 8192};  // 512: traces of many small record batches
       for (int tg : targets)
