@@ -925,13 +925,19 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   }
   wave_sync();
   // order inside each sub-bin by the full key: one lane per sub-bin holding
-  // two or more records (the lane that placed its second record)
+  // two or more records (the lane that placed its second record); each lane
+  // walks its own such records (a few iterations, not one per round)
   bool crowded = false;
   if (dsh > 0) {
+    unsigned int todo = fix;
+    while (todo) {
+      const int rr = __builtin_ctz(todo);
+      todo &= todo - 1u;
+      unsigned int kk = kr[0];
 #pragma unroll
-    for (int r = 0; r < IPL; ++r) {
-      if (fix & (1u << r)) {
-        const unsigned int d = (kr[r] >> 2) >> dsh;
+      for (int j = 1; j < IPL; ++j) kk = rr == j ? kr[j] : kk;  // kr[rr] without indexing registers
+      {
+        const unsigned int d = (kk >> 2) >> dsh;
         const int st0 = (int)((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu);
         const int st1 = (int)d + 1 < nbins ? (int)((W.bins[(d + 1) >> 1] >> (16u * ((d + 1) & 1u))) & 0xFFFFu) : ni;
         const int c = st1 - st0;
