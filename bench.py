@@ -316,6 +316,14 @@ def bench_batched(hp, traces, steps, warmup, tune_cache=None):
             step()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
+        # per-stage device times, from separate steps with HIP-event timing on
+        hp.hpop_session_enable_timing(sessions[0], True)
+        stage = {}
+        for _ in range(steps):
+            step()
+            for k, ms in hp.hpop_session_stage_times(sessions[0]):
+                stage.setdefault(k, []).append(ms)
+        hp.hpop_session_enable_timing(sessions[0], False)
         segs = sum(tr.n_hosts + tr.n_devices for tr in traces)
         tun = hp.hpop_session_get_tuning(sessions[0])
     finally:
@@ -323,6 +331,7 @@ def bench_batched(hp, traces, steps, warmup, tune_cache=None):
             hp.hpop_session_destroy(s)
     return {"traces": len(traces), "events": n_events, "segments": segs, "ms_per_step": round(dt * 1e3, 3),
             "events_per_s": n_events / dt,
+            "stage_ms": {k: round(float(np.mean(v)), 4) for k, v in stage.items()},
             "tuning": {"bucket_target": tun.bucket_target, "bucket_cap": tun.bucket_cap, "tile_elems": tun.tile_elems}}
 
 
@@ -499,6 +508,20 @@ def serving_slices(hp, W, sidx, n_rec, cursor, host):
     return arr, k, frontier
 
 
+def cgroup_throttle():
+    """(times throttled, throttled us) of this process's cgroup CPU quota, or None."""
+    for path, scale in (("/sys/fs/cgroup/cpu.stat", 1.0), ("/sys/fs/cgroup/cpu,cpuacct/cpu.stat", 1e-3),
+                        ("/sys/fs/cgroup/cpu/cpu.stat", 1e-3)):
+        try:
+            kv = dict(line.split() for line in open(path) if len(line.split()) == 2)
+        except (OSError, ValueError):
+            continue
+        if "nr_throttled" in kv:
+            us = float(kv.get("throttled_usec", kv.get("throttled_time", 0))) * scale
+            return int(kv["nr_throttled"]), us
+    return None
+
+
 def serving_run(hp, W, lam, host, keep=False):
     """One Poisson run of the serving workload at `lam` queries/s: a fresh
     server, every session warmed with its first W["warm"] records (untimed, in
@@ -543,7 +566,9 @@ def serving_run(hp, W, lam, host, keep=False):
             closes[i] = t1
         arrivals = np.cumsum(W["rng"].exponential(1.0 / lam, size=n_queries))
         queries = [(sid, (arr, k), a, b, int(arrivals[q] * 1e9)) for q, (sid, arr, k, a, b) in enumerate(plan)]
+        thr0 = cgroup_throttle()
         reg, glob, lat_ns, wall_ns, busy = hp.hpop_server_replay(srv, queries, mem)
+        thr1 = cgroup_throttle()
         st = hp.hpop_server_get_stats(srv)
     finally:
         hp.hpop_server_destroy(srv)
@@ -572,6 +597,9 @@ def serving_run(hp, W, lam, host, keep=False):
                             for k in ("prep", "grow", "wait", "h2d", "build", "move", "splice", "region")},
            "mean_phase_us": {k: round(getattr(st, "mean_%s_us" % k), 1)
                              for k in ("prep", "grow", "wait", "h2d", "build", "move", "splice", "region")}}
+    if thr0 and thr1:
+        # CPU quota throttling of the process's cgroup during the replay (stalls every thread)
+        res["cpu_throttled"] = {"times": thr1[0] - thr0[0], "ms": round((thr1[1] - thr0[1]) * 1e-3, 1)}
     if keep:
         kept["warm_trees"] = warm_trees
         kept["query_trees"] = list(zip(reg, glob))

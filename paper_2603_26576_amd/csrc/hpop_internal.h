@@ -46,7 +46,13 @@ struct ChunkDesc {
   int32_t slot;        // level rank of the kind: 0, 1 or 2
   int32_t chunk_id;    // index in the chunk table (error reports)
   int32_t owner;       // session (or serving query) the records belong to
+  int32_t tile_pos;    // -1: the chunk has tiles of its own; else its place among a shared tile's chunks
+  int32_t tile_off;    // in a shared tile: the tile's record index of the chunk's first record
 };
+
+// Chunks smaller than half a tile share tiles: consecutive ones (in the
+// chunk table) fill a tile with at most this many chunks and tile_elems records.
+constexpr int kTileChunks = 64;
 
 struct SegDesc {
   int64_t bucket_begin;  // first global bucket of the segment
@@ -136,8 +142,10 @@ struct Plan {
   const ChunkDesc* chunks;
   int32_t n_chunks;
   int32_t n_segs;
-  int64_t n_tiles;
-  int32_t* tile_chunk;               // [n_tiles] chunk of each streaming tile (filled by the reset kernel)
+  int64_t n_tiles;                   // tiles of single chunks [0, n_own_tiles), then shared tiles
+  int64_t n_own_tiles;
+  int32_t* tile_chunk;               // [n_tiles] chunk of each streaming tile, the last one of a shared
+                                     // tile (filled by the reset kernel)
   int32_t tile_elems;
   int32_t cap;                       // records a bucket may hold for the LDS sort
   int32_t slot_cap;                  // >0: single-pass scatter into fixed slots of this many records per bucket

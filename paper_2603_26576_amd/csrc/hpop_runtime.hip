@@ -410,12 +410,7 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
     err = "too many resources or record batches in one build";
     return HPOP_E_ARG;
   }
-  long long tiles = 0, buckets = 0, elems = 0;
-  for (auto& d : h_chunks) {
-    d.tile_begin = tiles;
-    tiles += (d.count + tile - 1) / tile;
-    elems += d.count;
-  }
+  long long buckets = 0, elems = 0;
   h_segs.clear();
   for (long long r = 0; r < n_segs; ++r) {
     SegDesc sd;
@@ -426,11 +421,49 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
     buckets += sd.nb;
     h_segs.push_back(sd);
   }
+  // Streaming tiles. A chunk of fewer than half a tile of records would leave
+  // its own tile mostly empty (traces of many small record batches), so such
+  // chunks share tiles: the chunks with tiles of their own come first in the
+  // table, then the small ones, packed in order up to a tile of records and
+  // kTileChunks chunks per tile. Shared tiles are numbered after the others,
+  // so tile_begin never decreases along the table. Tile sizes without a
+  // shared-tile kernel, and builds of 2^31 buckets or more (their kernels
+  // index buckets in 32 bits), keep one chunk per tile.
+  const bool share = (tile == 512 || tile == 2048) && buckets < INT_MAX;
+  const long long small_below = share ? tile / 2 : 0;
+  std::stable_partition(h_chunks.begin(), h_chunks.end(),
+                        [&](const ChunkDesc& d) { return d.count >= small_below; });
+  long long tiles = 0;
+  for (auto& d : h_chunks) {
+    elems += d.count;
+    if (d.count < small_below) continue;
+    d.tile_begin = tiles;
+    d.tile_pos = -1;
+    d.tile_off = 0;
+    tiles += (d.count + tile - 1) / tile;
+  }
+  const long long own_tiles = tiles;
+  int pos = 0;
+  long long fill = 0;
+  for (auto& d : h_chunks) {
+    if (d.count >= small_below) continue;
+    if (pos > 0 && (fill + d.count > tile || pos == kTileChunks)) {
+      ++tiles;  // this tile is full
+      pos = 0;
+      fill = 0;
+    }
+    d.tile_begin = tiles;
+    d.tile_pos = pos++;
+    d.tile_off = (int32_t)fill;
+    fill += d.count;
+  }
+  if (pos > 0) ++tiles;
   hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), tiles, n_segs, buckets, elems,
                               slots > 0 ? buckets * (long long)slots : 0, (long long)h_regions.size(), times,
                               std::max(1, n_owners), (long long)h_ivls.size(), err);
   if (st != HPOP_OK) return st;
   ws.plan.n_tiles = tiles;
+  ws.plan.n_own_tiles = own_tiles;
   ws.plan.tile_elems = tile;
   ws.plan.cap = cap;
   ws.plan.slot_cap = slots;
