@@ -1263,40 +1263,57 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
     }
   }
   wave_sync();
-  // order inside each sub-bin by the full key: one lane per sub-bin holding
-  // two or more records (the lane that placed its second record); each lane
-  // walks its own such records (a few iterations, not one per round)
+  // order inside each sub-bin by the full key, where it holds two or more
+  // records: an insertion sort per such sub-bin (c > 32 records: block path)
   bool crowded = false;
+  auto fix_sub_bin = [&](unsigned int d) {
+    const int st0 = (int)((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu);
+    const int st1 = (int)d + 1 < nbins ? (int)((W.bins[(d + 1) >> 1] >> (16u * ((d + 1) & 1u))) & 0xFFFFu) : ni;
+    const int c = st1 - st0;
+    if (c > 32) {
+      crowded = true;
+      return;
+    }
+    unsigned int* ko = W.key + st0;
+    unsigned int* eo = W.end + st0;
+    for (int a = 1; a < c; ++a) {
+      const unsigned int kx = ko[a], ex = eo[a];
+      int b = a - 1;
+      while (b >= 0 && ko[b] > kx) {
+        ko[b + 1] = ko[b];
+        eo[b + 1] = eo[b];
+        --b;
+      }
+      ko[b + 1] = kx;
+      eo[b + 1] = ex;
+    }
+  };
   if (dsh > 0) {
-    unsigned int todo = fix;
-    while (todo) {
-      const int rr = __builtin_ctz(todo);
-      todo &= todo - 1u;
-      unsigned int kk = kr[0];
+    // the sub-bins to fix (each named by the lane that placed its second
+    // record) are listed in the key array past the bucket's records, so the
+    // work spreads evenly over the lanes: ceil(fixes / 64) rounds instead of
+    // the largest number of fixes of one lane
+    unsigned int nfix;
+    const unsigned int fb = wave_excl_scan_u32<OpSumU>((unsigned int)__popc(fix), 0u, nfix);
+    if (nfix <= 2u * (unsigned int)(kWaveCap - ni)) {  // 16-bit entries in the free words
+      unsigned short* list = (unsigned short*)(W.key + ni);
+      unsigned int q = fb;
 #pragma unroll
-      for (int j = 1; j < IPL; ++j) kk = rr == j ? kr[j] : kk;  // kr[rr] without indexing registers
-      {
-        const unsigned int d = (kk >> 2) >> dsh;
-        const int st0 = (int)((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu);
-        const int st1 = (int)d + 1 < nbins ? (int)((W.bins[(d + 1) >> 1] >> (16u * ((d + 1) & 1u))) & 0xFFFFu) : ni;
-        const int c = st1 - st0;
-        if (c > 32) {
-          crowded = true;
-        } else {
-          unsigned int* ko = W.key + st0;
-          unsigned int* eo = W.end + st0;
-          for (int a = 1; a < c; ++a) {
-            const unsigned int kx = ko[a], ex = eo[a];
-            int b = a - 1;
-            while (b >= 0 && ko[b] > kx) {
-              ko[b + 1] = ko[b];
-              eo[b + 1] = eo[b];
-              --b;
-            }
-            ko[b + 1] = kx;
-            eo[b + 1] = ex;
-          }
-        }
+      for (int r = 0; r < IPL; ++r) {
+        if (fix & (1u << r)) list[q++] = (unsigned short)((kr[r] >> 2) >> dsh);
+      }
+      wave_sync();
+      for (unsigned int i = (unsigned int)lane; i < nfix; i += 64) fix_sub_bin(list[i]);
+    } else {
+      // no room: each lane walks its own such records
+      unsigned int todo = fix;
+      while (todo) {
+        const int rr = __builtin_ctz(todo);
+        todo &= todo - 1u;
+        unsigned int kk = kr[0];
+#pragma unroll
+        for (int j = 1; j < IPL; ++j) kk = rr == j ? kr[j] : kk;  // kr[rr] without indexing registers
+        fix_sub_bin((kk >> 2) >> dsh);
       }
     }
   }
