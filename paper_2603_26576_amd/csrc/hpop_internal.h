@@ -52,7 +52,7 @@ struct ChunkDesc {
 
 // Chunks smaller than half a tile share tiles: consecutive ones (in the
 // chunk table) fill a tile with at most this many chunks and tile_elems records.
-constexpr int kTileChunks = 64;
+constexpr int kTileChunks = 32;
 
 struct SegDesc {
   int64_t bucket_begin;  // first global bucket of the segment

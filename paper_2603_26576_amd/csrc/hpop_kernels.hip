@@ -50,16 +50,374 @@ __global__ void k_reset(Plan p) {
 }
 
 // ----------------------------------------------------------------------------
+// shared tiles: chunks of fewer than half a tile of records, several per tile.
+// The same passes as for a tile of one chunk, with the chunk (and so the
+// segment, kind and bucket geometry) looked up per record and buckets indexed
+// globally. They run in the same launches as the other tiles (the blocks past
+// n_own_tiles), reusing those kernels' LDS arrays where the layouts agree.
+// ----------------------------------------------------------------------------
+
+// The chunks of one shared tile, staged in LDS.
+struct ShTile {
+  const int64_t* s[kTileChunks];
+  const int64_t* e[kTileChunks];
+  long long bucket_begin[kTileChunks];
+  Geom g[kTileChunks];
+  int off[kTileChunks + 1];  // off[j]: the tile's index of chunk j's first record; off[n]: records in the tile
+  int seg[kTileChunks];
+  int slot[kTileChunks];
+  int n;                     // chunks in the tile
+  int first;                 // index of the first one in the chunk table
+};
+
+// Stages the chunks of shared tile `tile` (every thread calls; ends with a
+// barrier). They are the chunks up to the tile's last one whose first tile is
+// `tile`: thread j takes the j-th from the end and files it at its place. The
+// geometry exists only after the start-range pass.
+template <bool kGeom>
+__device__ __forceinline__ void sh_load(const Plan& p, long long tile, ShTile& T) {
+  const int last = p.tile_chunk[tile];
+  for (int j = threadIdx.x; j < kTileChunks && j <= last; j += blockDim.x) {
+    const ChunkDesc cd = p.chunks[last - j];
+    if (cd.tile_begin != tile) continue;
+    const int q = cd.tile_pos;
+    T.s[q] = cd.s;
+    T.e[q] = cd.e;
+    T.off[q] = cd.tile_off;
+    T.seg[q] = cd.seg;
+    T.slot[q] = cd.slot;
+    if (kGeom) {
+      T.bucket_begin[q] = p.segs[cd.seg].bucket_begin;
+      T.g[q] = p.geom[cd.seg];
+    }
+    if (j == 0) {
+      T.off[q + 1] = cd.tile_off + (int)cd.count;
+      T.n = q + 1;
+      T.first = last - q;
+    }
+  }
+  __syncthreads();
+}
+
+// The chunk of tile record x < off[n]: the largest j < n with off[j] <= x.
+__device__ __forceinline__ int sh_find(const ShTile& T, int x) {
+  int j = 0;
+#pragma unroll
+  for (int step = kTileChunks / 2; step > 0; step >>= 1) {
+    const int m = j + step;
+    if (m < T.n && T.off[m] <= x) j = m;
+  }
+  return j;
+}
+
+struct ShStatsSmem {
+  ShTile T;
+  unsigned long long mn[kTileChunks], mx[kTileChunks];  // start range per chunk of the tile
+};
+
+// Start range of the records of shared tile `tile`, per chunk, into the segment statistics.
+template <int THREADS>
+__device__ __forceinline__ void stats_shared(const Plan& p, long long tile, ShStatsSmem& S) {
+  for (int j = threadIdx.x; j < kTileChunks; j += THREADS) {
+    S.mn[j] = ULLONG_MAX;
+    S.mx[j] = 0;
+  }
+  sh_load<false>(p, tile, S.T);
+  const int n = S.T.off[S.T.n];
+  for (int x = threadIdx.x; x < n; x += THREADS) {
+    const int j = sh_find(S.T, x);
+    const unsigned long long v = (unsigned long long)S.T.s[j][x - S.T.off[j]];
+    if (v < (unsigned long long)kTimeLimit) {  // invalid starts stay out of the range
+      atomicMin(&S.mn[j], v);
+      atomicMax(&S.mx[j], v);
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < S.T.n; j += THREADS) {
+    if (S.mn[j] != ULLONG_MAX) {
+      atomicMin(&p.stats[S.T.seg[j]].min_s, S.mn[j]);
+      atomicMax(&p.stats[S.T.seg[j]].max_s, S.mx[j]);
+    }
+  }
+}
+
+// Per record of a shared tile: its chunk, and its start and end, loaded for
+// all rounds first from positions clamped into the tile (n >= 1).
+template <int THREADS, int IPT>
+__device__ __forceinline__ void sh_records(const ShTile& T, int n, int (&jj)[IPT], long long (&svs)[IPT],
+                                           long long (&evs)[IPT]) {
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const int x = threadIdx.x + k * THREADS;
+    const int xc = x < n ? x : n - 1;
+    jj[k] = sh_find(T, xc);
+  }
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const int x = threadIdx.x + k * THREADS;
+    const int i = (x < n ? x : n - 1) - T.off[jj[k]];
+    svs[k] = T.s[jj[k]][i];
+    evs[k] = T.e[jj[k]][i];
+  }
+}
+
+// Bucket counts of shared tile `tile` (s_rng and hist: the count kernel's LDS arrays).
+template <int THREADS, int IPT>
+__device__ __forceinline__ void hist_shared(const Plan& p, long long tile, ShTile& T, int (*s_rng)[THREADS / 64],
+                                            unsigned int* hist) {
+  constexpr int NW = THREADS / 64;
+  constexpr int HW = THREADS * IPT <= kHistWin ? THREADS * IPT / 4 : kHistWin;
+  for (int i = threadIdx.x; i < HW; i += THREADS) hist[i] = 0;
+  sh_load<true>(p, tile, T);
+  const int n = T.off[T.n];
+  int jj[IPT], gbk[IPT];
+  long long svs[IPT], evs[IPT];
+  sh_records<THREADS, IPT>(T, n, jj, svs, evs);
+  int bmin = INT_MAX, bmax = -1;
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    gbk[k] = -1;
+    if ((int)threadIdx.x + k * THREADS < n && rec_valid(svs[k], evs[k]) && svs[k] < evs[k]) {
+      const int j = jj[k];
+      gbk[k] = (int)(T.bucket_begin[j] + bucket_of(svs[k], T.g[j]));
+      bmin = min(bmin, gbk[k]);
+      bmax = max(bmax, gbk[k]);
+    }
+  }
+  bmin = wave_reduce_i32<OpMinI>(bmin, INT_MAX);
+  bmax = wave_reduce_i32<OpMaxI>(bmax, -1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
+  __syncthreads();
+  bmin = INT_MAX; bmax = -1;
+  for (int w = 0; w < NW; ++w) { bmin = min(bmin, s_rng[0][w]); bmax = max(bmax, s_rng[1][w]); }
+  if (bmax < 0) return;  // uniform: no valid record in this tile
+  if (bmax - bmin < HW) {
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      unsigned long long todo = __ballot(gbk[k] >= 0);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lb = __builtin_amdgcn_readlane(gbk[k], leader);
+        const unsigned long long m = __ballot(gbk[k] == lb);
+        if (lane == leader) atomicAdd(&hist[lb - bmin], (unsigned int)__popcll(m));
+        todo &= ~m;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= bmax - bmin; i += THREADS)
+      if (hist[i]) atomicAdd(&p.counts[bmin + i], hist[i]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < IPT; ++k)
+      if (gbk[k] >= 0) atomicAdd(&p.counts[gbk[k]], 1u);
+  }
+}
+
+// Scatter of shared tile `tile`. s_rng, hist, bbase and bunit are the
+// scatter kernel's LDS arrays; the largest ends are kept per bucket and kind
+// slot: slot 0 in the kernel's bmaxe, slots 1 and 2 in bmaxe12 (2 x HW).
+template <int THREADS, int IPT>
+__device__ __forceinline__ void scatter_shared(const Plan& p, long long tile, ShTile& T, int (*s_rng)[THREADS / 64],
+                                               unsigned long long* hist, unsigned long long* bbase,
+                                               unsigned long long* bmaxe0, unsigned long long* bmaxe12,
+                                               long long* bunit) {
+  constexpr int NW = THREADS / 64;
+  constexpr int HW = THREADS * IPT <= kHistWin ? THREADS * IPT / 4 : kHistWin;
+  auto bmaxe = [&](int w, int sl) -> unsigned long long& { return sl == 0 ? bmaxe0[w] : bmaxe12[(sl - 1) * HW + w]; };
+  for (int i = threadIdx.x; i < HW; i += THREADS) {
+    hist[i] = 0;
+    bmaxe0[i] = 0;
+    bmaxe12[i] = 0;
+    bmaxe12[HW + i] = 0;
+  }
+  sh_load<true>(p, tile, T);
+  const int n = T.off[T.n];
+  int jj[IPT], gbk[IPT];
+  bool nr[IPT];
+  unsigned int kx[IPT], ex[IPT];
+  {
+    long long svs[IPT], evs[IPT];
+    sh_records<THREADS, IPT>(T, n, jj, svs, evs);
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const int x = threadIdx.x + k * THREADS;
+      gbk[k] = -1;
+      nr[k] = false;
+      kx[k] = 0;
+      ex[k] = 0;
+      if (x < n) {
+        const int j = jj[k];
+        const long long sv = svs[k], ev = evs[k];
+        if (!rec_valid(sv, ev)) {
+          // first bad record of the build: chunk << 40 | index (rare path)
+          const ChunkDesc& cd = p.chunks[T.first + j];
+          atomicMin(p.err, ((unsigned long long)cd.chunk_id << 40) | (unsigned long long)(x - T.off[j]));
+          p.owner_err[cd.owner] = 1u;
+        } else if (sv < ev) {
+          const Geom& g = T.g[j];
+          const int b = bucket_of(sv, g);
+          const long long lo = bucket_lo(g, b);
+          gbk[k] = (int)(T.bucket_begin[j] + b);
+          nr[k] = seg_narrow(g);
+          kx[k] = ((unsigned int)(sv - lo) << 2) | (unsigned int)T.slot[j];
+          ex[k] = ev - lo < 0xFFFFFFFFll ? (unsigned int)(ev - lo + 1) : 0xFFFFFFFFu;  // far ends clamped
+        }
+      }
+    }
+  }
+  int bmin = INT_MAX, bmax = -1;
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    if (gbk[k] >= 0) {
+      bmin = min(bmin, gbk[k]);
+      bmax = max(bmax, gbk[k]);
+    }
+  }
+  bmin = wave_reduce_i32<OpMinI>(bmin, INT_MAX);
+  bmax = wave_reduce_i32<OpMaxI>(bmax, -1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
+  __syncthreads();
+  bmin = INT_MAX; bmax = -1;
+  for (int w = 0; w < NW; ++w) { bmin = min(bmin, s_rng[0][w]); bmax = max(bmax, s_rng[1][w]); }
+  if (bmax < 0) return;  // uniform: no valid record in this tile
+  const long long scap = p.slot_cap;
+  unsigned long long* gmax = p.maxend;
+  uint2* units = (uint2*)p.elems;
+  auto region = [&](long long gb, long long& ub, long long& ucap) {
+    if (scap) {
+      ub = 2 * gb * scap;
+      ucap = 2 * scap;
+    } else {
+      ub = 2 * (long long)p.offsets[gb];
+      ucap = 2 * (long long)p.counts[gb];
+    }
+  };
+  // a record in the 16 B form, read again from its chunk (rare)
+  auto put_wide = [&](int k, long long ub, long long ucap, unsigned long long rank) {
+    if (2 * ((long long)rank + 1) <= ucap) {
+      const int j = jj[k];
+      const int i = (int)threadIdx.x + k * THREADS - T.off[j];
+      Elem el;
+      el.s = T.s[j][i];
+      el.e_slot = (long long)((unsigned long long)T.e[j][i] | ((unsigned long long)T.slot[j] << kSlotShift));
+      *(Elem*)(units + ub + ucap - 2 * ((long long)rank + 1)) = el;
+    }
+  };
+  auto end_of = [&](int k) { return T.e[jj[k]][(int)threadIdx.x + k * THREADS - T.off[jj[k]]]; };
+  if (bmax - bmin < HW) {
+    unsigned int rk[IPT];
+    const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      // lanes of one bucket and kind share one LDS atomic: the leader reserves
+      // their ranks (per form) and folds their largest end in
+      rk[k] = 0;
+      const int sl = gbk[k] >= 0 ? T.slot[jj[k]] : 0;
+      unsigned long long todo = __ballot(gbk[k] >= 0);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lb = __builtin_amdgcn_readlane(gbk[k], leader);
+        const int ls = __builtin_amdgcn_readlane(sl, leader);
+        const bool in = gbk[k] == lb && sl == ls;
+        const unsigned long long m = __ballot(in);
+        const unsigned long long mn = __ballot(in && nr[k]);
+        long long emax;
+        unsigned int e32 = 0;
+        if (mn == m) e32 = (unsigned int)wave_reduce_i32<OpMaxU32>((int)(in ? ex[k] : 0u), 0);
+        if (mn == m && e32 != 0xFFFFFFFFu) {
+          // all 8 B records, none clamped: the largest end in 32 bits, relative to the bucket
+          const int jl = __builtin_amdgcn_readlane(jj[k], leader);
+          emax = bucket_lo(T.g[jl], lb - T.bucket_begin[jl]) + (long long)e32 - 1;
+        } else {
+          emax = wave_reduce_i64<OpMax>(in ? end_of(k) : 0ll, 0ll);
+        }
+        unsigned long long b = 0;
+        if (lane == leader) {
+          const unsigned long long c8 = (unsigned long long)__popcll(mn), c16 = (unsigned long long)__popcll(m & ~mn);
+          b = atomicAdd(&hist[lb - bmin], c8 | (c16 << 32));
+          atomicMax(&bmaxe(lb - bmin, ls), (unsigned long long)emax);
+        }
+        b = (unsigned long long)readlane64((long long)b, leader);
+        if (in) rk[k] = nr[k] ? (unsigned int)b + (unsigned int)__popcll(mn & lt)
+                              : (unsigned int)(b >> 32) + (unsigned int)__popcll(m & ~mn & lt);
+        todo &= ~m;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= bmax - bmin; i += THREADS) {
+      const unsigned long long h = hist[i];
+      if (h) {
+        const long long gb = (long long)bmin + i;
+        const unsigned long long old = atomicAdd(&p.cursor[gb], h);
+        bbase[i] = old;
+        long long ub, ucap;
+        region(gb, ub, ucap);
+        bunit[i] = ub;
+        for (int sl = 0; sl < 3; ++sl)
+          if (bmaxe(i, sl)) atomicMax(&gmax[gb * 3 + sl], bmaxe(i, sl));
+        const unsigned long long tot = (old & 0xFFFFFFFFull) + (old >> 32) + (h & 0xFFFFFFFFull) + (h >> 32);
+        if (scap && tot > (unsigned long long)scap && tot - (h & 0xFFFFFFFFull) - (h >> 32) <= (unsigned long long)scap)
+          atomicAdd(&p.oversized[1], 1ull);  // slot overflow: the build is redone with exact offsets
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      if (gbk[k] >= 0) {
+        const int w = gbk[k] - bmin;
+        const unsigned long long bb = bbase[w];
+        const long long ub = bunit[w];
+        long long ub2, ucap;
+        region(gbk[k], ub2, ucap);
+        if (nr[k]) {
+          const unsigned long long rank = (bb & 0xFFFFFFFFull) + rk[k];
+          if ((long long)rank < ucap) units[ub + (long long)rank] = make_uint2(kx[k], ex[k]);
+        } else {
+          put_wide(k, ub, ucap, (bb >> 32) + rk[k]);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      if (gbk[k] >= 0) {
+        const long long gb = gbk[k];
+        const unsigned long long old = atomicAdd(&p.cursor[gb], nr[k] ? 1ull : (1ull << 32));
+        atomicMax(&gmax[gb * 3 + T.slot[jj[k]]], (unsigned long long)end_of(k));
+        if (scap && (old & 0xFFFFFFFFull) + (old >> 32) == (unsigned long long)scap)
+          atomicAdd(&p.oversized[1], 1ull);
+        long long ub, ucap;
+        region(gb, ub, ucap);
+        if (nr[k]) {
+          if ((long long)(old & 0xFFFFFFFFull) < ucap) units[ub + (long long)(old & 0xFFFFFFFFull)] = make_uint2(kx[k], ex[k]);
+        } else {
+          put_wide(k, ub, ucap, old >> 32);
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // stats: validate records, per-segment min/max start and max end
 // ----------------------------------------------------------------------------
 
-template <int THREADS>
+template <int THREADS, bool kShared>
 __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
   // The bucket grid needs only the range of starts; validation happens in the
   // scatter, which reads both ends anyway. Starts outside [0, 2^62) belong to
   // invalid records and are left out of the range.
   constexpr int NW = THREADS / 64;
   __shared__ unsigned long long red[2][NW];
+  if constexpr (kShared) {
+    if (blockIdx.x >= p.n_own_tiles) {
+      __shared__ ShStatsSmem sh;
+      stats_shared<THREADS>(p, blockIdx.x, sh);
+      return;
+    }
+  }
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const long long base = (tile - cd.tile_begin) * (long long)p.tile_elems;
@@ -112,7 +470,17 @@ __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
 // Small tiles (at most 512 records): one wave per tile, four tiles per
 // workgroup, so a lane reduces 8 records instead of a workgroup reducing 2 per
 // thread (traces of many small record batches have mostly partial tiles).
+template <bool kShared>
 __global__ __launch_bounds__(256) void k_stats_small(Plan p) {
+  if constexpr (kShared) {
+    // blocks past those of the other tiles: one shared tile each
+    const long long own_blocks = (p.n_own_tiles + 3) / 4;
+    if (blockIdx.x >= own_blocks) {
+      __shared__ ShStatsSmem sh;
+      stats_shared<256>(p, p.n_own_tiles + (blockIdx.x - own_blocks), sh);
+      return;
+    }
+  }
   const int lane = threadIdx.x & 63;
   const long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (tile >= p.n_own_tiles) return;
@@ -158,12 +526,19 @@ __global__ void k_geom(Plan p) {
 // buckets, or a quarter of the tile's records for tiles of at most kHistWin records.
 // Wider tiles fall back to global atomics per record.
 
-template <int THREADS, int IPT>
+template <int THREADS, int IPT, bool kShared>
 __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   constexpr int NW = THREADS / 64;
   constexpr int HW = THREADS * IPT <= kHistWin ? THREADS * IPT / 4 : kHistWin;  // LDS bucket window
   __shared__ int s_rng[2][NW];
   __shared__ unsigned int hist[HW];
+  if constexpr (kShared) {
+    if (blockIdx.x >= p.n_own_tiles) {
+      __shared__ ShTile T;
+      hist_shared<THREADS, IPT>(p, blockIdx.x, T, s_rng, hist);
+      return;
+    }
+  }
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
@@ -296,7 +671,7 @@ __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
   if (b0 < p.n_buckets && p.n_buckets <= b0 + IPT) p.offsets[p.n_buckets] = run;
 }
 
-template <int THREADS, int IPT>
+template <int THREADS, int IPT, bool kShared>
 __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   constexpr int NW = THREADS / 64;
   // LDS bucket window: a quarter of the tile's records for tiles of at most kHistWin records
@@ -306,6 +681,14 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   __shared__ unsigned long long bbase[HW];  // the same counts placed before this tile
   __shared__ unsigned long long bmaxe[HW];  // largest end of the tile's records
   __shared__ long long bunit[HW];           // first unit of the bucket's region
+  if constexpr (kShared) {
+    if (blockIdx.x >= p.n_own_tiles) {
+      __shared__ ShTile T;
+      __shared__ unsigned long long bmaxe12[2 * HW];
+      scatter_shared<THREADS, IPT>(p, blockIdx.x, T, s_rng, hist, bbase, bmaxe, bmaxe12, bunit);
+      return;
+    }
+  }
   const long long tile = blockIdx.x;
   const ChunkDesc cd = p.chunks[p.tile_chunk[tile]];
   const SegDesc sd = p.segs[cd.seg];
@@ -465,345 +848,6 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
         const unsigned long long old = atomicAdd(&p.cursor[gb], nr[k] ? 1ull : (1ull << 32));
         const long long ev = cd.e[base + threadIdx.x + (long long)k * THREADS];
         atomicMax(&gmax[gb * 3 + cd.slot], (unsigned long long)ev);
-        if (scap && (old & 0xFFFFFFFFull) + (old >> 32) == (unsigned long long)scap)
-          atomicAdd(&p.oversized[1], 1ull);
-        long long ub, ucap;
-        region(gb, ub, ucap);
-        if (nr[k]) {
-          if ((long long)(old & 0xFFFFFFFFull) < ucap) units[ub + (long long)(old & 0xFFFFFFFFull)] = make_uint2(kx[k], ex[k]);
-        } else {
-          put_wide(k, ub, ucap, old >> 32);
-        }
-      }
-    }
-  }
-}
-
-// ----------------------------------------------------------------------------
-// shared tiles: chunks of fewer than half a tile of records, several per tile.
-// The same passes as above, with the chunk (and so the segment, kind and
-// bucket geometry) looked up per record, and buckets indexed globally.
-// ----------------------------------------------------------------------------
-
-// The chunks of one shared tile, staged in LDS.
-struct ShTile {
-  const int64_t* s[kTileChunks];
-  const int64_t* e[kTileChunks];
-  long long bucket_begin[kTileChunks];
-  Geom g[kTileChunks];
-  int off[kTileChunks + 1];  // off[j]: the tile's index of chunk j's first record; off[n]: records in the tile
-  int seg[kTileChunks];
-  int slot[kTileChunks];
-  int n;                     // chunks in the tile
-  int first;                 // index of the first one in the chunk table
-};
-
-// Stages the chunks of shared tile `tile` (every thread calls; ends with a
-// barrier). The geometry exists only after the start-range pass.
-template <bool kGeom>
-__device__ __forceinline__ void sh_load(const Plan& p, long long tile, ShTile& T) {
-  const int last = p.tile_chunk[tile];
-  const int n = p.chunks[last].tile_pos + 1;
-  const int first = last - n + 1;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    const ChunkDesc cd = p.chunks[first + j];
-    T.s[j] = cd.s;
-    T.e[j] = cd.e;
-    T.off[j] = cd.tile_off;
-    T.seg[j] = cd.seg;
-    T.slot[j] = cd.slot;
-    if (kGeom) {
-      T.bucket_begin[j] = p.segs[cd.seg].bucket_begin;
-      T.g[j] = p.geom[cd.seg];
-    }
-    if (j == n - 1) {
-      T.off[n] = cd.tile_off + (int)cd.count;
-      T.n = n;
-      T.first = first;
-    }
-  }
-  __syncthreads();
-}
-
-// The chunk of tile record x < off[n]: the largest j < n with off[j] <= x.
-__device__ __forceinline__ int sh_find(const ShTile& T, int x) {
-  int j = 0;
-#pragma unroll
-  for (int step = kTileChunks / 2; step > 0; step >>= 1) {
-    const int m = j + step;
-    if (m < T.n && T.off[m] <= x) j = m;
-  }
-  return j;
-}
-
-template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_stats_sh(Plan p) {
-  __shared__ ShTile T;
-  __shared__ unsigned long long mn[kTileChunks], mx[kTileChunks];
-  for (int j = threadIdx.x; j < kTileChunks; j += THREADS) {
-    mn[j] = ULLONG_MAX;
-    mx[j] = 0;
-  }
-  sh_load<false>(p, p.n_own_tiles + blockIdx.x, T);
-  const int n = T.off[T.n];
-  for (int x = threadIdx.x; x < n; x += THREADS) {
-    const int j = sh_find(T, x);
-    const unsigned long long s = (unsigned long long)T.s[j][x - T.off[j]];
-    if (s < (unsigned long long)kTimeLimit) {  // as in k_stats: invalid starts stay out of the range
-      atomicMin(&mn[j], s);
-      atomicMax(&mx[j], s);
-    }
-  }
-  __syncthreads();
-  for (int j = threadIdx.x; j < T.n; j += THREADS) {
-    if (mn[j] != ULLONG_MAX) {
-      atomicMin(&p.stats[T.seg[j]].min_s, mn[j]);
-      atomicMax(&p.stats[T.seg[j]].max_s, mx[j]);
-    }
-  }
-}
-
-// Per record of a shared tile: its chunk, and its start and end, loaded for
-// all rounds first from positions clamped into the tile (n >= 1).
-template <int THREADS, int IPT>
-__device__ __forceinline__ void sh_records(const ShTile& T, int n, int (&jj)[IPT], long long (&svs)[IPT],
-                                           long long (&evs)[IPT]) {
-#pragma unroll
-  for (int k = 0; k < IPT; ++k) {
-    const int x = threadIdx.x + k * THREADS;
-    const int xc = x < n ? x : n - 1;
-    jj[k] = sh_find(T, xc);
-  }
-#pragma unroll
-  for (int k = 0; k < IPT; ++k) {
-    const int x = threadIdx.x + k * THREADS;
-    const int i = (x < n ? x : n - 1) - T.off[jj[k]];
-    svs[k] = T.s[jj[k]][i];
-    evs[k] = T.e[jj[k]][i];
-  }
-}
-
-template <int THREADS, int IPT>
-__global__ __launch_bounds__(THREADS) void k_hist_sh(Plan p) {
-  constexpr int NW = THREADS / 64;
-  constexpr int HW = THREADS * IPT <= kHistWin ? THREADS * IPT / 4 : kHistWin;
-  __shared__ ShTile T;
-  __shared__ int s_rng[2][NW];
-  __shared__ unsigned int hist[HW];
-  for (int i = threadIdx.x; i < HW; i += THREADS) hist[i] = 0;
-  sh_load<true>(p, p.n_own_tiles + blockIdx.x, T);
-  const int n = T.off[T.n];
-  int jj[IPT], gbk[IPT];
-  long long svs[IPT], evs[IPT];
-  sh_records<THREADS, IPT>(T, n, jj, svs, evs);
-  int bmin = INT_MAX, bmax = -1;
-#pragma unroll
-  for (int k = 0; k < IPT; ++k) {
-    gbk[k] = -1;
-    if ((int)threadIdx.x + k * THREADS < n && rec_valid(svs[k], evs[k]) && svs[k] < evs[k]) {
-      const int j = jj[k];
-      gbk[k] = (int)(T.bucket_begin[j] + bucket_of(svs[k], T.g[j]));
-      bmin = min(bmin, gbk[k]);
-      bmax = max(bmax, gbk[k]);
-    }
-  }
-  bmin = wave_reduce_i32<OpMinI>(bmin, INT_MAX);
-  bmax = wave_reduce_i32<OpMaxI>(bmax, -1);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
-  __syncthreads();
-  bmin = INT_MAX; bmax = -1;
-  for (int w = 0; w < NW; ++w) { bmin = min(bmin, s_rng[0][w]); bmax = max(bmax, s_rng[1][w]); }
-  if (bmax < 0) return;  // uniform: no valid record in this tile
-  if (bmax - bmin < HW) {
-#pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      unsigned long long todo = __ballot(gbk[k] >= 0);
-      while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int lb = __builtin_amdgcn_readlane(gbk[k], leader);
-        const unsigned long long m = __ballot(gbk[k] == lb);
-        if (lane == leader) atomicAdd(&hist[lb - bmin], (unsigned int)__popcll(m));
-        todo &= ~m;
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= bmax - bmin; i += THREADS)
-      if (hist[i]) atomicAdd(&p.counts[bmin + i], hist[i]);
-  } else {
-#pragma unroll
-    for (int k = 0; k < IPT; ++k)
-      if (gbk[k] >= 0) atomicAdd(&p.counts[gbk[k]], 1u);
-  }
-}
-
-template <int THREADS, int IPT>
-__global__ __launch_bounds__(THREADS) void k_scatter_sh(Plan p) {
-  constexpr int NW = THREADS / 64;
-  constexpr int HW = THREADS * IPT <= kHistWin ? THREADS * IPT / 4 : kHistWin;
-  __shared__ ShTile T;
-  __shared__ int s_rng[2][NW];
-  __shared__ unsigned long long hist[HW];      // per window bucket: 8 B records | 16 B records << 32
-  __shared__ unsigned long long bbase[HW];     // the same counts placed before this tile
-  __shared__ unsigned long long bmaxe[3 * HW]; // largest end of the tile's records, per bucket and kind slot
-  __shared__ long long bunit[HW];              // first unit of the bucket's region
-  for (int i = threadIdx.x; i < HW; i += THREADS) hist[i] = 0;
-  for (int i = threadIdx.x; i < 3 * HW; i += THREADS) bmaxe[i] = 0;
-  sh_load<true>(p, p.n_own_tiles + blockIdx.x, T);
-  const int n = T.off[T.n];
-  int jj[IPT], gbk[IPT];
-  bool nr[IPT];
-  unsigned int kx[IPT], ex[IPT];
-  {
-    long long svs[IPT], evs[IPT];
-    sh_records<THREADS, IPT>(T, n, jj, svs, evs);
-#pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      const int x = threadIdx.x + k * THREADS;
-      gbk[k] = -1;
-      nr[k] = false;
-      kx[k] = 0;
-      ex[k] = 0;
-      if (x < n) {
-        const int j = jj[k];
-        const long long sv = svs[k], ev = evs[k];
-        if (!rec_valid(sv, ev)) {
-          // first bad record of the build: chunk << 40 | index (rare path)
-          const ChunkDesc& cd = p.chunks[T.first + j];
-          atomicMin(p.err, ((unsigned long long)cd.chunk_id << 40) | (unsigned long long)(x - T.off[j]));
-          p.owner_err[cd.owner] = 1u;
-        } else if (sv < ev) {
-          const Geom& g = T.g[j];
-          const int b = bucket_of(sv, g);
-          const long long lo = bucket_lo(g, b);
-          gbk[k] = (int)(T.bucket_begin[j] + b);
-          nr[k] = seg_narrow(g);
-          kx[k] = ((unsigned int)(sv - lo) << 2) | (unsigned int)T.slot[j];
-          ex[k] = ev - lo < 0xFFFFFFFFll ? (unsigned int)(ev - lo + 1) : 0xFFFFFFFFu;  // far ends clamped
-        }
-      }
-    }
-  }
-  int bmin = INT_MAX, bmax = -1;
-#pragma unroll
-  for (int k = 0; k < IPT; ++k) {
-    if (gbk[k] >= 0) {
-      bmin = min(bmin, gbk[k]);
-      bmax = max(bmax, gbk[k]);
-    }
-  }
-  bmin = wave_reduce_i32<OpMinI>(bmin, INT_MAX);
-  bmax = wave_reduce_i32<OpMaxI>(bmax, -1);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) { s_rng[0][wave] = bmin; s_rng[1][wave] = bmax; }
-  __syncthreads();
-  bmin = INT_MAX; bmax = -1;
-  for (int w = 0; w < NW; ++w) { bmin = min(bmin, s_rng[0][w]); bmax = max(bmax, s_rng[1][w]); }
-  if (bmax < 0) return;  // uniform: no valid record in this tile
-  const long long scap = p.slot_cap;
-  unsigned long long* gmax = p.maxend;
-  uint2* units = (uint2*)p.elems;
-  auto region = [&](long long gb, long long& ub, long long& ucap) {
-    if (scap) {
-      ub = 2 * gb * scap;
-      ucap = 2 * scap;
-    } else {
-      ub = 2 * (long long)p.offsets[gb];
-      ucap = 2 * (long long)p.counts[gb];
-    }
-  };
-  // a record in the 16 B form, read again from its chunk (rare)
-  auto put_wide = [&](int k, long long ub, long long ucap, unsigned long long rank) {
-    if (2 * ((long long)rank + 1) <= ucap) {
-      const int j = jj[k];
-      const int i = (int)threadIdx.x + k * THREADS - T.off[j];
-      Elem el;
-      el.s = T.s[j][i];
-      el.e_slot = (long long)((unsigned long long)T.e[j][i] | ((unsigned long long)T.slot[j] << kSlotShift));
-      *(Elem*)(units + ub + ucap - 2 * ((long long)rank + 1)) = el;
-    }
-  };
-  auto end_of = [&](int k) { return T.e[jj[k]][(int)threadIdx.x + k * THREADS - T.off[jj[k]]]; };
-  if (bmax - bmin < HW) {
-    unsigned int rk[IPT];
-    const unsigned long long lt = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      // lanes of one bucket and kind share one LDS atomic: the leader reserves
-      // their ranks (per form) and folds their largest end in
-      rk[k] = 0;
-      const int sl = gbk[k] >= 0 ? T.slot[jj[k]] : 0;
-      unsigned long long todo = __ballot(gbk[k] >= 0);
-      while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int lb = __builtin_amdgcn_readlane(gbk[k], leader);
-        const int ls = __builtin_amdgcn_readlane(sl, leader);
-        const bool in = gbk[k] == lb && sl == ls;
-        const unsigned long long m = __ballot(in);
-        const unsigned long long mn = __ballot(in && nr[k]);
-        long long emax;
-        unsigned int e32 = 0;
-        if (mn == m) e32 = (unsigned int)wave_reduce_i32<OpMaxU32>((int)(in ? ex[k] : 0u), 0);
-        if (mn == m && e32 != 0xFFFFFFFFu) {
-          // all 8 B records, none clamped: the largest end in 32 bits, relative to the bucket
-          const int jl = __builtin_amdgcn_readlane(jj[k], leader);
-          emax = bucket_lo(T.g[jl], lb - T.bucket_begin[jl]) + (long long)e32 - 1;
-        } else {
-          emax = wave_reduce_i64<OpMax>(in ? end_of(k) : 0ll, 0ll);
-        }
-        unsigned long long b = 0;
-        if (lane == leader) {
-          const unsigned long long c8 = (unsigned long long)__popcll(mn), c16 = (unsigned long long)__popcll(m & ~mn);
-          b = atomicAdd(&hist[lb - bmin], c8 | (c16 << 32));
-          atomicMax(&bmaxe[3 * (lb - bmin) + ls], (unsigned long long)emax);
-        }
-        b = (unsigned long long)readlane64((long long)b, leader);
-        if (in) rk[k] = nr[k] ? (unsigned int)b + (unsigned int)__popcll(mn & lt)
-                              : (unsigned int)(b >> 32) + (unsigned int)__popcll(m & ~mn & lt);
-        todo &= ~m;
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= bmax - bmin; i += THREADS) {
-      const unsigned long long h = hist[i];
-      if (h) {
-        const long long gb = (long long)bmin + i;
-        const unsigned long long old = atomicAdd(&p.cursor[gb], h);
-        bbase[i] = old;
-        long long ub, ucap;
-        region(gb, ub, ucap);
-        bunit[i] = ub;
-        for (int sl = 0; sl < 3; ++sl)
-          if (bmaxe[3 * i + sl]) atomicMax(&gmax[gb * 3 + sl], bmaxe[3 * i + sl]);
-        const unsigned long long tot = (old & 0xFFFFFFFFull) + (old >> 32) + (h & 0xFFFFFFFFull) + (h >> 32);
-        if (scap && tot > (unsigned long long)scap && tot - (h & 0xFFFFFFFFull) - (h >> 32) <= (unsigned long long)scap)
-          atomicAdd(&p.oversized[1], 1ull);  // slot overflow: the build is redone with exact offsets
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      if (gbk[k] >= 0) {
-        const int w = gbk[k] - bmin;
-        const unsigned long long bb = bbase[w];
-        const long long ub = bunit[w];
-        long long ub2, ucap;
-        region(gbk[k], ub2, ucap);
-        if (nr[k]) {
-          const unsigned long long rank = (bb & 0xFFFFFFFFull) + rk[k];
-          if ((long long)rank < ucap) units[ub + (long long)rank] = make_uint2(kx[k], ex[k]);
-        } else {
-          put_wide(k, ub, ucap, (bb >> 32) + rk[k]);
-        }
-      }
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      if (gbk[k] >= 0) {
-        const long long gb = gbk[k];
-        const unsigned long long old = atomicAdd(&p.cursor[gb], nr[k] ? 1ull : (1ull << 32));
-        atomicMax(&gmax[gb * 3 + T.slot[jj[k]]], (unsigned long long)end_of(k));
         if (scap && (old & 0xFFFFFFFFull) + (old >> 32) == (unsigned long long)scap)
           atomicAdd(&p.oversized[1], 1ull);
         long long ub, ucap;
@@ -1563,35 +1607,39 @@ hipError_t launch_reset(const Plan& p, hipStream_t st) {
 }
 
 hipError_t launch_stats(const Plan& p, hipStream_t st) {
-  if (p.n_own_tiles > 0) {
-    if (p.tile_elems <= 512)
-      hipLaunchKernelGGL(k_stats_small, dim3((unsigned)((p.n_own_tiles + 3) / 4)), dim3(256), 0, st, p);
-    else
-      hipLaunchKernelGGL(k_stats<256>, dim3((unsigned)p.n_own_tiles), dim3(256), 0, st, p);
+  // the tiles of single chunks, then (in the same launch) the shared tiles
+  const long long own = p.n_own_tiles, sh = p.n_tiles - p.n_own_tiles;
+  if (p.tile_elems <= 512) {
+    const unsigned blocks = (unsigned)((own + 3) / 4 + sh);
+    if (sh > 0) hipLaunchKernelGGL(k_stats_small<true>, dim3(blocks), dim3(256), 0, st, p);
+    else if (own > 0) hipLaunchKernelGGL(k_stats_small<false>, dim3(blocks), dim3(256), 0, st, p);
+  } else if (sh > 0) {
+    hipLaunchKernelGGL((k_stats<256, true>), dim3((unsigned)p.n_tiles), dim3(256), 0, st, p);
+  } else if (own > 0) {
+    hipLaunchKernelGGL((k_stats<256, false>), dim3((unsigned)p.n_tiles), dim3(256), 0, st, p);
   }
-  if (p.n_tiles > p.n_own_tiles)
-    hipLaunchKernelGGL(k_stats_sh<256>, dim3((unsigned)(p.n_tiles - p.n_own_tiles)), dim3(256), 0, st, p);
   if (p.n_segs > 0) hipLaunchKernelGGL(k_geom, dim3((unsigned)((p.n_segs + 255) / 256)), dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
+// Count and scatter launches: one block per tile, the shared tiles (if any)
+// after the others; plans share tiles only at 512 and 2048 records per tile.
 hipError_t launch_hist(const Plan& p, hipStream_t st) {
-  const unsigned own = (unsigned)p.n_own_tiles, sh = (unsigned)(p.n_tiles - p.n_own_tiles);
-  if (own > 0) {
+  if (p.n_tiles == 0) return hipSuccess;
+  const dim3 grid((unsigned)p.n_tiles);
+  if (p.n_tiles > p.n_own_tiles) {
     switch (p.tile_elems) {
-      case 512: hipLaunchKernelGGL((k_hist<128, 4>), dim3(own), dim3(128), 0, st, p); break;
-      case 2048: hipLaunchKernelGGL((k_hist<512, 4>), dim3(own), dim3(512), 0, st, p); break;
-      case 8192: hipLaunchKernelGGL((k_hist<1024, 8>), dim3(own), dim3(1024), 0, st, p); break;
-      default: hipLaunchKernelGGL((k_hist<512, 8>), dim3(own), dim3(512), 0, st, p); break;
-    }
-  }
-  if (sh > 0) {
-    // the plan shares tiles only at these sizes
-    switch (p.tile_elems) {
-      case 512: hipLaunchKernelGGL((k_hist_sh<128, 4>), dim3(sh), dim3(128), 0, st, p); break;
-      case 2048: hipLaunchKernelGGL((k_hist_sh<512, 4>), dim3(sh), dim3(512), 0, st, p); break;
+      case 512: hipLaunchKernelGGL((k_hist<128, 4, true>), grid, dim3(128), 0, st, p); break;
+      case 2048: hipLaunchKernelGGL((k_hist<512, 4, true>), grid, dim3(512), 0, st, p); break;
       default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+  }
+  switch (p.tile_elems) {
+    case 512: hipLaunchKernelGGL((k_hist<128, 4, false>), grid, dim3(128), 0, st, p); break;
+    case 2048: hipLaunchKernelGGL((k_hist<512, 4, false>), grid, dim3(512), 0, st, p); break;
+    case 8192: hipLaunchKernelGGL((k_hist<1024, 8, false>), grid, dim3(1024), 0, st, p); break;
+    default: hipLaunchKernelGGL((k_hist<512, 8, false>), grid, dim3(512), 0, st, p); break;
   }
   return hipGetLastError();
 }
@@ -1604,21 +1652,21 @@ hipError_t launch_scan(const Plan& p, hipStream_t st) {
 }
 
 hipError_t launch_scatter(const Plan& p, hipStream_t st) {
-  const unsigned own = (unsigned)p.n_own_tiles, sh = (unsigned)(p.n_tiles - p.n_own_tiles);
-  if (own > 0) {
+  if (p.n_tiles == 0) return hipSuccess;
+  const dim3 grid((unsigned)p.n_tiles);
+  if (p.n_tiles > p.n_own_tiles) {
     switch (p.tile_elems) {
-      case 512: hipLaunchKernelGGL((k_scatter<128, 4>), dim3(own), dim3(128), 0, st, p); break;
-      case 2048: hipLaunchKernelGGL((k_scatter<512, 4>), dim3(own), dim3(512), 0, st, p); break;
-      case 8192: hipLaunchKernelGGL((k_scatter<1024, 8>), dim3(own), dim3(1024), 0, st, p); break;
-      default: hipLaunchKernelGGL((k_scatter<512, 8>), dim3(own), dim3(512), 0, st, p); break;
-    }
-  }
-  if (sh > 0) {
-    switch (p.tile_elems) {
-      case 512: hipLaunchKernelGGL((k_scatter_sh<128, 4>), dim3(sh), dim3(128), 0, st, p); break;
-      case 2048: hipLaunchKernelGGL((k_scatter_sh<512, 4>), dim3(sh), dim3(512), 0, st, p); break;
+      case 512: hipLaunchKernelGGL((k_scatter<128, 4, true>), grid, dim3(128), 0, st, p); break;
+      case 2048: hipLaunchKernelGGL((k_scatter<512, 4, true>), grid, dim3(512), 0, st, p); break;
       default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+  }
+  switch (p.tile_elems) {
+    case 512: hipLaunchKernelGGL((k_scatter<128, 4, false>), grid, dim3(128), 0, st, p); break;
+    case 2048: hipLaunchKernelGGL((k_scatter<512, 4, false>), grid, dim3(512), 0, st, p); break;
+    case 8192: hipLaunchKernelGGL((k_scatter<1024, 8, false>), grid, dim3(1024), 0, st, p); break;
+    default: hipLaunchKernelGGL((k_scatter<512, 8, false>), grid, dim3(512), 0, st, p); break;
   }
   return hipGetLastError();
 }

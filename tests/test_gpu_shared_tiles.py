@@ -1,5 +1,5 @@
 """Shared streaming tiles: record batches of fewer than half a tile of records
-are packed several to a tile (at most 64 batches and one tile of records), and
+are packed several to a tile (at most 32 batches and one tile of records), and
 the start-range, count and scatter passes find each record's batch, resource,
 kind and bucket geometry per record.
 
@@ -68,7 +68,7 @@ def test_small_batches(tuning, max_batch, shuffle):
 
 
 def test_batch_limit_per_tile():
-    """Single-record batches: 64 of them fill a shared tile long before its
+    """Single-record batches: 32 of them fill a shared tile long before its
     records do."""
     rng = np.random.default_rng(5)
     base = tg.make_trace(42, 2, 3, 2, 700, 300, regions="tiles", n_regions=4)
