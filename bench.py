@@ -596,7 +596,11 @@ def serving_run(hp, W, lam, host, keep=False):
            "max_phase_us": {k: round(getattr(st, "max_%s_us" % k), 1)
                             for k in ("prep", "grow", "wait", "h2d", "build", "move", "splice", "region")},
            "mean_phase_us": {k: round(getattr(st, "mean_%s_us" % k), 1)
-                             for k in ("prep", "grow", "wait", "h2d", "build", "move", "splice", "region")}}
+                             for k in ("prep", "grow", "wait", "h2d", "build", "move", "splice", "region")},
+           # longest single runtime call while enqueueing a step, and which
+           "max_call_us": round(st.max_call_us, 1),
+           "max_call_site": hp.HPOP_CALL_SITES[st.max_call_site] if 0 <= st.max_call_site < len(hp.HPOP_CALL_SITES)
+           else None}
     if thr0 and thr1:
         # CPU quota throttling of the process's cgroup during the replay (stalls every thread)
         res["cpu_throttled"] = {"times": thr1[0] - thr0[0], "ms": round((thr1[1] - thr0[1]) * 1e-3, 1)}

@@ -391,7 +391,25 @@ typedef struct {
     /* the same phases' mean per step */
     double mean_prep_us, mean_grow_us, mean_wait_us;
     double mean_h2d_us, mean_build_us, mean_move_us, mean_splice_us, mean_region_us;
+    /* Longest single runtime call the worker made while enqueueing a step
+     * (copies, kernel launches, event records; not the step's
+     * synchronisation), in host time, and where: one of HPOP_CALL_*
+     * (-1: none yet). */
+    double max_call_us;
+    int32_t max_call_site;
+    int32_t reserved;
 } hpop_server_stats;
+
+/* Sites of hpop_server_stats.max_call_site. */
+#define HPOP_CALL_EVENT 0    /* a phase's HIP event record */
+#define HPOP_CALL_PAYLOAD 1  /* a host payload's copy to the device */
+#define HPOP_CALL_MOVE 2     /* the list moves: table copy and kernel */
+#define HPOP_CALL_BUILD 3    /* the build of the step's records: descriptor copies and kernels */
+#define HPOP_CALL_TABLES 4   /* list, item and request table copies */
+#define HPOP_CALL_CONTROL 5  /* the scratch control word's copy */
+#define HPOP_CALL_SPLICE 6   /* the prep and splice kernels */
+#define HPOP_CALL_REGION 7   /* the region kernel */
+#define HPOP_CALL_RESULTS 8  /* the copies of trees, lists and error flags to the host */
 
 hpop_status hpop_server_create(const hpop_server_config* cfg, hpop_server** out);
 hpop_status hpop_server_destroy(hpop_server* srv);

@@ -96,7 +96,11 @@ class hpop_server_stats(ctypes.Structure):
                 ("mean_prep_us", ctypes.c_double), ("mean_grow_us", ctypes.c_double), ("mean_wait_us", ctypes.c_double),
                 ("mean_h2d_us", ctypes.c_double), ("mean_build_us", ctypes.c_double),
                 ("mean_move_us", ctypes.c_double), ("mean_splice_us", ctypes.c_double),
-                ("mean_region_us", ctypes.c_double)]
+                ("mean_region_us", ctypes.c_double), ("max_call_us", ctypes.c_double),
+                ("max_call_site", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+HPOP_CALL_SITES = ("event", "payload", "move", "build", "tables", "control", "splice", "region", "results")
 
 
 class hpop_replay_query(ctypes.Structure):

@@ -530,6 +530,11 @@ struct hpop_server {
   hipEvent_t ev[6] = {};
   bool have_events = false;
   double step_prep_us = 0.0, step_wait_us = 0.0;  // of the step just run (set by run_step)
+  // longest single runtime call of the step's enqueueing, and its site (set by run_step)
+  double step_call_us = 0.0;
+  int step_call_site = -1;
+  double max_call_us = 0.0;
+  int max_call_site = -1;
 };
 
 namespace {
@@ -572,8 +577,20 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   std::vector<long long> level_new(S->lists.size(), 0);
   size_t hoff = 0;
   const auto t_start = std::chrono::steady_clock::now();
+  // host time of one runtime call (copies, launches, event records; not the
+  // step's synchronisation), the longest of the step kept with its site
+  auto timed = [&](int site, auto&& f) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const hipError_t r = f();
+    const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    if (us > S->step_call_us) {
+      S->step_call_us = us;
+      S->step_call_site = site;
+    }
+    return r;
+  };
   auto mark = [&](int i) {
-    if (S->have_events) (void)hipEventRecord(S->ev[i], st);
+    if (S->have_events) (void)timed(HPOP_CALL_EVENT, [&] { return hipEventRecord(S->ev[i], st); });
   };
   mark(0);
   for (int q = 0; q < nq; ++q) {
@@ -591,8 +608,9 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     const int64_t* dev_base = nullptr;
     if (Q->mem_space == HPOP_MEM_HOST && Q->host_words) {
       dev_base = (const int64_t*)((char*)S->d_stage.ptr + hoff);
-      const hipError_t e = hipMemcpyAsync((char*)S->d_stage.ptr + hoff, Q->host, Q->host_words * 8,
-                                          hipMemcpyHostToDevice, st);
+      const hipError_t e = timed(HPOP_CALL_PAYLOAD, [&] {
+        return hipMemcpyAsync((char*)S->d_stage.ptr + hoff, Q->host, Q->host_words * 8, hipMemcpyHostToDevice, st);
+      });
       if (e != hipSuccess) return err = std::string("host payload copy: ") + hipGetErrorString(e), HPOP_E_HIP;
       hoff += Q->host_words * 8;
     }
@@ -715,12 +733,15 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   if (!moves.empty()) {
     char* hm = (char*)S->h_out.ptr + b_lists + b_items + b_reqs;
     memcpy(hm, moves.data(), b_moves);
-    hipError_t e = hipMemcpyAsync(S->d_moves.ptr, hm, b_moves, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_list_move, dim3((unsigned)moves.size(), 8), dim3(256), 0, st,
-                         (const ListMove*)S->d_moves.ptr);
-      e = hipGetLastError();
-    }
+    hipError_t e = timed(HPOP_CALL_MOVE, [&] {
+      hipError_t r = hipMemcpyAsync(S->d_moves.ptr, hm, b_moves, hipMemcpyHostToDevice, st);
+      if (r == hipSuccess) {
+        hipLaunchKernelGGL(k_list_move, dim3((unsigned)moves.size(), 8), dim3(256), 0, st,
+                           (const ListMove*)S->d_moves.ptr);
+        r = hipGetLastError();
+      }
+      return r;
+    });
     if (e != hipSuccess) {
       (void)hipStreamSynchronize(st);
       new_heap.release(A);
@@ -755,8 +776,11 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
     err = "pinned host allocation failed";
     return HPOP_E_OOM;
   }
-  rc = En.upload(err);
-  if (rc == HPOP_OK) rc = En.enqueue(true, false, err);
+  (void)timed(HPOP_CALL_BUILD, [&] {
+    rc = En.upload(err);
+    if (rc == HPOP_OK) rc = En.enqueue(true, false, err);
+    return hipSuccess;
+  });
   if (rc != HPOP_OK) return rc;
   mark(3);  // build of the new records
   char* h = (char*)S->h_out.ptr;
@@ -764,10 +788,13 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   memcpy(h + b_lists, items.data(), b_items);
   memcpy(h + b_lists + b_items, reqs.data(), b_reqs);
   char* hres = h + b_lists + b_items + b_reqs + b_moves;
-  hipError_t e = hipSuccess;
-  if (b_lists) e = hipMemcpyAsync(S->d_lists.ptr, h, b_lists, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && b_items) e = hipMemcpyAsync(S->d_items.ptr, h + b_lists, b_items, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(S->d_reqs.ptr, h + b_lists + b_items, b_reqs, hipMemcpyHostToDevice, st);
+  hipError_t e = timed(HPOP_CALL_TABLES, [&] {
+    hipError_t r = hipSuccess;
+    if (b_lists) r = hipMemcpyAsync(S->d_lists.ptr, h, b_lists, hipMemcpyHostToDevice, st);
+    if (r == hipSuccess && b_items) r = hipMemcpyAsync(S->d_items.ptr, h + b_lists, b_items, hipMemcpyHostToDevice, st);
+    if (r == hipSuccess) r = hipMemcpyAsync(S->d_reqs.ptr, h + b_lists + b_items, b_reqs, hipMemcpyHostToDevice, st);
+    return r;
+  });
   if (e != hipSuccess) return err = hipGetErrorString(e), HPOP_E_HIP;
   const Plan& P = En.ws.plan;
   char* o = hres + sizeof(ServCtl);  // results: trees, lists, error flags
@@ -775,26 +802,36 @@ hpop_status run_step(hpop_server* S, std::vector<Query*>& batch, std::string& er
   for (int attempt = 0; attempt < 4; ++attempt) {
     ServCtl ctl{0, (unsigned long long)S->pool_cap, 0, 0};
     memcpy(hres, &ctl, sizeof ctl);
-    e = hipMemcpyAsync(S->d_ctl.ptr, hres, sizeof ctl, hipMemcpyHostToDevice, st);
+    e = timed(HPOP_CALL_CONTROL,
+              [&] { return hipMemcpyAsync(S->d_ctl.ptr, hres, sizeof ctl, hipMemcpyHostToDevice, st); });
     if (e != hipSuccess) return err = hipGetErrorString(e), HPOP_E_HIP;
     if (ni > 0) {
-      hipLaunchKernelGGL(k_serv_prep, dim3((unsigned)((3 * ni + 63) / 64)), dim3(64), 0, st,
-                         (ServItem*)S->d_items.ptr, ni, P, (const ListDev*)S->d_lists.ptr,
-                         (long long*)S->d_frontier.ptr, (ServCtl*)S->d_ctl.ptr);
-      hipLaunchKernelGGL(k_serv_splice, dim3((unsigned)(3 * ni)), dim3(kServThreads), 0, st,
-                         (const ServItem*)S->d_items.ptr, P, (ListDev*)S->d_lists.ptr, (Elem*)S->d_pool.ptr,
-                         (const ServCtl*)S->d_ctl.ptr);
+      (void)timed(HPOP_CALL_SPLICE, [&] {
+        hipLaunchKernelGGL(k_serv_prep, dim3((unsigned)((3 * ni + 63) / 64)), dim3(64), 0, st,
+                           (ServItem*)S->d_items.ptr, ni, P, (const ListDev*)S->d_lists.ptr,
+                           (long long*)S->d_frontier.ptr, (ServCtl*)S->d_ctl.ptr);
+        hipLaunchKernelGGL(k_serv_splice, dim3((unsigned)(3 * ni)), dim3(kServThreads), 0, st,
+                           (const ServItem*)S->d_items.ptr, P, (ListDev*)S->d_lists.ptr, (Elem*)S->d_pool.ptr,
+                           (const ServCtl*)S->d_ctl.ptr);
+        return hipSuccess;
+      });
     }
     mark(4);  // prep and splice
     // on a scratch overflow no list was written and these trees are discarded
-    hipLaunchKernelGGL(k_serv_region, dim3((unsigned)(2 * nq)), dim3(256), 0, st, (const ServReq*)S->d_reqs.ptr,
-                       (const ListDev*)S->d_lists.ptr, (const long long*)S->d_frontier.ptr, (Tree*)S->d_trees.ptr);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipMemcpyAsync(hres, S->d_ctl.ptr, sizeof(ServCtl), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(o, S->d_trees.ptr, b_trees, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && b_lists)
-      e = hipMemcpyAsync(o + b_trees, S->d_lists.ptr, b_lists, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(o + b_trees + b_lists, P.owner_err, nq * 4, hipMemcpyDeviceToHost, st);
+    e = timed(HPOP_CALL_REGION, [&] {
+      hipLaunchKernelGGL(k_serv_region, dim3((unsigned)(2 * nq)), dim3(256), 0, st, (const ServReq*)S->d_reqs.ptr,
+                         (const ListDev*)S->d_lists.ptr, (const long long*)S->d_frontier.ptr, (Tree*)S->d_trees.ptr);
+      return hipGetLastError();
+    });
+    if (e == hipSuccess)
+      e = timed(HPOP_CALL_RESULTS, [&] {
+        hipError_t r = hipMemcpyAsync(hres, S->d_ctl.ptr, sizeof(ServCtl), hipMemcpyDeviceToHost, st);
+        if (r == hipSuccess) r = hipMemcpyAsync(o, S->d_trees.ptr, b_trees, hipMemcpyDeviceToHost, st);
+        if (r == hipSuccess && b_lists)
+          r = hipMemcpyAsync(o + b_trees, S->d_lists.ptr, b_lists, hipMemcpyDeviceToHost, st);
+        if (r == hipSuccess) r = hipMemcpyAsync(o + b_trees + b_lists, P.owner_err, nq * 4, hipMemcpyDeviceToHost, st);
+        return r;
+      });
     mark(5);  // region trees and result copies
     const auto t_sync = std::chrono::steady_clock::now();
     if (attempt == 0) S->step_prep_us = std::chrono::duration<double, std::micro>(t_sync - t_start).count();
@@ -879,6 +916,8 @@ void worker_loop(hpop_server* S) {
     std::string err;
     hpop_status st;
     S->step_prep_us = S->step_wait_us = 0.0;
+    S->step_call_us = 0.0;
+    S->step_call_site = -1;
     const double alloc0 = g_alloc_us;
     {
       std::lock_guard<std::mutex> sg(S->state_mu);
@@ -896,6 +935,10 @@ void worker_loop(hpop_server* S) {
     S->max_prep_us = std::max(S->max_prep_us, S->step_prep_us);
     S->max_wait_us = std::max(S->max_wait_us, S->step_wait_us);
     S->max_grow_us = std::max(S->max_grow_us, grow_us);
+    if (S->step_call_us > S->max_call_us) {
+      S->max_call_us = S->step_call_us;
+      S->max_call_site = S->step_call_site;
+    }
     S->sum_prep_us += S->step_prep_us;
     S->sum_wait_us += S->step_wait_us;
     S->sum_grow_us += grow_us;
@@ -1231,6 +1274,9 @@ hpop_status hpop_server_get_stats(hpop_server* S, hpop_server_stats* out) {
   out->mean_build_us = S->sum_phase_us[2] / ns;
   out->mean_splice_us = S->sum_phase_us[3] / ns;
   out->mean_region_us = S->sum_phase_us[4] / ns;
+  out->max_call_us = S->max_call_us;
+  out->max_call_site = S->max_call_site;
+  out->reserved = 0;
   {
     std::lock_guard<std::mutex> pg(S->staging.mu);
     out->host_staging_bytes = (int64_t)S->staging.bytes;
@@ -1249,6 +1295,8 @@ hpop_status hpop_server_reset_stats(hpop_server* S) {
   S->max_prep_us = S->max_grow_us = S->max_wait_us = 0.0;
   S->sum_prep_us = S->sum_grow_us = S->sum_wait_us = 0.0;
   for (int i = 0; i < 5; ++i) S->max_phase_us[i] = S->sum_phase_us[i] = 0.0;
+  S->max_call_us = 0.0;
+  S->max_call_site = -1;
   return HPOP_OK;
 }
 

@@ -255,9 +255,12 @@ def test_host_staging_area_bounds_and_phase_statistics():
         for f in ("max_prep_us", "max_wait_us", "max_h2d_us", "max_build_us", "max_splice_us", "max_region_us"):
             assert getattr(st, f) > 0, f
             assert 0 < getattr(st, f.replace("max_", "mean_")) <= getattr(st, f), f
+        # the longest enqueueing call: a site of the step, within the longest step
+        assert 0 <= st.max_call_site < len(hp.HPOP_CALL_SITES) and 0 < st.max_call_us <= st.max_step_us
         hp.hpop_server_reset_stats(srv)
         st = hp.hpop_server_get_stats(srv)
         assert st.completed == 0 and st.device_steps == 0 and st.max_step_us == 0 and st.max_build_us == 0
+        assert st.max_call_us == 0 and st.max_call_site == -1
         assert st.host_staging_bytes == 1 << 20
         # the session's lists hold every query's records: one more (empty) query reads them back
         frontier = max(int(c.end.max()) for c in chunks_all)
