@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -66,19 +67,29 @@ def kernel_source_hash():
 
 def load_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary of this
-    kernel and workload, if it was taken on the current kernel sources."""
+    kernel and workload (its own record, else its line in the record of every
+    build kernel), if it was taken on the current kernel sources."""
     p = os.path.join(ROOT, "profiles", "traffic_%s_%s.txt" % (kernel, workload))
-    if not os.path.exists(p):
-        return None
+    whole = not os.path.exists(p)
+    if whole:
+        p = os.path.join(ROOT, "profiles", "traffic_path_%s.txt" % workload)
+        if not os.path.exists(p):
+            return None
     d = {}
     for line in open(p):
         if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
+            k, v = line.rsplit(":", 1) if line.startswith("kernel ") else line.split(":", 1)
             d[k.strip()] = v.strip()
     if d.get("source_hash") != kernel_source_hash():
         return None
     try:
-        return int(d["bytes_per_launch"])
+        if not whole:
+            return int(d["bytes_per_launch"])
+        # "kernel <name>: bytes", the name with its template arguments (one
+        # instantiation runs per build)
+        pat = re.compile(r"::k_%s(<|$)" % re.escape(kernel))
+        hits = [int(v) for k, v in d.items() if k.startswith("kernel ") and pat.search(k)]
+        return hits[0] if len(hits) == 1 else None
     except (KeyError, ValueError):
         return None
 

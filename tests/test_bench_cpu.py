@@ -121,3 +121,27 @@ def test_serving_slices_are_consecutive_prefixes():
         if want_n:
             assert tr.regions[1][1] == max(int(c.end.max()) for c in tr.chunks)
         closes[i] = t1
+
+
+def test_traffic_of_any_build_kernel_from_the_path_record(tmp_path, monkeypatch):
+    """A kernel without a record of its own takes its line of the record of
+    every build kernel (template arguments in the name; k_stats is not
+    k_stats_small)."""
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "traffic_path_w.txt").write_text(
+        "# test\nworkload: w\nsource_hash: abcd\n"
+        "kernel hpop::k_merge_wave: 100\n"
+        "kernel void hpop::k_scatter<512, 4, false>: 300\n"
+        "kernel void hpop::k_stats<256, false>: 50\n"
+        "kernel void hpop::k_stats_small<true>: 7\n"
+        "bytes_per_step: 457\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "abcd")
+    assert bench.load_traffic("scatter", "w") == 300
+    assert bench.load_traffic("merge_wave", "w") == 100
+    assert bench.load_traffic("stats", "w") == 50
+    assert bench.load_traffic("region_part", "w") is None
+    assert bench.load_path_traffic("w") == 457
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "ffff")
+    assert bench.load_traffic("scatter", "w") is None
