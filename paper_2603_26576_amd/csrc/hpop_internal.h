@@ -178,7 +178,7 @@ struct Plan {
   unsigned long long* racc;          // [n_racc][9] per-region partial sums and maxima, zero between launches
   int64_t n_racc;
   int32_t n_owners;
-  int32_t pad2;
+  int32_t seg_group;                 // > 1: the per-segment passes take segments in groups (many small segments)
 };
 
 }  // namespace hpop

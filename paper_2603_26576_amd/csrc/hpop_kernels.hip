@@ -871,11 +871,8 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
 
 constexpr int kSegRows = 8;
 
-template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
-  const int lane = threadIdx.x & 63;
-  const long long seg = (long long)blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6);
-  if (seg >= p.n_segs) return;
+// The carry pass of segment `seg` by one whole wave (every lane calls).
+__device__ __forceinline__ void carry_segment(const Plan& p, long long seg, int lane) {
   const SegDesc sd = p.segs[seg];
   const SegStats st = p.stats[seg];
   const long long nb = sd.nb;
@@ -920,10 +917,15 @@ __global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
 }
 
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_base(Plan p) {
+__global__ __launch_bounds__(THREADS) void k_carry(Plan p) {
   const int lane = threadIdx.x & 63;
   const long long seg = (long long)blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6);
   if (seg >= p.n_segs) return;
+  carry_segment(p, seg, lane);
+}
+
+// The base pass of segment `seg` by one whole wave (every lane calls).
+__device__ __forceinline__ void base_segment(const Plan& p, long long seg, int lane) {
   const SegDesc sd = p.segs[seg];
   const long long nb = sd.nb;
   long long run[3] = {0, 0, 0};
@@ -950,6 +952,102 @@ __global__ __launch_bounds__(THREADS) void k_base(Plan p) {
   }
   if (lane == 0) {
     for (int l = 0; l < 3; ++l) p.seg_total[seg * 3 + l] = run[l];
+  }
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_base(Plan p) {
+  const int lane = threadIdx.x & 63;
+  const long long seg = (long long)blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6);
+  if (seg >= p.n_segs) return;
+  base_segment(p, seg, lane);
+}
+
+// Plans of many small segments (a batch of small traces): a wave takes
+// kSegGroup consecutive segments. A segment of at most kSegGroup buckets is
+// scanned by its own group of kSegGroup lanes (a lane per bucket, scans by
+// lane shuffles within the group); the larger ones of the wave follow, one
+// after another, with the whole wave as above.
+constexpr int kSegGroup = 8;
+
+// inclusive scan over the kSegGroup lanes of a group (identity in lanes past
+// the segment's buckets)
+template <class Op>
+__device__ __forceinline__ long long group_incl_scan(long long v, int k) {
+#pragma unroll
+  for (int d = 1; d < kSegGroup; d <<= 1) {
+    const long long o = __shfl_up(v, (unsigned)d, kSegGroup);
+    if (k >= d) v = Op::apply(v, o);
+  }
+  return v;
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_carry_grouped(Plan p) {
+  const int lane = threadIdx.x & 63, k = lane & (kSegGroup - 1);
+  const long long seg0 = ((long long)blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6)) * kSegGroup;
+  if (seg0 >= p.n_segs) return;
+  const long long seg = seg0 + (lane / kSegGroup);
+  const bool have = seg < p.n_segs;
+  const SegDesc sd = have ? p.segs[seg] : SegDesc{0, 0, 0};
+  const bool small = have && sd.nb <= kSegGroup;
+  if (small) {  // uniform within each group
+    const SegStats st = p.stats[seg];
+    const long long init = st.min_s > st.max_s ? -1 : (long long)st.min_s - 1;
+    long long v[3] = {LLONG_MIN, LLONG_MIN, LLONG_MIN};
+    if (k < sd.nb) {
+      const long long gb = sd.bucket_begin + k;
+      p.bucket_seg[gb] = (int32_t)seg;
+      const unsigned long long* q = p.maxend + gb * 3;
+      const unsigned long long m0 = q[0], m1 = q[1], m2 = q[2];
+      v[0] = m0 ? (long long)m0 : LLONG_MIN;
+      v[1] = m1 && (long long)m1 > v[0] ? (long long)m1 : v[0];
+      v[2] = m2 && (long long)m2 > v[1] ? (long long)m2 : v[1];
+    }
+    long long last2 = init;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const long long inc = group_incl_scan<OpMax>(v[l], k);
+      long long ex = __shfl_up(inc, 1u, kSegGroup);
+      if (k == 0) ex = LLONG_MIN;
+      if (k < sd.nb) p.carry[(sd.bucket_begin + k) * 3 + l] = ex > init ? ex : init;
+      if (l == 2) last2 = __shfl(inc, kSegGroup - 1, kSegGroup);
+    }
+    const long long r2 = last2 > init ? last2 : init;
+    if (k == 0) p.stats[seg].max_e = (unsigned long long)(r2 > init ? r2 : (init + 1 > 0 ? init + 1 : 0));
+  }
+  unsigned long long big = __ballot(k == 0 && have && !small);
+  while (big) {
+    const int g = __ffsll((long long)big) - 1;
+    big &= big - 1;
+    carry_segment(p, seg0 + g / kSegGroup, lane);
+  }
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_base_grouped(Plan p) {
+  const int lane = threadIdx.x & 63, k = lane & (kSegGroup - 1);
+  const long long seg0 = ((long long)blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6)) * kSegGroup;
+  if (seg0 >= p.n_segs) return;
+  const long long seg = seg0 + (lane / kSegGroup);
+  const bool have = seg < p.n_segs;
+  const SegDesc sd = have ? p.segs[seg] : SegDesc{0, 0, 0};
+  const bool small = have && sd.nb <= kSegGroup;
+  if (small) {  // uniform within each group
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const long long v = k < sd.nb ? p.bsum[(sd.bucket_begin + k) * 3 + l] : 0;
+      const long long inc = group_incl_scan<OpSum>(v, k);
+      if (k < sd.nb) p.base[(sd.bucket_begin + k) * 3 + l] = inc - v;
+      const long long tot = __shfl(inc, kSegGroup - 1, kSegGroup);
+      if (k == 0) p.seg_total[seg * 3 + l] = tot;
+    }
+  }
+  unsigned long long big = __ballot(k == 0 && have && !small);
+  while (big) {
+    const int g = __ffsll((long long)big) - 1;
+    big &= big - 1;
+    base_segment(p, seg0 + g / kSegGroup, lane);
   }
 }
 
@@ -1673,7 +1771,10 @@ hipError_t launch_scatter(const Plan& p, hipStream_t st) {
 
 hipError_t launch_carry(const Plan& p, hipStream_t st) {
   if (p.n_segs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_carry<64>, dim3((unsigned)p.n_segs), dim3(64), 0, st, p);  // a wave per segment, spread over the CUs
+  if (p.seg_group > 1)
+    hipLaunchKernelGGL(k_carry_grouped<64>, dim3((unsigned)((p.n_segs + kSegGroup - 1) / kSegGroup)), dim3(64), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_carry<64>, dim3((unsigned)p.n_segs), dim3(64), 0, st, p);  // a wave per segment, spread over the CUs
   return hipGetLastError();
 }
 
@@ -1696,7 +1797,10 @@ hipError_t launch_merge_block(const Plan& p, int cap, hipStream_t st) {
 
 hipError_t launch_base(const Plan& p, hipStream_t st) {
   if (p.n_segs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_base<64>, dim3((unsigned)p.n_segs), dim3(64), 0, st, p);  // a wave per segment, spread over the CUs
+  if (p.seg_group > 1)
+    hipLaunchKernelGGL(k_base_grouped<64>, dim3((unsigned)((p.n_segs + kSegGroup - 1) / kSegGroup)), dim3(64), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_base<64>, dim3((unsigned)p.n_segs), dim3(64), 0, st, p);  // a wave per segment, spread over the CUs
   return hipGetLastError();
 }
 

@@ -147,6 +147,7 @@ struct hpop_session {
   std::vector<std::pair<int64_t, int64_t>> regions;  // [t0, t1), or the span of a per-resource region
   std::vector<std::vector<hpop::IvlDesc>> region_ivls;  // per region: its intervals (empty: [t0, t1))
   unsigned long long version = 0;
+  bool copies_pending = false;  // record copies enqueued on `stream` since a batch last waited for it
   hpop::PinnedBuf staging;
   hpop_tuning tuning{};
   bool timing = false;

@@ -268,7 +268,7 @@ hpop_status Workspace::prepare(Alloc& a, long long n_chunks, long long n_tiles, 
   p.queue = carve<unsigned int>(cur, n_buckets);
   p.owner_err = carve<unsigned int>(cur, n_owners);
   p.n_owners = (int32_t)n_owners;
-  p.pad2 = 0;
+  p.seg_group = 1;
   d_regions = carve<RegionDesc>(cur, n_regions);
   d_trees = carve<Tree>(cur, n_regions);
   p.racc = carve<unsigned long long>(cur, 9 * n_regions);
@@ -464,6 +464,9 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
   if (st != HPOP_OK) return st;
   ws.plan.n_tiles = tiles;
   ws.plan.n_own_tiles = own_tiles;
+  // many segments of a few buckets each (batches of small traces): the
+  // per-segment passes take them eight to a wave
+  ws.plan.seg_group = n_segs >= 4096 && buckets <= 8 * n_segs ? 8 : 1;
   ws.plan.tile_elems = tile;
   ws.plan.cap = cap;
   ws.plan.slot_cap = slots;
@@ -872,6 +875,7 @@ hpop_status hpop_add_events_multi(hpop_session* s, const hpop_event_chunk* chunk
   s->arena.used = s->arena_used;
   if (!s->arena.reserve(s->alloc, s->arena_used + need, true))
     return fail(s, HPOP_E_OOM, "device allocation for " + std::to_string(need) + " bytes of records failed");
+  s->copies_pending = true;  // the arena's growth and the records' copies go on the session stream
   char* base = (char*)s->arena.ptr;
   size_t off = s->arena_used;
   std::vector<RecChunk> added;
@@ -1093,11 +1097,14 @@ hpop_status hpop_batch_compute(hpop_session* const* sessions, int32_t k, uint32_
     if (sessions[i]->device != sessions[0]->device) return fail(nullptr, HPOP_E_ARG, "sessions on different devices");
   }
   hpop_session* s0 = sessions[0];
-  // records of the other sessions were copied on their own streams
+  // records of the other sessions were copied on their own streams: wait for
+  // those with copies since their last wait (a wait on each idle stream of a
+  // thousand sessions would cost more than the build)
   for (int i = 1; i < k; ++i)
-    if (sessions[i]->stream != s0->stream) {
+    if (sessions[i]->copies_pending && sessions[i]->stream != s0->stream) {
       hipError_t e = hipStreamSynchronize(sessions[i]->stream);
       if (e != hipSuccess) return fail(nullptr, HPOP_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+      sessions[i]->copies_pending = false;
     }
   std::string err;
   s0->last_timed_batch = true;

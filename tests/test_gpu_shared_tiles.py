@@ -162,3 +162,30 @@ def test_batched_sessions_share_tiles(tile):
     finally:
         for s in sessions:
             hp.hpop_session_destroy(s)
+
+
+def many_resources_trace(seed, n_hosts, n_devices, big_every):
+    """Mostly resources of 0-40 records (one bucket each), every big_every-th
+    one with thousands (many buckets)."""
+    rng = np.random.default_rng(seed)
+    chunks = []
+    for r in range(n_hosts + n_devices):
+        n = int(rng.integers(3000, 6000)) if r % big_every == 0 else int(rng.integers(0, 41))
+        if n == 0:
+            continue
+        s = np.sort(rng.integers(0, 1 << 30, size=n)).astype(np.int64)
+        e = s + rng.integers(0, 1 << 22, size=n)
+        kinds = (tg.HOST_USEFUL, tg.HOST_OFFLOAD, tg.HOST_MPI) if r < n_hosts else (tg.DEV_KERNEL, tg.DEV_MEMOP)
+        k = rng.integers(0, len(kinds), size=n)
+        for i, kd in enumerate(kinds):
+            if (k == i).any():
+                chunks.append(tg.Chunk(r, kd, s[k == i], e[k == i]))
+    return tg.Trace(n_hosts, n_devices, chunks, [(0, 1 << 30), (1 << 28, 1 << 29), (12345, (1 << 30) + (1 << 22))])
+
+
+@pytest.mark.parametrize("tuning", [{"bucket_target": 64, "tile_elems": 512},
+                                    {"bucket_target": 16, "tile_elems": 2048, "scatter_slots": -1}])
+def test_thousands_of_small_resources(tuning):
+    """5000 resources, most of a bucket or two: the per-resource passes take
+    them eight to a wave; the large ones among them take a whole wave."""
+    check(many_resources_trace(12, 3000, 2000, 97), tuning)
