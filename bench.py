@@ -916,7 +916,7 @@ def main():
     ap.add_argument("--serving-queries", type=int, default=2000)
     ap.add_argument("--serving-lambdas", default="2000,5000,10000,20000")
     ap.add_argument("--serving-host-lambdas", default="2000,5000,10000,20000",
-                    help="runs with payloads in host memory")
+                    help="runs with payloads in host memory (0: none)")
     ap.add_argument("--no-small", action="store_true", help="skip the small-trace latency leg")
     ap.add_argument("--no-mid", action="store_true", help="skip the mid-trace leg")
     ap.add_argument("--no-entered", action="store_true", help="skip the regions-entered-repeatedly leg")
@@ -955,7 +955,7 @@ def main():
         return
     if args.serving_only:
         lams = [int(x) for x in args.serving_lambdas.split(",") if x]
-        host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x]
+        host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x and int(x) > 0]
         print(json.dumps({"serving": serving_leg(hp, lams, args.serving_queries, host_lambdas=host_lams)}), flush=True)
         return
     log("generating workload %s (scale %g)" % (args.workload, args.scale))
@@ -1020,7 +1020,7 @@ def main():
         log("batched: %s" % out["batched"])
     if not args.no_serving and args.serving_queries > 0:
         lams = [int(x) for x in args.serving_lambdas.split(",") if x]
-        host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x]
+        host_lams = [int(x) for x in args.serving_host_lambdas.split(",") if x and int(x) > 0]
         log("serving leg: lambdas %s, %d queries each" % (lams, args.serving_queries))
         out["serving"] = serving_leg(hp, lams, args.serving_queries, host_lambdas=host_lams)
     if not args.no_streams:
