@@ -940,6 +940,7 @@ hpop_status hpop_session_synchronize(hpop_session* s) {
   if (!s) return fail(nullptr, HPOP_E_ARG, "null session");
   hipError_t e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return fail(s, HPOP_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  s->copies_pending = false;
   return HPOP_OK;
 }
 

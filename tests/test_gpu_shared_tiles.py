@@ -189,3 +189,53 @@ def test_thousands_of_small_resources(tuning):
     """5000 resources, most of a bucket or two: the per-resource passes take
     them eight to a wave; the large ones among them take a whole wave."""
     check(many_resources_trace(12, 3000, 2000, 97), tuning)
+
+
+@pytest.mark.parametrize("device", [False, True])
+def test_batch_sees_records_added_between_batched_calls(device):
+    """Each session copies its records on its own stream; a batched call waits
+    only for sessions that copied records since the last wait. Records added
+    after one batched call (to a session that is not the first) are in the
+    next one, and a call with nothing new repeats the same trees."""
+    rng = np.random.default_rng(31)
+    traces = [tg.make_trace(int(rng.integers(0, 1 << 30)), 2, 2, 2, 3000, 800, regions="nested", n_regions=2)
+              for _ in range(6)]
+    halves = []
+    for tr in traces:
+        first, second = [], []
+        for c in tr.chunks:
+            h = len(c.start) // 2
+            first.append(tg.Chunk(c.resource, c.kind, c.start[:h].copy(), c.end[:h].copy()))
+            second.append(tg.Chunk(c.resource, c.kind, c.start[h:].copy(), c.end[h:].copy()))
+        halves.append((tg.Trace(tr.n_hosts, tr.n_devices, first, list(tr.regions)), second))
+    sessions, keep = [], []
+    try:
+        for tr, _ in halves:
+            s, kp = new_session(tr, device=device, tuning={"bucket_target": 64, "tile_elems": 512})
+            sessions.append(s)
+            keep.append(kp)
+
+        def check_all(trees, trs):
+            k = 0
+            for tr in trs:
+                want = oracle.compute(tr)
+                for g in range(len(tr.regions)):
+                    np.testing.assert_array_equal(hp.tree_sums(trees[k]), want["sums"][g])
+                    np.testing.assert_array_equal(hp.tree_ratios(trees[k]).view(np.int64),
+                                                  want["ratios"][g].view(np.int64))
+                    k += 1
+
+        check_all(hp.hpop_batch_compute(sessions), [tr for tr, _ in halves])
+        # the second half of sessions 2 and 5 only, then at once a batched call
+        for i in (2, 5):
+            keep.append(hp.add_chunks(sessions[i], [(c.resource, c.kind, c.start, c.end) for c in halves[i][1]],
+                                      device=device))
+        now = [traces[i] if i in (2, 5) else halves[i][0] for i in range(len(traces))]
+        got = hp.hpop_batch_compute(sessions)
+        check_all(got, now)
+        again = hp.hpop_batch_compute(sessions, hp.HPOP_FORCE_REBUILD)
+        for a, b in zip(got, again):
+            assert bytes(a) == bytes(b)
+    finally:
+        for s in sessions:
+            hp.hpop_session_destroy(s)
