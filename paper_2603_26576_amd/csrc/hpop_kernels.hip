@@ -57,6 +57,13 @@ __global__ void k_reset(Plan p) {
 // n_own_tiles), reusing those kernels' LDS arrays where the layouts agree.
 // ----------------------------------------------------------------------------
 
+// One record in the 8 B bucketed form, stored past the caches: the regrouped
+// records (1 GB for 1.25e8) are read back only by the merge, after the
+// scatter has finished.
+__device__ __forceinline__ void put_rec8(uint2* dst, unsigned int key, unsigned int end) {
+  __builtin_nontemporal_store((unsigned long long)key | ((unsigned long long)end << 32), (unsigned long long*)dst);
+}
+
 // The chunks of one shared tile, staged in LDS.
 struct ShTile {
   const int64_t* s[kTileChunks];
@@ -373,7 +380,8 @@ __device__ __forceinline__ void scatter_shared(const Plan& p, long long tile, Sh
         region(gbk[k], ub2, ucap);
         if (nr[k]) {
           const unsigned long long rank = (bb & 0xFFFFFFFFull) + rk[k];
-          if ((long long)rank < ucap) units[ub + (long long)rank] = make_uint2(kx[k], ex[k]);
+          // non-temporal: written once here and read once by the merge, never cached in between
+          if ((long long)rank < ucap) put_rec8(units + ub + (long long)rank, kx[k], ex[k]);
         } else {
           put_wide(k, ub, ucap, (bb >> 32) + rk[k]);
         }
@@ -832,7 +840,8 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
         if (nr[k]) {
           const unsigned long long rank = (bb & 0xFFFFFFFFull) + rk[k];
           const long long ucap = scap ? 2 * scap : 2 * (long long)p.counts[sd.bucket_begin + bk[k]];
-          if ((long long)rank < ucap) units[ub + (long long)rank] = make_uint2(kx[k], ex[k]);
+          // non-temporal: written once here and read once by the merge, never cached in between
+          if ((long long)rank < ucap) put_rec8(units + ub + (long long)rank, kx[k], ex[k]);
         } else {
           long long ub2, ucap;
           region(sd.bucket_begin + bk[k], ub2, ucap);
