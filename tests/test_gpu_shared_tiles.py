@@ -239,3 +239,25 @@ def test_batch_sees_records_added_between_batched_calls(device):
     finally:
         for s in sessions:
             hp.hpop_session_destroy(s)
+
+
+def test_slot_overflow_in_shared_tiles_falls_back_to_exact_offsets():
+    """Small batches (shared tiles) whose buckets outgrow 64 fixed scatter
+    slots: the build is redone with exact offsets (count pass included) and
+    gives the oracle's results; with enough slots the single pass is back."""
+    rng = np.random.default_rng(17)
+    base = tg.make_trace(44, 3, 3, 4, 6000, 1500, w_range=(0.5, 1.5), regions="nested", n_regions=3)
+    tr = in_batches(base, rng, 120, True)
+    want = oracle.compute(tr)
+    s, keep = new_session(tr)
+    try:
+        hp.hpop_session_enable_timing(s, 1)
+        for tuning, exact in (({"bucket_target": 256, "tile_elems": 512, "scatter_slots": 64}, True),
+                              ({"bucket_target": 256, "tile_elems": 512}, False)):
+            print("case: tuning=%s" % tuning, flush=True)
+            hp.hpop_session_set_tuning(s, **tuning)
+            assert_same(engine_results(s, tr, hp.HPOP_FORCE_REBUILD), want, str(tuning))
+            names = [n for n, _ in hp.hpop_session_stage_times(s)]
+            assert ("hist" in names) == exact, (tuning, names)
+    finally:
+        hp.hpop_session_destroy(s)
