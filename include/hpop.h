@@ -276,6 +276,14 @@ hpop_status hpop_session_get_tuning(const hpop_session* s, hpop_tuning* out);
 hpop_status hpop_session_enable_timing(hpop_session* s, int32_t on);
 hpop_status hpop_session_stage_times(const hpop_session* s, int32_t cap, const char** names,
                                      float* ms, int32_t* n_out);
+/* Time only one stage while timing is enabled (names as stage_times reports
+ * them: "reset", "stats", "hist", "scan", "scatter", "carry", "merge_wave",
+ * "merge_block", "base", "region"): one event right before its launches and
+ * one right after, instead of one after every stage, so timing perturbs the
+ * build less. NULL or "" times every stage again. A stage the build does not
+ * run yields no entry. HPOP_E_ARG for an unknown name. Applies to the
+ * session's own builds and to batched builds it leads. */
+hpop_status hpop_session_time_stage(hpop_session* s, const char* stage);
 
 /* Autotuner: times candidate tunings on the given sessions (batched when
  * k > 1), keeps the fastest, applies it to every session and returns it.

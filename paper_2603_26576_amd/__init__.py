@@ -143,6 +143,7 @@ _SIGS = {
     "hpop_session_set_tuning": (_I32, [_P, ctypes.POINTER(hpop_tuning)]),
     "hpop_session_get_tuning": (_I32, [_P, ctypes.POINTER(hpop_tuning)]),
     "hpop_session_enable_timing": (_I32, [_P, _I32]),
+    "hpop_session_time_stage": (_I32, [_P, ctypes.c_char_p]),
     "hpop_session_stage_times": (_I32, [_P, _I32, ctypes.POINTER(ctypes.c_char_p),
                                         ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_I32)]),
     "hpop_autotune": (_I32, [ctypes.POINTER(_P), _I32, ctypes.c_char_p, ctypes.POINTER(hpop_tuning)]),
@@ -390,6 +391,10 @@ def hpop_session_get_tuning(s):
 
 def hpop_session_enable_timing(s, on=True):
     _check(lib().hpop_session_enable_timing(s, 1 if on else 0), s)
+
+
+def hpop_session_time_stage(s, stage=None):
+    _check(lib().hpop_session_time_stage(s, stage.encode() if stage else None), s)
 
 
 def hpop_session_stage_times(s):

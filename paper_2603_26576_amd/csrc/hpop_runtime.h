@@ -123,6 +123,7 @@ struct Engine {
   hpop_status assemble_plan(const hpop_tuning& tun, const std::vector<long long>& seg_count,
                             const std::vector<char>& seg_host, int n_owners, long long times, std::string& err);
   hpop_status upload(std::string& err);
+  std::string timing_stage;  // non-empty: time only this stage (see hpop_session_time_stage)
   hpop_status enqueue(bool build, bool with_timing, std::string& err);
   hpop_status collect_timing(std::string& err);
   hpop_status run(hpop_session* const* ss, int k, uint32_t flags, hpop_metric_tree* out, bool timing,
@@ -151,6 +152,7 @@ struct hpop_session {
   hpop::PinnedBuf staging;
   hpop_tuning tuning{};
   bool timing = false;
+  std::string timing_stage;
   bool last_timed_batch = false;
   hpop::Engine engine;
   hpop::Engine batch_engine;

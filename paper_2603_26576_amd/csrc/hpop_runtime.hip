@@ -527,41 +527,60 @@ hpop_status Engine::enqueue(bool build, bool with_timing, std::string& err) {
   }
   mark_names.clear();
   int ev = 0;
+  // every stage: one event before the first and one after each; one named
+  // stage (timing_stage): an event right before it and one right after it
+  const bool one = with_timing && !timing_stage.empty();
+  auto pre = [&](const char* name) -> hipError_t {
+    if (!one || timing_stage != name) return hipSuccess;
+    return hipEventRecord(events[ev++], st);
+  };
   auto mark = [&](const char* name) -> hipError_t {
-    if (!with_timing) return hipSuccess;
+    if (!with_timing || (one && (!name || timing_stage != name))) return hipSuccess;
     if (name) mark_names.push_back(name);
     return hipEventRecord(events[ev++], st);
   };
   HPOP_HIP(mark(nullptr), "hipEventRecord");
   if (build) {
+    HPOP_HIP(pre("reset"), "hipEventRecord");
     HPOP_HIP(launch_reset(p, st), "k_reset");
     HPOP_HIP(mark("reset"), "hipEventRecord");
+    HPOP_HIP(pre("stats"), "hipEventRecord");
     HPOP_HIP(launch_stats(p, st), "k_stats");
     HPOP_HIP(mark("stats"), "hipEventRecord");
     if (p.slot_cap == 0) {  // exact offsets: count, then scan, then scatter
-      HPOP_HIP(launch_hist(p, st), "k_hist");
+      HPOP_HIP(pre("hist"), "hipEventRecord");
+    HPOP_HIP(launch_hist(p, st), "k_hist");
       HPOP_HIP(mark("hist"), "hipEventRecord");
+      HPOP_HIP(pre("scan"), "hipEventRecord");
       HPOP_HIP(launch_scan(p, st), "k_scan");
       HPOP_HIP(mark("scan"), "hipEventRecord");
+      HPOP_HIP(pre("scatter"), "hipEventRecord");
       HPOP_HIP(launch_scatter(p, st), "k_scatter");
       HPOP_HIP(mark("scatter"), "hipEventRecord");
     } else {  // fixed slots: scatter in one pass, then offsets of the merged intervals
+      HPOP_HIP(pre("scatter"), "hipEventRecord");
       HPOP_HIP(launch_scatter(p, st), "k_scatter");
       HPOP_HIP(mark("scatter"), "hipEventRecord");
+      HPOP_HIP(pre("scan"), "hipEventRecord");
       HPOP_HIP(launch_scan(p, st), "k_scan");
       HPOP_HIP(mark("scan"), "hipEventRecord");
     }
+    HPOP_HIP(pre("carry"), "hipEventRecord");
     HPOP_HIP(launch_carry(p, st), "k_carry");
     HPOP_HIP(mark("carry"), "hipEventRecord");
+    HPOP_HIP(pre("merge_wave"), "hipEventRecord");
     HPOP_HIP(launch_merge_wave(p, st), "k_merge_wave");
     HPOP_HIP(mark("merge_wave"), "hipEventRecord");
+    HPOP_HIP(pre("merge_block"), "hipEventRecord");
     HPOP_HIP(launch_merge_block(p, p.cap, st), "k_merge_block");
     HPOP_HIP(mark("merge_block"), "hipEventRecord");
+    HPOP_HIP(pre("base"), "hipEventRecord");
     HPOP_HIP(launch_base(p, st), "k_base");
     HPOP_HIP(mark("base"), "hipEventRecord");
   }
   int max_res = 0;
   for (const RegionDesc& rd : h_regions) max_res = std::max(max_res, rd.n_hosts + rd.n_devices);
+  HPOP_HIP(pre("region"), "hipEventRecord");
   HPOP_HIP(launch_region(p, ws.d_regions, nreg, max_res, ws.d_trees, ws.d_times, ws.d_ivls, (long long)h_ivls.size(),
                          ws.d_macc, st),
            "k_region");
@@ -1177,6 +1196,19 @@ hpop_status hpop_session_get_tuning(const hpop_session* s, hpop_tuning* out) {
 hpop_status hpop_session_enable_timing(hpop_session* s, int32_t on) {
   if (!s) return HPOP_E_ARG;
   s->timing = on != 0;
+  return HPOP_OK;
+}
+
+hpop_status hpop_session_time_stage(hpop_session* s, const char* stage) {
+  if (!s) return HPOP_E_ARG;
+  static const char* const known[] = {"reset", "stats", "hist", "scan", "scatter", "carry",
+                                      "merge_wave", "merge_block", "base", "region"};
+  std::string name = stage ? stage : "";
+  if (!name.empty() && std::find(std::begin(known), std::end(known), name) == std::end(known))
+    return fail(s, HPOP_E_ARG, "unknown stage name: " + name);
+  s->timing_stage = name;
+  s->engine.timing_stage = name;
+  s->batch_engine.timing_stage = name;
   return HPOP_OK;
 }
 

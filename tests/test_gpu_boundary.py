@@ -130,3 +130,31 @@ def test_server_argument_errors():
         assert reg.sumK == 1 and reg.E == 10 and glob.E == 2
     finally:
         hp.hpop_server_destroy(srv)
+
+
+def test_time_one_stage():
+    """Timing every stage, then one named stage only (two events around its
+    launches), then every stage again; the results never change."""
+    tr = tg.make_trace(5, 2, 2, 2, 3000, 800, regions="tiles", n_regions=3)
+    want = oracle.compute(tr)
+    s, keep = new_session(tr)
+    try:
+        hp.hpop_session_enable_timing(s, True)
+        assert_same(engine_results(s, tr, hp.HPOP_FORCE_REBUILD), want, "every stage timed")
+        names_all = [n for n, _ in hp.hpop_session_stage_times(s)]
+        assert names_all[:2] == ["reset", "stats"] and "merge_wave" in names_all and names_all[-1] == "region"
+        hp.hpop_session_time_stage(s, "scatter")
+        assert_same(engine_results(s, tr, hp.HPOP_FORCE_REBUILD), want, "scatter timed")
+        st = hp.hpop_session_stage_times(s)
+        assert [n for n, _ in st] == ["scatter"] and st[0][1] > 0
+        hp.hpop_session_time_stage(s, "hist")  # the count pass: not run with fixed slots
+        assert_same(engine_results(s, tr, hp.HPOP_FORCE_REBUILD), want, "hist timed")
+        assert hp.hpop_session_stage_times(s) == []
+        with pytest.raises(hp.HpopError) as ei:
+            hp.hpop_session_time_stage(s, "no_such_stage")
+        assert ei.value.status == hp.HPOP_E_ARG
+        hp.hpop_session_time_stage(s, None)
+        assert_same(engine_results(s, tr, hp.HPOP_FORCE_REBUILD), want, "every stage again")
+        assert [n for n, _ in hp.hpop_session_stage_times(s)] == names_all
+    finally:
+        hp.hpop_session_destroy(s)
