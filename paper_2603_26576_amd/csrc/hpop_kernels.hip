@@ -1202,7 +1202,7 @@ __device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (
 }
 
 // Flatten of one sorted bucket by one wave: lane owns sorted positions
-// [lane*IPL, lane*IPL + cnt), kept in registers through the three phases
+// [lane*IPL, lane*IPL + IPL), kept in registers through the three phases
 // (running max of ends, measures and break counts, component writes). A
 // record outside level l takes part as the empty pair (0, 0), which changes
 // no maximum, measure or break, so the phases need no branches; only the
@@ -1216,17 +1216,10 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
                                              const long long (&maxe)[3]) {
   const int lane = threadIdx.x & 63;
   const int q0 = lane * IPL;
-  const int cnt = min(max(ni - q0, 0), IPL);
+  // positions past the bucket already hold the padding pair (key 3, end 0)
   unsigned int kv[IPL], ev[IPL];
   lds_load<IPL>(W.key + q0, kv);
   lds_load<IPL>(W.end + q0, ev);
-#pragma unroll
-  for (int j = 0; j < IPL; ++j) {
-    if (j >= cnt) {
-      kv[j] = 3u;
-      ev[j] = 0;
-    }
-  }
   // start - lo + 1, the same shift as the ends (recomputed at each use: fewer
   // live registers than keeping it)
   auto sv = [&](int j) { return (kv[j] >> 2) + 1u; };
@@ -1242,8 +1235,11 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
     for (int j = 0; j < IPL; ++j) tmax = max(tmax, e_in(j, l));
     unsigned int tot;
     const unsigned int ex = wave_excl_scan_u32<OpMaxU>(tmax, 0u, tot);
-    const long long c = carry[l];
-    const unsigned int cr = c < lo ? 0u : (c - lo >= 0xFFFFFFFFll ? 0xFFFFFFFFu : (unsigned int)(c - lo + 1));
+    // carry - lo + 1 clamped to [0, 2^32 - 1], in wave-uniform 32-bit halves
+    const long long d = carry[l] - lo;
+    const int dh = (int)(d >> 32);
+    const unsigned int dl = (unsigned int)d;
+    const unsigned int cr = dh < 0 ? 0u : (dh > 0 || dl == 0xFFFFFFFFu ? 0xFFFFFFFFu : dl + 1u);
     M[l] = max(ex, cr);
   }
   // per-lane measure per level; break counts packed in 10-bit fields (<= 512 each)
@@ -1290,10 +1286,9 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
       const unsigned int s = s_in(j, l), e = e_in(j, l);
-      if (s > Ml) {
-        stage[r] = make_uint2(s - 1, Pl);  // CompN {start - lo, measure before}
-        ++r;
-      }
+      const bool brk = s > Ml;
+      if (brk) stage[r] = make_uint2(kv[j] >> 2, Pl);  // CompN {start - lo, measure before}
+      r += brk ? 1u : 0u;
       const unsigned int b = max(s, Ml);
       Pl += max(e, b) - b;
       Ml = max(Ml, e);
@@ -1321,13 +1316,17 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
   }
 }
 
-// Sort of one bucket of ni <= 64*IPL records into W, then its flatten.
-// Returns false (nothing written) when the bucket must take the block path.
+// Sort of one bucket of 64*(IPL-1) < ni <= 64*IPL records into W, then its
+// flatten: every round but the last is full, so only the last one tests for
+// positions past the bucket. Returns false (nothing written) when the bucket
+// must take the block path.
 template <int IPL>
 __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
                                             const uint2* rec, const long long (&carry)[3],
                                             const long long (&maxe)[3]) {
   const int lane = threadIdx.x & 63;
+  // round r holds position lane + 64 r; rounds before the last are inside the bucket
+  auto in_bucket = [&](int r) { return r < IPL - 1 || lane + 64 * r < ni; };
   unsigned int kr[IPL], er[IPL], rk[IPL];
   // every lane loads every round, from a position clamped into the bucket
   // (ni >= 1): the loads issue back to back instead of one masked block (and
@@ -1335,14 +1334,17 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   uint2 x[IPL];
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
-    const int i = lane + 64 * r;
-    x[r] = rec[i < ni ? i : ni - 1];  // already relative to lo: (start - lo) << 2 | slot, end - lo + 1
+    // a 32-bit byte offset from the wave-uniform base (ni <= kWaveCap)
+    const unsigned int i = (unsigned int)(r < IPL - 1 ? lane + 64 * r : min(lane + 64 * r, ni - 1));
+    x[r] = *(const uint2*)((const char*)rec + 8u * i);  // relative to lo: (start - lo) << 2 | slot, end - lo + 1
   }
+  // a position past the bucket keeps the padding pair of the flatten: key 3
+  // (rank 3, start lo), end 0; it is stored at its own index below
   unsigned int kor = 0;
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
-    const bool in = lane + 64 * r < ni;
-    kr[r] = in ? x[r].x : 0u;
+    const bool in = in_bucket(r);
+    kr[r] = in ? x[r].x : 3u;
     er[r] = in ? x[r].y : 0u;
     kor |= kr[r];
   }
@@ -1359,17 +1361,18 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   for (int j = 0; j < wpl; ++j) W.bins[lane * wpl + j] = 0;
   wave_sync();
   const int hb = kor ? 32 - __clz((int)kor) : 0;
-  const int dsh = hb > dbits ? hb - dbits : 0;  // sub-bin = (key >> 2) >> dsh
+  const int ksh = 2 + (hb > dbits ? hb - dbits : 0);  // sub-bin = key >> ksh (ksh <= 25)
   // the atomics of all rounds are issued with no branch, so they overlap
   // instead of waiting one by one; a position past the bucket adds 0 to a
   // word of its own (word `lane`: there are at least 64), so lanes past the
   // bucket never pile onto one address
+  // (sub-bin d = key >> ksh counts in half d & 1 of word d >> 1)
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
-    const bool in = lane + 64 * r < ni;
-    const unsigned int d = in ? (kr[r] >> 2) >> dsh : 2u * (unsigned int)lane;
-    const unsigned int sh = 16u * (d & 1u);
-    rk[r] = (atomicAdd(&W.bins[d >> 1], in ? 1u << sh : 0u) >> sh) & 0xFFFFu;
+    const bool in = in_bucket(r);
+    const unsigned int w = in ? kr[r] >> (ksh + 1) : (unsigned int)lane;
+    const unsigned int sh = in ? ((kr[r] >> ksh) & 1u) << 4 : 0u;
+    rk[r] = __builtin_amdgcn_ubfe(atomicAdd(&W.bins[w], in ? 1u << sh : 0u), sh, 16);
   }
   wave_sync();
   // exclusive scan of the sub-bin counters (lane order = sub-bin order)
@@ -1396,9 +1399,10 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
 #pragma unroll
     for (int u = 0; u < G; ++u) {  // the reads of a group first (past the bucket: word `lane`)
       if (r0 + u >= IPL) break;  // a last group shorter than G
-      const bool in = lane + 64 * (r0 + u) < ni;
-      const unsigned int d = in ? (kr[r0 + u] >> 2) >> dsh : 2u * (unsigned int)lane;
-      pos[u] = ((W.bins[d >> 1] >> (16u * (d & 1u))) & 0xFFFFu) + rk[r0 + u];
+      const bool in = in_bucket(r0 + u);
+      const unsigned int w = in ? kr[r0 + u] >> (ksh + 1) : (unsigned int)lane;
+      const unsigned int sh = in ? ((kr[r0 + u] >> ksh) & 1u) << 4 : 0u;
+      pos[u] = __builtin_amdgcn_ubfe(W.bins[w], sh, 16) + rk[r0 + u];
     }
 #pragma unroll
     for (int u = 0; u < G; ++u) {
@@ -1406,7 +1410,7 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
       // read as a record, and no branch around the stores (distinct addresses)
       const int r = r0 + u;
       if (r >= IPL) break;
-      const bool in = lane + 64 * r < ni;
+      const bool in = in_bucket(r);
       const unsigned int q = in ? pos[u] : (unsigned int)(lane + 64 * r);
       W.key[q] = kr[r];
       W.end[q] = er[r];
@@ -1439,7 +1443,7 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
       eo[b + 1] = ex;
     }
   };
-  if (dsh > 0) {
+  if (ksh > 2) {
     // the sub-bins to fix (each named by the lane that placed its second
     // record) are listed in the key array past the bucket's records, so the
     // work spreads evenly over the lanes: ceil(fixes / 64) rounds instead of
@@ -1451,10 +1455,13 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
       unsigned int q = fb;
 #pragma unroll
       for (int r = 0; r < IPL; ++r) {
-        if (fix & (1u << r)) list[q++] = (unsigned short)((kr[r] >> 2) >> dsh);
+        if (fix & (1u << r)) list[q++] = (unsigned short)(kr[r] >> ksh);
       }
       wave_sync();
       for (unsigned int i = (unsigned int)lane; i < nfix; i += 64) fix_sub_bin(list[i]);
+      wave_sync();
+      // the list's words back to the padding key
+      for (unsigned int i = (unsigned int)lane; 2 * i < nfix; i += 64) W.key[ni + i] = 3u;
     } else {
       // no room: each lane walks its own such records
       unsigned int todo = fix;
@@ -1464,7 +1471,7 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
         unsigned int kk = kr[0];
 #pragma unroll
         for (int j = 1; j < IPL; ++j) kk = rr == j ? kr[j] : kk;  // kr[rr] without indexing registers
-        fix_sub_bin((kk >> 2) >> dsh);
+        fix_sub_bin(kk >> ksh);
       }
     }
   }
