@@ -1201,13 +1201,25 @@ __device__ __forceinline__ void lds_load(const unsigned int* src, unsigned int (
   }
 }
 
+template <int N>
+__device__ __forceinline__ void lds_store(unsigned int* dst, const unsigned int (&src)[N]) {
+  if constexpr (N == 4) {
+    *(uint4*)dst = make_uint4(src[0], src[1], src[2], src[3]);
+  } else if constexpr (N == 2) {
+    *(uint2*)dst = make_uint2(src[0], src[1]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) dst[j] = src[j];
+  }
+}
+
 // Flatten of one sorted bucket by one wave: lane owns sorted positions
 // [lane*IPL, lane*IPL + IPL), kept in registers through the three phases
 // (running max of ends, measures and break counts, component writes). A
 // record outside level l takes part as the empty pair (0, 0), which changes
 // no maximum, measure or break, so the phases need no branches; only the
 // component stores are conditional. A position past the bucket holds the key
-// 3 (rank 3, start lo) with end 0: outside every lower level, and in the top
+// 2 (rank 2, start lo) with end 0: outside every lower level, and in the top
 // level the pair (1, 0), which also changes nothing there, because position 0
 // holds a record whose end is at least 1 and comes first in the sweep.
 template <int IPL, int NLEV>
@@ -1216,16 +1228,20 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
                                              const long long (&maxe)[3]) {
   const int lane = threadIdx.x & 63;
   const int q0 = lane * IPL;
-  // positions past the bucket already hold the padding pair (key 3, end 0)
+  // positions past the bucket already hold the padding pair (key 2, end 0)
   unsigned int kv[IPL], ev[IPL];
   lds_load<IPL>(W.key + q0, kv);
   lds_load<IPL>(W.end + q0, ev);
   // start - lo + 1, the same shift as the ends (recomputed at each use: fewer
   // live registers than keeping it)
   auto sv = [&](int j) { return (kv[j] >> 2) + 1u; };
-  // the top level holds every record; the ones below only ranks <= l
-  auto s_in = [&](int j, int l) { return l == NLEV - 1 || (kv[j] & 3u) <= (unsigned int)l ? sv(j) : 0u; };
-  auto e_in = [&](int j, int l) { return l == NLEV - 1 || (kv[j] & 3u) <= (unsigned int)l ? ev[j] : 0u; };
+  // the top level holds every record; the ones below only ranks <= l (ranks
+  // are 0..2, so rank <= 1 is rank != 2: both tests share one mask of the key)
+  auto in_level = [&](int j, int l) {
+    return l == NLEV - 1 || (l == 0 ? (kv[j] & 3u) == 0u : (kv[j] & 3u) != 2u);
+  };
+  auto s_in = [&](int j, int l) { return in_level(j, l) ? sv(j) : 0u; };
+  auto e_in = [&](int j, int l) { return in_level(j, l) ? ev[j] : 0u; };
   // the largest end before each lane: earlier lanes, else the earlier buckets
   unsigned int M[NLEV];
 #pragma unroll
@@ -1247,16 +1263,17 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
   unsigned int nbrk = 0;
 #pragma unroll
   for (int l = 0; l < NLEV; ++l) {
-    unsigned int Mb = M[l], a = 0;
+    unsigned int Mb = M[l], a = 0, c = 0;
 #pragma unroll
     for (int j = 0; j < IPL; ++j) {
       const unsigned int s = s_in(j, l), e = e_in(j, l);
       const unsigned int b = max(s, Mb);
       a += max(e, b) - b;
-      nbrk += s > Mb ? 1u << (10 * l) : 0u;
+      c += s > Mb ? 1u : 0u;
       Mb = max(Mb, e);
     }
     acc[l] = a;
+    nbrk |= c << (10 * l);
   }
   if constexpr (IPL == 8) {
     // opaque to the compiler: it recomputes the per-level selections of each
@@ -1338,13 +1355,13 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
     const unsigned int i = (unsigned int)(r < IPL - 1 ? lane + 64 * r : min(lane + 64 * r, ni - 1));
     x[r] = *(const uint2*)((const char*)rec + 8u * i);  // relative to lo: (start - lo) << 2 | slot, end - lo + 1
   }
-  // a position past the bucket keeps the padding pair of the flatten: key 3
-  // (rank 3, start lo), end 0; it is stored at its own index below
+  // a position past the bucket keeps the padding pair of the flatten: key 2
+  // (rank 2, start lo), end 0; it is stored at its own index below
   unsigned int kor = 0;
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
     const bool in = in_bucket(r);
-    kr[r] = in ? x[r].x : 3u;
+    kr[r] = in ? x[r].x : 2u;
     er[r] = in ? x[r].y : 0u;
     kor |= kr[r];
   }
@@ -1354,11 +1371,15 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   const int nlev = sd.n_levels;
   kor >>= 2;
   kor = (unsigned int)wave_reduce_i32<OpOrI>((int)kor, 0);
-  // sub-bins: about one per record, 128 .. 512; a lane owns bpl of them (two per LDS word)
-  int dbits = 7;
-  while ((1 << dbits) < ni && dbits < 9) ++dbits;
-  const int nbins = 1 << dbits, wpl = nbins >> 7;
-  for (int j = 0; j < wpl; ++j) W.bins[lane * wpl + j] = 0;
+  // sub-bins: about one per record (128 up to 128 records, 256 up to 256,
+  // else 512: the round count fixes the range of ni); a lane owns 2*wpl of
+  // them, two per LDS word
+  constexpr int dbits = IPL <= 2 ? 7 : (IPL <= 4 ? 8 : 9);
+  constexpr int nbins = 1 << dbits, wpl = nbins >> 7;
+  unsigned int bw[wpl];
+#pragma unroll
+  for (int j = 0; j < wpl; ++j) bw[j] = 0;
+  lds_store<wpl>(W.bins + lane * wpl, bw);
   wave_sync();
   const int hb = kor ? 32 - __clz((int)kor) : 0;
   const int ksh = 2 + (hb > dbits ? hb - dbits : 0);  // sub-bin = key >> ksh (ksh <= 25)
@@ -1376,20 +1397,19 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   }
   wave_sync();
   // exclusive scan of the sub-bin counters (lane order = sub-bin order)
+  lds_load<wpl>(W.bins + lane * wpl, bw);
   unsigned int tot = 0;
-  for (int j = 0; j < wpl; ++j) {
-    const unsigned int w = W.bins[lane * wpl + j];
-    tot += (w & 0xFFFFu) + (w >> 16);
-  }
+#pragma unroll
+  for (int j = 0; j < wpl; ++j) tot += (bw[j] & 0xFFFFu) + (bw[j] >> 16);
   unsigned int all;
   unsigned int run = wave_excl_scan_u32<OpSumU>(tot, 0u, all);
-  wave_sync();
+#pragma unroll
   for (int j = 0; j < wpl; ++j) {
-    const unsigned int w = W.bins[lane * wpl + j];
-    const unsigned int a = run, b = run + (w & 0xFFFFu);
-    run = b + (w >> 16);
-    W.bins[lane * wpl + j] = a | (b << 16);
+    const unsigned int a = run, b = run + (bw[j] & 0xFFFFu);
+    run = b + (bw[j] >> 16);
+    bw[j] = a | (b << 16);
   }
+  lds_store<wpl>(W.bins + lane * wpl, bw);
   wave_sync();
   unsigned int fix = 0;  // bit r: the record of round r is the second one of its sub-bin
   constexpr int G = IPL < 4 ? IPL : 4;  // rounds placed together (bounds the live registers)
@@ -1461,7 +1481,7 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
       for (unsigned int i = (unsigned int)lane; i < nfix; i += 64) fix_sub_bin(list[i]);
       wave_sync();
       // the list's words back to the padding key
-      for (unsigned int i = (unsigned int)lane; 2 * i < nfix; i += 64) W.key[ni + i] = 3u;
+      for (unsigned int i = (unsigned int)lane; 2 * i < nfix; i += 64) W.key[ni + i] = 2u;
     } else {
       // no room: each lane walks its own such records
       unsigned int todo = fix;
