@@ -1333,14 +1333,20 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
   }
 }
 
+// Records of the first rounds that the wave path loads before it knows the
+// bucket's count (fixed slots only).
+constexpr int kWavePre = 4;
+
 // Sort of one bucket of 64*(IPL-1) < ni <= 64*IPL records into W, then its
 // flatten: every round but the last is full, so only the last one tests for
-// positions past the bucket. Returns false (nothing written) when the bucket
-// must take the block path.
-template <int IPL>
+// positions past the bucket. With fixed slots (kSlots) the first kWavePre
+// rounds come loaded in `pre`, and the others load without clamping: the
+// bucket's slots hold at least 64*IPL records. Returns false (nothing
+// written) when the bucket must take the block path.
+template <int IPL, bool kSlots>
 __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
-                                            const uint2* rec, const long long (&carry)[3],
-                                            const long long (&maxe)[3]) {
+                                            const uint2* rec, const uint2 (&pre)[kWavePre], long long lo, int nlev,
+                                            const long long (&carry)[3], const long long (&maxe)[3]) {
   const int lane = threadIdx.x & 63;
   // round r holds position lane + 64 r; rounds before the last are inside the bucket
   auto in_bucket = [&](int r) { return r < IPL - 1 || lane + 64 * r < ni; };
@@ -1351,8 +1357,12 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
   uint2 x[IPL];
 #pragma unroll
   for (int r = 0; r < IPL; ++r) {
+    if (kSlots && r < kWavePre) {
+      x[r] = pre[r];
+      continue;
+    }
     // a 32-bit byte offset from the wave-uniform base (ni <= kWaveCap)
-    const unsigned int i = (unsigned int)(r < IPL - 1 ? lane + 64 * r : min(lane + 64 * r, ni - 1));
+    const unsigned int i = (unsigned int)(kSlots || r < IPL - 1 ? lane + 64 * r : min(lane + 64 * r, ni - 1));
     x[r] = *(const uint2*)((const char*)rec + 8u * i);  // relative to lo: (start - lo) << 2 | slot, end - lo + 1
   }
   // a position past the bucket keeps the padding pair of the flatten: key 2
@@ -1365,10 +1375,6 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
     er[r] = in ? x[r].y : 0u;
     kor |= kr[r];
   }
-  // the segment's geometry only now, while the records are in flight
-  const SegDesc sd = p.segs[p.bucket_seg[gb]];
-  const long long lo = bucket_lo(seg_geom(p, p.bucket_seg[gb]), gb - sd.bucket_begin);
-  const int nlev = sd.n_levels;
   kor >>= 2;
   kor = (unsigned int)wave_reduce_i32<OpOrI>((int)kor, 0);
   // sub-bins: about one per record (128 up to 128 records, 256 up to 256,
@@ -1503,7 +1509,9 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
 }
 
 // One wave per bucket, 8 waves per SIMD (64 VGPRs). Buckets that need the
-// block path go to its queue.
+// block path go to its queue. kSlots: fixed slots of at least 128 records
+// (2 slot_cap record places per bucket, whatever its count).
+template <bool kSlots>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_merge_wave(Plan p) {
   __shared__ WaveSmem wsm[4];
   const int lane = threadIdx.x & 63;
@@ -1511,17 +1519,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const long long gb = (long long)blockIdx.x * 4 + wave;
   if (gb >= p.n_buckets) return;
   WaveSmem& W = wsm[wave];
-  const BucketRecs br = bucket_recs(p, gb);
-  const long long n = (long long)br.n8 + br.n16;
+  uint2 pre[kWavePre];
+  if constexpr (kSlots) {
+    // the first rounds load while the bucket's count is still on its way:
+    // its slots start at a known place and hold 2 slot_cap >= 256 records
+    const uint2* base = (const uint2*)p.elems + 2 * gb * (long long)p.slot_cap;
+#pragma unroll
+    for (int r = 0; r < kWavePre; ++r) pre[r] = base[lane + 64 * r];
+  }
+  // every per-bucket word is read here, before any of them is used, so the
+  // reads travel together (only the segment's words wait for its index)
+  BucketRecs br;
+  if constexpr (kSlots) {
+    // fixed slots (slot_cap > 0): the places need no other word
+    const unsigned long long cu = p.cursor[gb];
+    br.n8 = (int)(unsigned int)cu;
+    br.n16 = (int)(cu >> 32);
+    br.overflow = (long long)br.n8 + br.n16 > (long long)p.slot_cap;
+    br.narrow = (const uint2*)p.elems + 2 * gb * (long long)p.slot_cap;
+    br.wide = nullptr;  // never read here: such buckets take the block path
+  } else {
+    br = bucket_recs(p, gb);
+  }
   const long long off = (long long)p.offsets[gb];
   const long long carry[3] = {p.carry[gb * 3], p.carry[gb * 3 + 1], p.carry[gb * 3 + 2]};
+  const unsigned long long mx[3] = {p.maxend[gb * 3], p.maxend[gb * 3 + 1], p.maxend[gb * 3 + 2]};
+  const int seg = p.bucket_seg[gb];
+  const SegDesc sd = p.segs[seg];
+  const Geom g = seg_geom(p, seg);
+  const long long n = (long long)br.n8 + br.n16;
   // largest end per level of the bucket's own records (0: none)
   long long maxe[3];
-  maxe[0] = (long long)p.maxend[gb * 3];
-  maxe[1] = max(maxe[0], (long long)p.maxend[gb * 3 + 1]);
-  maxe[2] = max(maxe[1], (long long)p.maxend[gb * 3 + 2]);
+  maxe[0] = (long long)mx[0];
+  maxe[1] = max(maxe[0], (long long)mx[1]);
+  maxe[2] = max(maxe[1], (long long)mx[2]);
   if (n == 0 || br.overflow) {
     // empty, or a slot overflow that makes the host redo the build
+    // a use of the early loads on this path too, so that the compiler issues
+    // them before the count's test instead of moving them below it
+    if constexpr (kSlots) asm volatile("" ::"v"(pre[0].x), "v"(pre[1].x), "v"(pre[2].x), "v"(pre[3].x));
+    asm volatile("" ::"s"(off), "s"(carry[0]), "s"(carry[1]), "s"(carry[2]), "s"(mx[0]), "s"(mx[1]), "s"(mx[2]),
+                 "s"(sd.bucket_begin), "s"(sd.n_levels), "s"(g.min_s), "s"(g.wx), "s"(g.s0));
     if (lane < 3) {
       p.bsum[gb * 3 + lane] = 0;
       p.ncomp[gb * 3 + lane] = 0;
@@ -1533,16 +1571,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     // only 8 B records (so the segment is narrow: buckets at most 2^30 ns wide)
     const int ni = (int)n;
     const uint2* rec = br.narrow;
+    const long long lo = bucket_lo(g, gb - sd.bucket_begin);
+    const int nlev = sd.n_levels;
     // as many records per lane as the bucket needs: every slot costs the
     // same instructions, filled or not
-    if (ni <= 64) done = wave_bucket<1>(p, W, gb, off, ni, rec, carry, maxe);
-    else if (ni <= 128) done = wave_bucket<2>(p, W, gb, off, ni, rec, carry, maxe);
-    else if (ni <= 192) done = wave_bucket<3>(p, W, gb, off, ni, rec, carry, maxe);
-    else if (ni <= 256) done = wave_bucket<4>(p, W, gb, off, ni, rec, carry, maxe);
-    else if (ni <= 320) done = wave_bucket<5>(p, W, gb, off, ni, rec, carry, maxe);
-    else if (ni <= 384) done = wave_bucket<6>(p, W, gb, off, ni, rec, carry, maxe);
-    else if (ni <= 448) done = wave_bucket<7>(p, W, gb, off, ni, rec, carry, maxe);
-    else done = wave_bucket<8>(p, W, gb, off, ni, rec, carry, maxe);
+    if (ni <= 64) done = wave_bucket<1, kSlots>(p, W, gb, off, ni, rec, pre, lo, nlev, carry, maxe);
+    else if (ni <= 128) done = wave_bucket<2, kSlots>(p, W, gb, off, ni, rec, pre, lo, nlev, carry, maxe);
+    else if (ni <= 192) done = wave_bucket<3, kSlots>(p, W, gb, off, ni, rec, pre, lo, nlev, carry, maxe);
+    else if (ni <= 256) done = wave_bucket<4, kSlots>(p, W, gb, off, ni, rec, pre, lo, nlev, carry, maxe);
+    else if (ni <= 320) done = wave_bucket<5, kSlots>(p, W, gb, off, ni, rec, pre, lo, nlev, carry, maxe);
+    else if (ni <= 384) done = wave_bucket<6, kSlots>(p, W, gb, off, ni, rec, pre, lo, nlev, carry, maxe);
+    else if (ni <= 448) done = wave_bucket<7, kSlots>(p, W, gb, off, ni, rec, pre, lo, nlev, carry, maxe);
+    else done = wave_bucket<8, kSlots>(p, W, gb, off, ni, rec, pre, lo, nlev, carry, maxe);
   }
   if (!done && lane == 0) p.queue[atomicAdd(&p.ticket[2], 1u)] = (unsigned int)gb;
 }
@@ -1816,7 +1856,11 @@ hipError_t launch_carry(const Plan& p, hipStream_t st) {
 
 hipError_t launch_merge_wave(const Plan& p, hipStream_t st) {
   if (p.n_buckets == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_merge_wave, dim3((unsigned)((p.n_buckets + 3) / 4)), dim3(256), 0, st, p);
+  const dim3 grid((unsigned)((p.n_buckets + 3) / 4));
+  if (p.slot_cap >= 128)
+    hipLaunchKernelGGL(k_merge_wave<true>, grid, dim3(256), 0, st, p);
+  else
+    hipLaunchKernelGGL(k_merge_wave<false>, grid, dim3(256), 0, st, p);
   return hipGetLastError();
 }
 
