@@ -1130,15 +1130,22 @@ __device__ void merge_bucket_block(const Plan& p, long long gb, SortSmem<THREADS
   __syncthreads();
 }
 
-// Buckets the wave path handed over (ticket[2] of them in p.queue), taken by
-// persistent workgroups from a shared counter (ticket[1]). Every workgroup
-// exits once the counter passes the queue length.
+// Buckets the wave path handed over (ticket[2] of them in p.queue): one per
+// workgroup by index when they are at most as many as the workgroups, else
+// taken by persistent workgroups from a shared counter (ticket[1]), every
+// workgroup leaving once the counter passes the queue length.
 template <int THREADS, int CAP>
 __global__ __launch_bounds__(THREADS) void k_merge_block(Plan p) {
   __shared__ SortSmem<THREADS, CAP> sm;
   __shared__ int s_seg;
   __shared__ unsigned int s_idx;
   const unsigned int qlen = __hip_atomic_load(&p.ticket[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (qlen <= gridDim.x) {
+    // at most one bucket per workgroup: taken by index, so the workgroups
+    // without one leave at once instead of queueing on the shared counter
+    if (blockIdx.x < qlen) merge_bucket_block<THREADS, CAP>(p, (long long)p.queue[blockIdx.x], sm, &s_seg);
+    return;
+  }
   while (true) {
     if (threadIdx.x == 0) s_idx = atomicAdd(&p.ticket[1], 1u);
     __syncthreads();
