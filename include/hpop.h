@@ -278,10 +278,12 @@ hpop_status hpop_session_stage_times(const hpop_session* s, int32_t cap, const c
                                      float* ms, int32_t* n_out);
 /* Time only one stage while timing is enabled (names as stage_times reports
  * them: "reset", "stats", "hist", "scan", "scatter", "carry", "merge_wave",
- * "merge_block", "base", "region"): one event right before its launches and
- * one right after, instead of one after every stage, so timing perturbs the
- * build less. NULL or "" times every stage again. A stage the build does not
- * run yields no entry. HPOP_E_ARG for an unknown name. Applies to the
+ * "merge_block", "base", "region"; with fixed scatter slots "scan" also
+ * holds the carry pass, and "hist" and "carry" do not run): one event right
+ * before its launches and one right after, instead of one after every stage,
+ * so timing perturbs the build less. NULL or "" times every stage again. A
+ * stage the build does not run yields no entry. HPOP_E_ARG for an unknown
+ * name. Applies to the
  * session's own builds and to batched builds it leads. */
 hpop_status hpop_session_time_stage(hpop_session* s, const char* stage);
 

@@ -17,6 +17,7 @@ hipError_t launch_hist(const Plan& p, hipStream_t st);
 hipError_t launch_scan(const Plan& p, hipStream_t st);
 hipError_t launch_scatter(const Plan& p, hipStream_t st);
 hipError_t launch_carry(const Plan& p, hipStream_t st);
+hipError_t launch_scan_carry(const Plan& p, hipStream_t st);  // fixed slots: scan and carry in one launch
 hipError_t launch_merge_wave(const Plan& p, hipStream_t st);
 hipError_t launch_merge_block(const Plan& p, int cap, hipStream_t st);
 hipError_t launch_base(const Plan& p, hipStream_t st);

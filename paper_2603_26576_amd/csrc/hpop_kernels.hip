@@ -610,9 +610,10 @@ __global__ __launch_bounds__(THREADS) void k_hist(Plan p) {
   }
 }
 
-// exclusive scan of bucket counts -> offsets (decoupled look-back)
+// exclusive scan of bucket counts -> offsets (decoupled look-back), one tile
+// of kScanTile buckets per workgroup in the order of a ticket
 template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
+__device__ __forceinline__ void scan_tile(const Plan& p) {
   constexpr int IPT = kScanTile / THREADS;
   __shared__ unsigned int s_bid;
   __shared__ long long lds[THREADS / 64];
@@ -677,6 +678,11 @@ __global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
   }
   // the thread holding the last bucket also writes the grand total
   if (b0 < p.n_buckets && p.n_buckets <= b0 + IPT) p.offsets[p.n_buckets] = run;
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_scan(Plan p) {
+  scan_tile<THREADS>(p);
 }
 
 template <int THREADS, int IPT, bool kShared>
@@ -991,10 +997,10 @@ __device__ __forceinline__ long long group_incl_scan(long long v, int k) {
   return v;
 }
 
-template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_carry_grouped(Plan p) {
-  const int lane = threadIdx.x & 63, k = lane & (kSegGroup - 1);
-  const long long seg0 = ((long long)blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6)) * kSegGroup;
+// The carry pass of segments [w kSegGroup, (w + 1) kSegGroup) by one wave.
+__device__ __forceinline__ void carry_group(const Plan& p, long long w, int lane) {
+  const int k = lane & (kSegGroup - 1);
+  const long long seg0 = w * kSegGroup;
   if (seg0 >= p.n_segs) return;
   const long long seg = seg0 + (lane / kSegGroup);
   const bool have = seg < p.n_segs;
@@ -1030,6 +1036,30 @@ __global__ __launch_bounds__(THREADS) void k_carry_grouped(Plan p) {
     const int g = __ffsll((long long)big) - 1;
     big &= big - 1;
     carry_segment(p, seg0 + g / kSegGroup, lane);
+  }
+}
+
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_carry_grouped(Plan p) {
+  carry_group(p, (long long)blockIdx.x * (THREADS / 64) + (threadIdx.x >> 6), threadIdx.x & 63);
+}
+
+// Fixed slots: the bucket scan and the carry pass read only what the scatter
+// wrote, so one launch does both: workgroups [0, scan_blocks) scan (tiles in
+// ticket order), the ones after give each wave a segment (or a group of
+// kSegGroup segments).
+template <bool kGrouped>
+__global__ __launch_bounds__(256) void k_scan_carry(Plan p, int scan_blocks) {
+  if ((int)blockIdx.x < scan_blocks) {
+    scan_tile<256>(p);
+    return;
+  }
+  const int lane = threadIdx.x & 63;
+  const long long w = (long long)(blockIdx.x - scan_blocks) * 4 + (threadIdx.x >> 6);
+  if constexpr (kGrouped) {
+    carry_group(p, w, lane);
+  } else {
+    if (w < p.n_segs) carry_segment(p, w, lane);
   }
 }
 
@@ -1858,6 +1888,18 @@ hipError_t launch_carry(const Plan& p, hipStream_t st) {
     hipLaunchKernelGGL(k_carry_grouped<64>, dim3((unsigned)((p.n_segs + kSegGroup - 1) / kSegGroup)), dim3(64), 0, st, p);
   else
     hipLaunchKernelGGL(k_carry<64>, dim3((unsigned)p.n_segs), dim3(64), 0, st, p);  // a wave per segment, spread over the CUs
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_carry(const Plan& p, hipStream_t st) {
+  const long long scan_blocks = (p.n_buckets + kScanTile - 1) / kScanTile;
+  const long long waves = p.seg_group > 1 ? (p.n_segs + kSegGroup - 1) / kSegGroup : p.n_segs;
+  const long long blocks = scan_blocks + (waves + 3) / 4;
+  if (blocks == 0) return hipSuccess;
+  if (p.seg_group > 1)
+    hipLaunchKernelGGL(k_scan_carry<true>, dim3((unsigned)blocks), dim3(256), 0, st, p, (int)scan_blocks);
+  else
+    hipLaunchKernelGGL(k_scan_carry<false>, dim3((unsigned)blocks), dim3(256), 0, st, p, (int)scan_blocks);
   return hipGetLastError();
 }
 

@@ -547,9 +547,9 @@ hpop_status Engine::enqueue(bool build, bool with_timing, std::string& err) {
     HPOP_HIP(pre("stats"), "hipEventRecord");
     HPOP_HIP(launch_stats(p, st), "k_stats");
     HPOP_HIP(mark("stats"), "hipEventRecord");
-    if (p.slot_cap == 0) {  // exact offsets: count, then scan, then scatter
+    if (p.slot_cap == 0) {  // exact offsets: count, then scan, then scatter, then carry
       HPOP_HIP(pre("hist"), "hipEventRecord");
-    HPOP_HIP(launch_hist(p, st), "k_hist");
+      HPOP_HIP(launch_hist(p, st), "k_hist");
       HPOP_HIP(mark("hist"), "hipEventRecord");
       HPOP_HIP(pre("scan"), "hipEventRecord");
       HPOP_HIP(launch_scan(p, st), "k_scan");
@@ -557,17 +557,17 @@ hpop_status Engine::enqueue(bool build, bool with_timing, std::string& err) {
       HPOP_HIP(pre("scatter"), "hipEventRecord");
       HPOP_HIP(launch_scatter(p, st), "k_scatter");
       HPOP_HIP(mark("scatter"), "hipEventRecord");
-    } else {  // fixed slots: scatter in one pass, then offsets of the merged intervals
+      HPOP_HIP(pre("carry"), "hipEventRecord");
+      HPOP_HIP(launch_carry(p, st), "k_carry");
+      HPOP_HIP(mark("carry"), "hipEventRecord");
+    } else {  // fixed slots: scatter in one pass, then offsets of the merged intervals and the carry pass together
       HPOP_HIP(pre("scatter"), "hipEventRecord");
       HPOP_HIP(launch_scatter(p, st), "k_scatter");
       HPOP_HIP(mark("scatter"), "hipEventRecord");
       HPOP_HIP(pre("scan"), "hipEventRecord");
-      HPOP_HIP(launch_scan(p, st), "k_scan");
+      HPOP_HIP(launch_scan_carry(p, st), "k_scan_carry");
       HPOP_HIP(mark("scan"), "hipEventRecord");
     }
-    HPOP_HIP(pre("carry"), "hipEventRecord");
-    HPOP_HIP(launch_carry(p, st), "k_carry");
-    HPOP_HIP(mark("carry"), "hipEventRecord");
     HPOP_HIP(pre("merge_wave"), "hipEventRecord");
     HPOP_HIP(launch_merge_wave(p, st), "k_merge_wave");
     HPOP_HIP(mark("merge_wave"), "hipEventRecord");
