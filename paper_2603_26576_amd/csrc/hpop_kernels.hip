@@ -1377,9 +1377,9 @@ constexpr int kWavePre = 4;
 // Sort of one bucket of 64*(IPL-1) < ni <= 64*IPL records into W, then its
 // flatten: every round but the last is full, so only the last one tests for
 // positions past the bucket. With fixed slots (kSlots) the first kWavePre
-// rounds come loaded in `pre`, and the others load without clamping: the
-// bucket's slots hold at least 64*IPL records. Returns false (nothing
-// written) when the bucket must take the block path.
+// rounds come loaded in `pre` (read before the count was known, so past the
+// end of a bucket of fewer records: places its slots hold). Returns false
+// (nothing written) when the bucket must take the block path.
 template <int IPL, bool kSlots>
 __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long long gb, long long off, int ni,
                                             const uint2* rec, const uint2 (&pre)[kWavePre], long long lo, int nlev,
@@ -1398,8 +1398,9 @@ __device__ __forceinline__ bool wave_bucket(const Plan& p, WaveSmem& W, long lon
       x[r] = pre[r];
       continue;
     }
-    // a 32-bit byte offset from the wave-uniform base (ni <= kWaveCap)
-    const unsigned int i = (unsigned int)(kSlots || r < IPL - 1 ? lane + 64 * r : min(lane + 64 * r, ni - 1));
+    // a 32-bit byte offset from the wave-uniform base (ni <= kWaveCap); the
+    // last round clamps into the bucket, so it reads no lines past its end
+    const unsigned int i = (unsigned int)(r < IPL - 1 ? lane + 64 * r : min(lane + 64 * r, ni - 1));
     x[r] = *(const uint2*)((const char*)rec + 8u * i);  // relative to lo: (start - lo) << 2 | slot, end - lo + 1
   }
   // a position past the bucket keeps the padding pair of the flatten: key 2
