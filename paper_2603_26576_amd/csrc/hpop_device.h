@@ -97,15 +97,6 @@ __device__ __forceinline__ Elem widen(uint2 x, long long lo, const unsigned long
 __device__ __forceinline__ int bucket_of(long long s, const Geom& g) { return bucket_of_start(g, s); }
 
 // index of the last entry with key <= x in a sorted array of n int64 (n >= 1, a[0] <= x)
-__device__ __forceinline__ int upper_index_chunk(const ChunkDesc* c, int n, long long x) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (c[mid].tile_begin <= x) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ int upper_index_seg(const SegDesc* s, int n, long long x) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {

@@ -145,7 +145,7 @@ struct Plan {
   int64_t n_tiles;                   // tiles of single chunks [0, n_own_tiles), then shared tiles
   int64_t n_own_tiles;
   int32_t* tile_chunk;               // [n_tiles] chunk of each streaming tile, the last one of a shared
-                                     // tile (filled by the reset kernel)
+                                     // tile (computed with the plan on the host, uploaded with the chunks)
   int32_t tile_elems;
   int32_t cap;                       // records a bucket may hold for the LDS sort
   int32_t slot_cap;                  // >0: single-pass scatter into fixed slots of this many records per bucket

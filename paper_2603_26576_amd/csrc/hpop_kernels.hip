@@ -44,9 +44,6 @@ __global__ void k_reset(Plan p) {
   if (tid < 4) p.ticket[tid] = 0;
   for (long long i = tid; i < p.n_owners; i += stride) p.owner_err[i] = 0;
   for (long long i = tid; i < 9 * p.n_racc; i += stride) p.racc[i] = 0;
-  // tile -> chunk map of the streaming passes, so that their workgroups start
-  // with one load instead of a dependent binary search
-  for (long long t = tid; t < p.n_tiles; t += stride) p.tile_chunk[t] = upper_index_chunk(p.chunks, p.n_chunks, t);
 }
 
 // ----------------------------------------------------------------------------

@@ -93,6 +93,7 @@ struct Engine {
   Alloc alloc;
   Workspace ws;
   std::vector<ChunkDesc> h_chunks;
+  std::vector<int32_t> h_tile_chunk;  // [n_tiles] chunk of each streaming tile (see Plan::tile_chunk)
   std::vector<SegDesc> h_segs;
   std::vector<RegionDesc> h_regions;
   std::vector<IvlDesc> h_ivls;

@@ -458,6 +458,14 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
     fill += d.count;
   }
   if (pos > 0) ++tiles;
+  // tile -> chunk map of the streaming passes: the last chunk whose first
+  // tile is at or before the tile (for a shared tile, its last chunk), so
+  // their workgroups start with one load instead of a search
+  h_tile_chunk.resize((size_t)tiles);
+  for (long long t = 0, c = 0, nc = (long long)h_chunks.size(); t < tiles; ++t) {
+    while (c + 1 < nc && h_chunks[(size_t)c + 1].tile_begin <= t) ++c;
+    h_tile_chunk[(size_t)t] = (int32_t)c;
+  }
   hpop_status st = ws.prepare(alloc, (long long)h_chunks.size(), tiles, n_segs, buckets, elems,
                               slots > 0 ? buckets * (long long)slots : 0, (long long)h_regions.size(), times,
                               std::max(1, n_owners), (long long)h_ivls.size(), err);
@@ -477,11 +485,15 @@ hpop_status Engine::assemble_plan(const hpop_tuning& tun, const std::vector<long
 
 hpop_status Engine::upload(std::string& err) {
   const size_t bc = h_chunks.size() * sizeof(ChunkDesc), bs = h_segs.size() * sizeof(SegDesc),
-               br = h_regions.size() * sizeof(RegionDesc), bi = h_ivls.size() * sizeof(IvlDesc);
+               br = h_regions.size() * sizeof(RegionDesc), bi = h_ivls.size() * sizeof(IvlDesc),
+               bt = h_tile_chunk.size() * sizeof(int32_t);
   if (ws.fixed) {
     // no page-locked staging (it would be an allocation): copies straight from
     // the host vectors, which stay untouched until the caller synchronises
     if (bc) HPOP_HIP(hipMemcpyAsync(ws.d_chunks, h_chunks.data(), bc, hipMemcpyHostToDevice, alloc.stream), "upload chunks");
+    if (bt)
+      HPOP_HIP(hipMemcpyAsync(ws.plan.tile_chunk, h_tile_chunk.data(), bt, hipMemcpyHostToDevice, alloc.stream),
+               "upload tile map");
     if (bs) HPOP_HIP(hipMemcpyAsync(ws.d_segs, h_segs.data(), bs, hipMemcpyHostToDevice, alloc.stream), "upload segments");
     if (br)
       HPOP_HIP(hipMemcpyAsync(ws.d_regions, h_regions.data(), br, hipMemcpyHostToDevice, alloc.stream),
@@ -496,7 +508,7 @@ hpop_status Engine::upload(std::string& err) {
   // wait for everything else queued on the stream)
   if (ws.desc_done) HPOP_HIP(hipEventSynchronize(ws.desc_done), "hipEventSynchronize");
   else HPOP_HIP(hipEventCreateWithFlags(&ws.desc_done, hipEventDisableTiming), "hipEventCreate");
-  if (!ws.pinned_desc.reserve(bc + bs + br + bi + 64)) {
+  if (!ws.pinned_desc.reserve(bc + bs + br + bi + bt + 64)) {
     err = "pinned host allocation failed";
     return HPOP_E_OOM;
   }
@@ -505,6 +517,7 @@ hpop_status Engine::upload(std::string& err) {
   if (bs) memcpy(h + bc, h_segs.data(), bs);
   if (br) memcpy(h + bc + bs, h_regions.data(), br);
   if (bi) memcpy(h + bc + bs + br, h_ivls.data(), bi);
+  if (bt) memcpy(h + bc + bs + br + bi, h_tile_chunk.data(), bt);
   if (bc) HPOP_HIP(hipMemcpyAsync(ws.d_chunks, h, bc, hipMemcpyHostToDevice, alloc.stream), "upload chunks");
   if (bs) HPOP_HIP(hipMemcpyAsync(ws.d_segs, h + bc, bs, hipMemcpyHostToDevice, alloc.stream), "upload segments");
   if (br)
@@ -512,6 +525,9 @@ hpop_status Engine::upload(std::string& err) {
   if (bi)
     HPOP_HIP(hipMemcpyAsync(ws.d_ivls, h + bc + bs + br, bi, hipMemcpyHostToDevice, alloc.stream),
              "upload region intervals");
+  if (bt)
+    HPOP_HIP(hipMemcpyAsync(ws.plan.tile_chunk, h + bc + bs + br + bi, bt, hipMemcpyHostToDevice, alloc.stream),
+             "upload tile map");
   HPOP_HIP(hipEventRecord(ws.desc_done, alloc.stream), "hipEventRecord");
   return HPOP_OK;
 }

@@ -82,6 +82,19 @@ def test_tunings_agree(tuning):
     check(tr, tuning=tuning)
 
 
+def test_block_path_queue_longer_than_its_grid():
+    """Buckets of about 1024 records all leave the wave path (at most 512
+    records); more of them than the block path has workgroups (1024), so the
+    workgroups take them from the shared counter instead of by index."""
+    tr = tg.make_trace(24, 4, 4, 4, 250000, 60000, w_range=(0.5, 1.5), regions="nested", n_regions=4)
+    sizes = {}
+    for c in tr.chunks:
+        sizes[c.resource] = sizes.get(c.resource, 0) + c.start.size
+    buckets = sum(-(-n // 1024) for n in sizes.values())
+    assert buckets > 1024, buckets
+    check(tr, tuning={"bucket_target": 1024, "bucket_cap": 2048, "tile_elems": 2048})
+
+
 def test_slot_overflow_does_not_outlive_its_tuning():
     """A tuning whose scatter slots overflow falls back to exact offsets
     (k_hist); a later tuning with large enough slots takes the single-pass
