@@ -54,11 +54,19 @@ __global__ void k_reset(Plan p) {
 // n_own_tiles), reusing those kernels' LDS arrays where the layouts agree.
 // ----------------------------------------------------------------------------
 
-// One record in the 8 B bucketed form, stored past the caches: the regrouped
-// records (1 GB for 1.25e8) are read back only by the merge, after the
-// scatter has finished.
+// One 8 B word stored past the caches: a record in the bucketed form (the
+// regrouped records, 1 GB for 1.25e8, are read back only by the merge, after
+// the scatter has finished), or a merged interval of the wave merge.
 __device__ __forceinline__ void put_rec8(uint2* dst, unsigned int key, unsigned int end) {
   __builtin_nontemporal_store((unsigned long long)key | ((unsigned long long)end << 32), (unsigned long long*)dst);
+}
+
+// Two 8 B words loaded past the caches: the start-range pass reads every
+// start once, and the scatter after it reads them again from HBM anyway.
+__device__ __forceinline__ ulonglong2 get_pair_nt(const ulonglong2* src) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  const u64x2 t = __builtin_nontemporal_load((const u64x2*)src);
+  return make_ulonglong2(t.x, t.y);
 }
 
 // The chunks of one shared tile, staged in LDS.
@@ -442,7 +450,7 @@ __global__ __launch_bounds__(THREADS) void k_stats(Plan p) {
     for (int j0 = threadIdx.x; j0 < npairs; j0 += U * THREADS) {
       ulonglong2 x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = j0 + u * THREADS < npairs ? v[j0 + u * THREADS] : make_ulonglong2(ULLONG_MAX, ULLONG_MAX);
+      for (int u = 0; u < U; ++u) x[u] = j0 + u * THREADS < npairs ? get_pair_nt(v + j0 + u * THREADS) : make_ulonglong2(ULLONG_MAX, ULLONG_MAX);
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         take(x[u].x);
@@ -1347,7 +1355,13 @@ __device__ __forceinline__ void wave_flatten(const Plan& p, WaveSmem& W, long lo
     wave_sync();
     const int nl = (int)((totr >> (10 * l)) & 0x3FFu);
     uint2* out = (uint2*)(p.compn[l] + off);
-    for (int i = lane; i < nl; i += 64) out[i] = stage[i];
+    // non-temporal, like the bucketed records: the components (1.2 GB on the
+    // large trace) would otherwise sit dirty in L2 and be written back while
+    // the next kernels stream their own data
+    for (int i = lane; i < nl; i += 64) {
+      const uint2 c = stage[i];
+      put_rec8(out + i, c.x, c.y);
+    }
     wave_sync();
   }
   if (lane < 3) {
