@@ -723,14 +723,14 @@ __global__ __launch_bounds__(THREADS) void k_scatter(Plan p) {
   int bmin = INT_MAX, bmax = -1;
   // the loads of all rounds first, from positions clamped into the tile
   // (base < end): they issue back to back instead of one masked block (and
-  // one wait) per round
+  // one wait) per round; non-temporal, as this pass reads each record once
   long long svs[IPT], evs[IPT];
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
     const long long i = base + threadIdx.x + (long long)k * THREADS;
     const long long ic = i < end ? i : end - 1;
-    svs[k] = cd.s[ic];
-    evs[k] = cd.e[ic];
+    svs[k] = __builtin_nontemporal_load(cd.s + ic);
+    evs[k] = __builtin_nontemporal_load(cd.e + ic);
   }
 #pragma unroll
   for (int k = 0; k < IPT; ++k) {
