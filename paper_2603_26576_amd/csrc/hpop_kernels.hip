@@ -505,7 +505,7 @@ __global__ __launch_bounds__(256) void k_stats_small(Plan p) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) {  // all loads first, from positions clamped into the tile (base < end)
     const long long i = base + lane + 64 * k;
-    v[k] = cd.s[i < end ? i : end - 1];
+    v[k] = __builtin_nontemporal_load(cd.s + (i < end ? i : end - 1));
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
