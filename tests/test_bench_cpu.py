@@ -143,5 +143,14 @@ def test_traffic_of_any_build_kernel_from_the_path_record(tmp_path, monkeypatch)
     assert bench.load_traffic("stats", "w") == 50
     assert bench.load_traffic("region_part", "w") is None
     assert bench.load_path_traffic("w") == 457
+    # a kernel templated on a flag (the merge with fixed slots) and a fused one
+    (prof / "traffic_path_w.txt").write_text(
+        "# test\nworkload: w\nsource_hash: abcd\n"
+        "kernel void hpop::k_merge_wave<true>: 120\n"
+        "kernel void hpop::k_scan_carry<false>: 9\n"
+        "bytes_per_step: 129\n")
+    assert bench.load_traffic("merge_wave", "w") == 120
+    assert bench.load_traffic("scan", "w") is None
+    assert bench.load_traffic("scan_carry", "w") == 9
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "ffff")
     assert bench.load_traffic("scatter", "w") is None
